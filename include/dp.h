@@ -1,0 +1,226 @@
+/*
+ * dp.h -- C ABI of the MI355X (gfx950) library for displacement-based probing
+ * of Tr(P A^{-1}) (Switzer, Stathopoulos, Romero, Laeuchli, Orginos,
+ * "Probing for the trace estimation of a permuted matrix inverse
+ * corresponding to a lattice displacement", arXiv:2106.01275).
+ *
+ * The problem (Sec. 3): A is a nearest-neighbour operator on a 4-D torus,
+ * P the permutation that shifts sites by p along dimension 0, and the wanted
+ * quantity is Tr(P A^{-1}) = sum_x A^{-1}[x + p e0, x].  It is estimated with
+ * Hutchinson's estimator (Sec. 2, eq. (1)) on probing vectors built from a
+ * greedy colouring of the displaced distance-k neighbourhoods (Sec. 3,
+ * eqs. (5)-(6); Sec. 2.1-2.2, eqs. (3)-(4)); every probe costs one linear
+ * solve A x = z, followed by the displaced contraction z^H P x.
+ *
+ * Conventions shared by every call
+ *   - Lattice extents dims[4]; site index idx = ((x0*D1 + x1)*D2 + x2)*D3 + x3
+ *     (dimension 0, the displacement dimension, varies slowest).
+ *   - (P v)(x) = v(x + p e0).
+ *   - Vectors at the ABI are complex128 (re, im interleaved), layout
+ *     [rhs][site][colour], colour = 0..nc-1, nc in {1, 3}.
+ *   - Links are complex128 [4][N][nc][nc]; U_mu(x)[a][b] connects x to x+mu.
+ *   - The operator (free field for nc = 1 and links == NULL, otherwise
+ *     gauge covariant):
+ *       (A v)(x) = (m2 + 8) v(x) - sum_mu [U_mu(x) v(x+mu) + U_mu(x-mu)^H v(x-mu)].
+ *   - The caller owns every buffer passed in; the library never frees one.
+ *     "device" buffers live on the context's HIP device; "host" buffers in
+ *     host memory.
+ *   - Device work is ordered on the stream argument.  Calls that return host
+ *     results synchronise that stream before returning.
+ *   - No exception crosses the ABI.  Every call returns a dp_status;
+ *     dp_last_error() gives a message for the last failure.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef DP_H
+#define DP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dp_status;
+enum {
+    DP_OK = 0,
+    DP_EINVAL = 1,        /* bad argument: dims <= 0, nc not 1 or 3, p < 0, ... */
+    DP_ENOMEM = 2,        /* device or host allocation failed */
+    DP_EHIP = 3,          /* a HIP runtime call failed */
+    DP_ENOCONV = 4,       /* max_iter reached; outputs are written, stats say which */
+    DP_EBREAKDOWN = 5,    /* CG breakdown: p^H A p <= 0 or not finite */
+    DP_EUNSUPPORTED = 6   /* valid request this build does not support */
+};
+
+/* visitation order of the greedy colouring (Sec. 3.1) */
+enum { DP_ORDER_NATURAL = 0, DP_ORDER_REDBLACK = 1, DP_ORDER_BEST = 2 };
+
+/* noise of the probing vectors (Sec. 2): real Rademacher, complex
+ * Z2 x Z2 stored unnormalised as (+-1) + i(+-1) (quadratic results carry a
+ * factor 1/2), and Z4 = {1, i, -1, -i} */
+enum { DP_NOISE_REAL_Z2 = 0, DP_NOISE_Z2_COMPLEX = 1, DP_NOISE_Z4 = 2 };
+
+/* storage precision of the inner solver's vectors and links */
+enum { DP_PREC_F64 = 0, DP_PREC_F32 = 1, DP_PREC_BF16 = 2 };
+
+typedef struct dp_ctx dp_ctx;
+
+/* Creates a context bound to HIP device hip_device.  The context owns all
+ * scratch memory (workspaces, reduction buffers, tuning results). */
+dp_status dp_create(dp_ctx **ctx, int32_t hip_device);
+void dp_destroy(dp_ctx *ctx);
+/* Message of the last failure of a call on ctx (ctx == NULL: of the last
+ * context-free call in this thread).  Never NULL. */
+const char *dp_last_error(const dp_ctx *ctx);
+
+/*
+ * Greedy displaced distance-k colouring (Sec. 3.1; DisColoring and
+ * CreateStencil): each site, in the visitation order, gets the smallest
+ * colour not used by an already coloured site of
+ *     N(x, p, k) = {y != x : |y - (x + p e0)|_1 <= k or |y - (x - p e0)|_1 <= k}
+ * (distances on the torus).  Colours are 0-based and dense.
+ *   dims      host int32[4], each >= 1.
+ *   p         displacement along dimension 0, >= 0.
+ *   ks        host int32[nlevels], distances, strictly increasing, >= 0.
+ *   nlevels   1: a flat distance-ks[0] colouring.  > 1: nested levels
+ *             (hierarchical probing, Sec. 2.3): level l refines every colour
+ *             class of level l-1 by a distance-ks[l] colouring of that class;
+ *             the children of parent colour c are numbered after those of
+ *             colours 0..c-1.
+ *   order     DP_ORDER_*; BEST takes the order with fewer colours at the last
+ *             level, ties to NATURAL (Sec. 4.1).
+ *   colors    host int32[nlevels][N], written.
+ *   ncolors   host int32[nlevels], written.
+ *   order_used host int32, written with the order taken (may be NULL).
+ * Host only; deterministic. */
+dp_status dp_build_coloring(const int32_t dims[4], int32_t p, const int32_t *ks,
+                            int32_t nlevels, int32_t order, int32_t *colors,
+                            int32_t *ncolors, int32_t *order_used);
+
+/* Which probing vectors to use (Sec. 2.1-2.2, eqs. (3)-(4)). */
+typedef struct {
+    int32_t dims[4];
+    int32_t nc;                 /* colours per site: 1 or 3 */
+    const int32_t *colors_dev;  /* device int32[N], one colouring level */
+    int32_t ncolors;            /* number of colours m in colors_dev */
+    uint64_t seed;              /* noise seed */
+    int32_t sample0;            /* first noise sample s */
+    int32_t nsamples;           /* number of noise samples */
+    int32_t noise;              /* DP_NOISE_* */
+    int32_t dilute;             /* 1: one probe per colour component (n_dil = nc) */
+} dp_probe_spec;
+
+/*
+ * Writes probing vectors j in [rhs0, rhs0 + nrhs) of the enumeration
+ *     j = ((s - sample0) * ncolors + c) * n_dil + a,   n_dil = dilute ? nc : 1:
+ *     v_j(x, b) = z0(s, x, b) * [colour(x) == c] * (dilute ? [b == a] : 1),
+ * with z0 from the counter-based SplitMix64 hash
+ *     h = mix(mix(seed) ^ ((s*N + idx)*nc + b))
+ * (REAL_Z2: -1 if bit 63 else +1; Z2_COMPLEX: re from bit 63, im from bit 62;
+ *  Z4: h >> 62 -> {1, i, -1, -i}).
+ *   out  device complex128 [nrhs][N][nc], caller-owned.
+ * Values are exact (+-1, +-i, +-1+-i). */
+dp_status dp_make_probes(dp_ctx *ctx, const dp_probe_spec *ps, int64_t rhs0, int64_t nrhs,
+                         void *out, hipStream_t stream);
+
+/* One operator instance. */
+typedef struct {
+    int32_t dims[4];
+    int32_t nc;          /* 1 or 3 */
+    double m2;           /* mass term */
+    const void *links;   /* device complex128 [4][N][nc][nc]; NULL means U = 1 */
+} dp_operator;
+
+typedef struct {
+    double tol;             /* stop when |b - A x| / |b| <= tol (FP64 true residual
+                               for mixed precision; recursive residual for F64) */
+    int32_t max_iter;       /* iteration limit per right-hand side (0: 100000) */
+    int32_t inner;          /* DP_PREC_*: storage of the inner CG vectors and links;
+                               F32 and BF16 accumulate in FP32 and are refined by
+                               FP64 reliable updates */
+    int32_t rhs_block;      /* right-hand sides solved together (W); 0 = autotune */
+    double reliable_delta;  /* mixed precision: replace the residual by the FP64
+                               true residual once it dropped by this factor (0: 0.1) */
+    int32_t use_graph;      /* 1: replay the iteration loop from a captured hipGraph */
+    int32_t profile;        /* 1: time the stencil kernel launches with HIP events */
+} dp_solve_opts;
+
+typedef struct {
+    int64_t nrhs;            /* right-hand sides solved */
+    int64_t rhs_iters;       /* sum over right-hand sides of CG iterations to convergence */
+    int32_t max_iters;       /* largest iteration count of one right-hand side */
+    int32_t nconverged;      /* right-hand sides that met tol */
+    int32_t nbreakdown;      /* right-hand sides that broke down */
+    int32_t reliable_updates;/* FP64 reliable updates performed (all blocks) */
+    double max_true_resid;   /* max over right-hand sides of |b - A x| / |b| (FP64) */
+    int32_t rhs_block;       /* W used */
+    int32_t stencil_launches;/* profile = 1: stencil kernel launches timed */
+    double stencil_ms;       /* profile = 1: summed duration of those launches */
+    double seconds;          /* wall time of the call */
+} dp_solve_stats;
+
+/*
+ * Solves A_i x = b for every right-hand side of every instance with CG
+ * (Hestenes-Stiefel, x0 = 0).
+ *   ninst  number of instances (>= 1).
+ *   ops    host dp_operator[ninst].
+ *   b      host array [ninst] of device complex128 [nrhs[i]][N_i][nc_i].
+ *   x      host array [ninst] of device complex128 [nrhs[i]][N_i][nc_i], written.
+ *   nrhs   host int64[ninst].
+ *   st     host dp_solve_stats[ninst], written (may be NULL).
+ * Returns DP_ENOCONV / DP_EBREAKDOWN (outputs still written) when some
+ * right-hand side failed. */
+dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops,
+                         const void *const *b, void *const *x, const int64_t *nrhs,
+                         const dp_solve_opts *o, dp_solve_stats *st, hipStream_t stream);
+
+typedef struct {
+    double tr[2];            /* the estimate T = (1/s) sum_s T_s (complex) */
+    double stderr_;          /* sqrt(var_s(T_s) / s), unbiased variance; NaN if s < 2 */
+    double *per_sample;      /* host double[nsamples][2] (T_s), written if non-NULL */
+    double *per_rhs;         /* host double[nrhs][2] (t_j, unnormalised), written if non-NULL */
+    dp_solve_stats solve;    /* statistics of the solves */
+} dp_trace_result;
+
+/*
+ * Probed estimate of Tr(P A^{-1}) (eqs. (1), (3), (4); Sec. 3):
+ *     t_j = sum_x sum_b conj(v_j(x,b)) x_j(x + p e0, b),  x_j = A^{-1} v_j,
+ *     T_s = norm * sum_{j in sample s} t_j  (norm = 1/2 for Z2_COMPLEX, else 1),
+ *     T = mean over samples.
+ * Probes are generated on the device from the spec; solutions are contracted
+ * as soon as their block converges and are never all held at once.
+ *   ninst, ops, p, ps, out: arrays [ninst] (host); instance i uses ops[i],
+ *   displacement p[i] >= 0 and probes ps[i] (ps[i].dims/nc must equal ops[i]'s).
+ *   out[i].per_sample / per_rhs are optional caller-owned host buffers. */
+dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops,
+                            const int32_t *p, const dp_probe_spec *ps, const dp_solve_opts *o,
+                            dp_trace_result *out, hipStream_t stream);
+
+/*
+ * Adjoint gradient of the probed estimate T (same probes as dp_trace_estimate).
+ * With x_j = A^{-1} v_j and lambda_j = A^{-1} P^T v_j ((P^T v)(y) = v(y - p e0)),
+ * recomputed here (no Krylov history is kept):
+ *     dT/dm2              = -(norm/s) sum_j lambda_j^H x_j
+ *     dT/dU_mu(x)[a][b]    =  (norm/s) sum_j conj(lambda_j(x)_a) x_j(x+mu)_b
+ *     dT/dconj(U)_mu(x)[a][b] = (norm/s) sum_j x_j(x)_a conj(lambda_j(x+mu)_b)
+ * (Wirtinger derivatives with U and conj(U) independent).
+ *   dT_dm2    host double[2], written.
+ *   dT_dU, dT_dUbar  device complex128 [4][N][nc][nc], caller-owned, overwritten
+ *             (either may be NULL). */
+dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *op, int32_t p, const dp_probe_spec *ps,
+                        const dp_solve_opts *o, dp_trace_result *out, double dT_dm2[2],
+                        void *dT_dU, void *dT_dUbar, hipStream_t stream);
+
+/*
+ * y = A v for nrhs vectors with the stencil kernel of the given storage
+ * precision (DP_PREC_*): inputs are rounded to that precision, the result is
+ * returned in complex128.  v, y: device complex128 [nrhs][N][nc].
+ * The operator of the problem statement, exposed for verification. */
+dp_status dp_apply(dp_ctx *ctx, const dp_operator *op, int32_t prec, const void *v, void *y,
+                   int64_t nrhs, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DP_H */

@@ -1,0 +1,358 @@
+"""Python binding of libdprobe, the gfx950 library for displacement-based
+probing of Tr(P A^{-1}) (arXiv:2106.01275).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels (or, for the colouring, its host code).  PyTorch provides device
+memory and streams.  The names follow the C ABI in include/dp.h:
+
+    build_coloring, make_probes, solve_batch, trace_estimate, trace_grad,
+    apply (the operator, for verification)
+
+plus ProbedTrace, a torch.autograd.Function over trace_estimate/trace_grad.
+The library must be built (python -m paper_2106_01275_amd.build); importing
+this module never falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdprobe.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, EUNSUPPORTED = range(7)
+ORDER = {"natural": 0, "redblack": 1, "best": 2}
+NOISE = {"real_z2": 0, "z2_complex": 1, "z4": 2}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+NOISE_NORM = {"real_z2": 1.0, "z2_complex": 0.5, "z4": 1.0}
+
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOCONV", 5: "EBREAKDOWN", 6: "EUNSUPPORTED"}
+
+
+class DPError(RuntimeError):
+    def __init__(self, status, msg, result=None):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.result = result
+
+
+class ProbeSpec(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("nc", ctypes.c_int32), ("colors_dev", ctypes.c_void_p),
+                ("ncolors", ctypes.c_int32), ("seed", ctypes.c_uint64), ("sample0", ctypes.c_int32),
+                ("nsamples", ctypes.c_int32), ("noise", ctypes.c_int32), ("dilute", ctypes.c_int32)]
+
+
+class Operator(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("nc", ctypes.c_int32), ("m2", ctypes.c_double),
+                ("links", ctypes.c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("rhs_block", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
+                ("use_graph", ctypes.c_int32), ("profile", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("nrhs", ctypes.c_int64), ("rhs_iters", ctypes.c_int64), ("max_iters", ctypes.c_int32),
+                ("nconverged", ctypes.c_int32), ("nbreakdown", ctypes.c_int32),
+                ("reliable_updates", ctypes.c_int32), ("max_true_resid", ctypes.c_double),
+                ("rhs_block", ctypes.c_int32), ("stencil_launches", ctypes.c_int32),
+                ("stencil_ms", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TraceResult(ctypes.Structure):
+    _fields_ = [("tr", ctypes.c_double * 2), ("stderr_", ctypes.c_double),
+                ("per_sample", ctypes.c_void_p), ("per_rhs", ctypes.c_void_p), ("solve", SolveStats)]
+
+
+EXPORTS = ["dp_create", "dp_destroy", "dp_last_error", "dp_build_coloring", "dp_make_probes",
+           "dp_solve_batch", "dp_trace_estimate", "dp_trace_grad", "dp_apply"]
+
+_lib = None
+
+
+def lib():
+    """Loads libdprobe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2106_01275_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.dp_create.argtypes = [ctypes.POINTER(vp), i32]
+        L.dp_destroy.argtypes = [vp]
+        L.dp_destroy.restype = None
+        L.dp_last_error.argtypes = [vp]
+        L.dp_last_error.restype = ctypes.c_char_p
+        L.dp_build_coloring.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp]
+        L.dp_make_probes.argtypes = [vp, ctypes.POINTER(ProbeSpec), i64, i64, vp, vp]
+        L.dp_solve_batch.argtypes = [vp, i32, ctypes.POINTER(Operator), vp, vp, vp,
+                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
+        L.dp_trace_estimate.argtypes = [vp, i32, ctypes.POINTER(Operator), vp, ctypes.POINTER(ProbeSpec),
+                                        ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp]
+        L.dp_trace_grad.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(ProbeSpec),
+                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp, vp, vp, vp]
+        L.dp_apply.argtypes = [vp, ctypes.POINTER(Operator), i32, vp, vp, i64, vp]
+        for name in ("dp_create", "dp_build_coloring", "dp_make_probes", "dp_solve_batch",
+                     "dp_trace_estimate", "dp_trace_grad", "dp_apply"):
+            getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _dims4(dims):
+    d = [1, 1, 1, 1]
+    d[: len(dims)] = [int(v) for v in dims]
+    return d
+
+
+def build_coloring(dims, p, ks, order="natural"):
+    """Greedy displaced colouring (host).  ks: one distance or an increasing
+    list (nested levels).  Returns (colors int32[nlev, N] or [N], ncolors,
+    order used)."""
+    flat = np.isscalar(ks)
+    ks = _i32([ks] if flat else list(ks))
+    d = _i32(_dims4(dims))
+    N = int(np.prod(d))
+    col = np.zeros((len(ks), N), dtype=np.int32)
+    nc = np.zeros(len(ks), dtype=np.int32)
+    used = np.zeros(1, dtype=np.int32)
+    st = lib().dp_build_coloring(d.ctypes.data, int(p), ks.ctypes.data, len(ks), ORDER[order],
+                                 col.ctypes.data, nc.ctypes.data, used.ctypes.data)
+    if st != OK:
+        raise DPError(st, lib().dp_last_error(None).decode())
+    used_name = {v: k for k, v in ORDER.items()}[int(used[0])]
+    if flat:
+        return col[0], int(nc[0]), used_name
+    return col, nc, used_name
+
+
+class Context:
+    """A library context bound to one HIP device (the torch device index)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        h = ctypes.c_void_p()
+        st = lib().dp_create(ctypes.byref(h), device)
+        if st != OK:
+            raise DPError(st, lib().dp_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().dp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _err(self, st, result=None):
+        raise DPError(st, lib().dp_last_error(self.h).decode(), result)
+
+    def _cdev(self, t, dtype):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+            raise TypeError(f"expected a contiguous {dtype} tensor on the GPU")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def operator(self, dims, nc, m2, links=None):
+        """links: complex128 cuda tensor [4, N, nc, nc] or None (U = 1)."""
+        op = Operator()
+        op.dims[:] = _dims4(dims)
+        op.nc = nc
+        op.m2 = float(m2)
+        op.links = None if links is None else self._cdev(links, self.torch.complex128).value
+        op._keep = links
+        return op
+
+    def probe_spec(self, dims, nc, colors_dev, ncolors, seed, sample0, nsamples, noise, dilute):
+        ps = ProbeSpec()
+        ps.dims[:] = _dims4(dims)
+        ps.nc = nc
+        ps.colors_dev = self._cdev(colors_dev, self.torch.int32).value
+        ps.ncolors = int(ncolors)
+        ps.seed = int(seed)
+        ps.sample0 = int(sample0)
+        ps.nsamples = int(nsamples)
+        ps.noise = NOISE[noise] if isinstance(noise, str) else int(noise)
+        ps.dilute = int(bool(dilute))
+        ps._keep = colors_dev
+        return ps
+
+    @staticmethod
+    def opts(tol=1e-10, max_iter=0, inner="f64", rhs_block=0, reliable_delta=0.1, use_graph=0, profile=0):
+        o = SolveOpts()
+        o.tol = tol
+        o.max_iter = max_iter
+        o.inner = PREC[inner] if isinstance(inner, str) else int(inner)
+        o.rhs_block = rhs_block
+        o.reliable_delta = reliable_delta
+        o.use_graph = use_graph
+        o.profile = profile
+        return o
+
+    # ------------------------------------------------------------ entry points
+    def make_probes(self, ps, rhs0, nrhs, out=None):
+        torch = self.torch
+        N = int(np.prod(list(ps.dims)))
+        if out is None:
+            out = torch.empty((nrhs, N, ps.nc), dtype=torch.complex128, device=f"cuda:{self.device}")
+        st = lib().dp_make_probes(self.h, ctypes.byref(ps), rhs0, nrhs, self._cdev(out, torch.complex128),
+                                  self._stream())
+        if st != OK:
+            self._err(st)
+        return out
+
+    def solve_batch(self, ops, bs, opts, xs=None, check=True):
+        """ops: list of Operator; bs: list of complex128 [nrhs, N, nc] tensors."""
+        torch = self.torch
+        n = len(ops)
+        if xs is None:
+            xs = [torch.empty_like(b) for b in bs]
+        arr_ops = (Operator * n)(*ops)
+        pb = (ctypes.c_void_p * n)(*[self._cdev(b, torch.complex128).value for b in bs])
+        px = (ctypes.c_void_p * n)(*[self._cdev(x, torch.complex128).value for x in xs])
+        nr = (ctypes.c_int64 * n)(*[b.shape[0] for b in bs])
+        stats = (SolveStats * n)()
+        st = lib().dp_solve_batch(self.h, n, arr_ops, pb, px, nr, ctypes.byref(opts), stats, self._stream())
+        res = (xs, [s.asdict() for s in stats])
+        if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
+            self._err(st, res)
+        return res
+
+    def trace_estimate(self, ops, ps, p, opts, check=True):
+        """ops, ps, p: lists (one entry per instance).  Returns a list of dicts."""
+        n = len(ops)
+        arr_ops = (Operator * n)(*ops)
+        arr_ps = (ProbeSpec * n)(*ps)
+        arr_p = (ctypes.c_int32 * n)(*[int(v) for v in p])
+        res = (TraceResult * n)()
+        bufs = []
+        for i in range(n):
+            ndil = ps[i].nc if ps[i].dilute else 1
+            nrhs = ps[i].nsamples * ps[i].ncolors * ndil
+            per_s = np.zeros(2 * ps[i].nsamples)
+            per_r = np.zeros(2 * nrhs)
+            bufs.append((per_s, per_r))
+            res[i].per_sample = per_s.ctypes.data
+            res[i].per_rhs = per_r.ctypes.data
+        st = lib().dp_trace_estimate(self.h, n, arr_ops, arr_p, arr_ps, ctypes.byref(opts), res,
+                                     self._stream())
+        out = []
+        for i in range(n):
+            out.append({"T": complex(res[i].tr[0], res[i].tr[1]), "stderr": res[i].stderr_,
+                        "per_sample": bufs[i][0].view(np.complex128).copy(),
+                        "tj": bufs[i][1].view(np.complex128).copy(), "solve": res[i].solve.asdict()})
+        if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
+            self._err(st, out)
+        return out
+
+    def trace_grad(self, op, ps, p, opts, want_links=True, check=True):
+        """Returns (T, dT/dm2, dT/dU, dT/dUbar, stats); the link gradients are
+        complex128 cuda tensors [4, N, nc, nc] (None if want_links is False)."""
+        torch = self.torch
+        N = int(np.prod(list(op.dims)))
+        res = TraceResult()
+        ndil = ps.nc if ps.dilute else 1
+        per_r = np.zeros(2 * ps.nsamples * ps.ncolors * ndil)
+        res.per_rhs = per_r.ctypes.data
+        g = (ctypes.c_double * 2)()
+        dU = dUb = None
+        if want_links:
+            dU = torch.empty((4, N, op.nc, op.nc), dtype=torch.complex128, device=f"cuda:{self.device}")
+            dUb = torch.empty_like(dU)
+        st = lib().dp_trace_grad(self.h, ctypes.byref(op), int(p), ctypes.byref(ps), ctypes.byref(opts),
+                                 ctypes.byref(res), g,
+                                 None if dU is None else self._cdev(dU, torch.complex128),
+                                 None if dUb is None else self._cdev(dUb, torch.complex128), self._stream())
+        out = (complex(res.tr[0], res.tr[1]), complex(g[0], g[1]), dU, dUb, res.solve.asdict())
+        if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
+            self._err(st, out)
+        return out
+
+    def apply(self, op, v, prec="f64"):
+        torch = self.torch
+        y = torch.empty_like(v)
+        st = lib().dp_apply(self.h, ctypes.byref(op), PREC[prec], self._cdev(v, torch.complex128),
+                            self._cdev(y, torch.complex128), v.shape[0], self._stream())
+        if st != OK:
+            self._err(st)
+        return y
+
+
+_ctx_cache = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _ctx_cache:
+        _ctx_cache[device] = Context(device)
+    return _ctx_cache[device]
+
+
+def _make_probed_trace():
+    import torch
+
+    class ProbedTrace(torch.autograd.Function):
+        """T = probed estimate of Tr(P A^{-1}) as a differentiable function of
+        m2 (real scalar tensor) and the links U (complex128 [4, N, nc, nc]).
+
+        Forward runs trace_estimate; backward recomputes the solves with
+        trace_grad (no Krylov history is stored) and maps the Wirtinger pair
+        (dT/dU, dT/dconj(U)) to PyTorch's convention for a complex output:
+        grad_U = conj(g) dT/dconj(U) + g conj(dT/dU),
+        grad_m2 = Re(conj(g) dT/dm2)."""
+
+        @staticmethod
+        def forward(ctx_, m2, U, dims, nc, p, colors_dev, ncolors, seed, sample0, nsamples, noise, dilute,
+                    opts):
+            c = context(U.device.index or 0)
+            op = c.operator(dims, nc, float(m2), U.detach().contiguous())
+            ps = c.probe_spec(dims, nc, colors_dev, ncolors, seed, sample0, nsamples, noise, dilute)
+            r = c.trace_estimate([op], [ps], [p], opts)[0]
+            ctx_.save_for_backward(m2, U)
+            ctx_.args = (dims, nc, p, colors_dev, ncolors, seed, sample0, nsamples, noise, dilute, opts)
+            return torch.tensor(r["T"], dtype=torch.complex128, device=U.device)
+
+        @staticmethod
+        def backward(ctx_, g):
+            m2, U = ctx_.saved_tensors
+            dims, nc, p, colors_dev, ncolors, seed, sample0, nsamples, noise, dilute, opts = ctx_.args
+            c = context(U.device.index or 0)
+            op = c.operator(dims, nc, float(m2), U.detach().contiguous())
+            ps = c.probe_spec(dims, nc, colors_dev, ncolors, seed, sample0, nsamples, noise, dilute)
+            _, dm2, dU, dUb, _ = c.trace_grad(op, ps, p, opts)
+            gc = torch.conj(g)
+            grad_U = gc * dUb + g * torch.conj(dU)
+            grad_m2 = (gc * dm2).real.to(m2.dtype).reshape(m2.shape)
+            return (grad_m2, grad_U) + (None,) * 11
+
+    return ProbedTrace
+
+
+def probed_trace(m2, U, dims, nc, p, colors_dev, ncolors, seed=0, sample0=0, nsamples=1, noise="z2_complex",
+                 dilute=True, opts=None):
+    """Differentiable probed estimate of Tr(P A^{-1}) (see ProbedTrace)."""
+    if opts is None:
+        opts = Context.opts(tol=1e-10)
+    return _make_probed_trace().apply(m2, U, tuple(dims), nc, p, colors_dev, ncolors, seed, sample0, nsamples,
+                                      noise, dilute, opts)

@@ -1,0 +1,413 @@
+// extern "C" entry points of the dp library (declared in include/dp.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "context.h"
+
+using namespace dp;
+
+namespace {
+
+thread_local std::string g_err;
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+dp_status check_ctx(dp_ctx *ctx) {
+    if (!ctx) {
+        g_err = "null context";
+        return DP_EINVAL;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        ctx->err = "hipSetDevice failed";
+        return DP_EHIP;
+    }
+    return DP_OK;
+}
+
+dp_status solve_cfg(dp_ctx *ctx, const dp_solve_opts *o, SolveCfg &c) {
+    if (!o) {
+        ctx->err = "null solve options";
+        return DP_EINVAL;
+    }
+    c.tol = o->tol;
+    c.max_iter = o->max_iter > 0 ? o->max_iter : 100000;
+    c.inner = o->inner;
+    c.delta = o->reliable_delta > 0 ? o->reliable_delta : 0.1;
+    c.profile = o->profile;
+    if (!(c.tol > 0) || !(c.delta < 1)) {
+        ctx->err = "tol must be > 0 and reliable_delta < 1";
+        return DP_EINVAL;
+    }
+    if (c.inner != kF64 && c.inner != kF32 && c.inner != kBF16) {
+        ctx->err = "unknown inner precision";
+        return DP_EINVAL;
+    }
+    return DP_OK;
+}
+
+dp_status check_spec(dp_ctx *ctx, const dp_probe_spec &ps, const dp_operator *op) {
+    for (int d = 0; d < 4; ++d)
+        if (ps.dims[d] < 1 || (op && ps.dims[d] != op->dims[d])) {
+            ctx->err = "probe spec dims invalid or not equal to the operator's";
+            return DP_EINVAL;
+        }
+    if ((ps.nc != 1 && ps.nc != 3) || (op && ps.nc != op->nc)) {
+        ctx->err = "probe spec nc invalid or not equal to the operator's";
+        return DP_EINVAL;
+    }
+    if (!ps.colors_dev || ps.ncolors < 1 || ps.nsamples < 1 || ps.sample0 < 0 ||
+        ps.noise < DP_NOISE_REAL_Z2 || ps.noise > DP_NOISE_Z4) {
+        ctx->err = "probe spec: colors_dev, ncolors >= 1, nsamples >= 1, sample0 >= 0, noise kind";
+        return DP_EINVAL;
+    }
+    return DP_OK;
+}
+
+ProbeGen make_gen(const dp_probe_spec &ps, long long rhs0, long long nvalid, int shift) {
+    ProbeGen g{};
+    g.colors = ps.colors_dev;
+    g.seed = ps.seed;
+    g.ncolors = ps.ncolors;
+    g.sample0 = ps.sample0;
+    g.noise = ps.noise;
+    g.dilute = ps.dilute ? 1 : 0;
+    g.rhs0 = rhs0;
+    g.nvalid = nvalid;
+    g.shift = shift;
+    return g;
+}
+
+double noise_norm(int kind) { return kind == DP_NOISE_Z2_COMPLEX ? 0.5 : 1.0; }
+
+dp_status final_status(const dp_solve_stats &st) {
+    if (st.nbreakdown > 0) return DP_EBREAKDOWN;
+    if (st.nconverged < st.nrhs) return DP_ENOCONV;
+    return DP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dp_status dp_create(dp_ctx **out, int32_t hip_device) {
+    if (!out) {
+        g_err = "dp_create: null output";
+        return DP_EINVAL;
+    }
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+        g_err = "dp_create: no such HIP device";
+        return DP_EHIP;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        g_err = "dp_create: hipSetDevice failed";
+        return DP_EHIP;
+    }
+    dp_ctx *ctx = new (std::nothrow) dp_ctx();
+    if (!ctx) {
+        g_err = "dp_create: out of host memory";
+        return DP_ENOMEM;
+    }
+    ctx->device = hip_device;
+    if (hipHostMalloc((void **)&ctx->ctrl_host, 64, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->state_host, 8 * kMaxW * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        g_err = "dp_create: pinned allocation failed";
+        dp_destroy(ctx);
+        return DP_ENOMEM;
+    }
+    *out = ctx;
+    return DP_OK;
+}
+
+void dp_destroy(dp_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (int s = 0; s < kNumSlots; ++s)
+        if (ctx->slot[s]) (void)hipFree(ctx->slot[s]);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto &pr : ctx->ev_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    if (ctx->ctrl_host) (void)hipHostFree(ctx->ctrl_host);
+    if (ctx->state_host) (void)hipHostFree(ctx->state_host);
+    delete ctx;
+}
+
+const char *dp_last_error(const dp_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+dp_status dp_build_coloring(const int32_t dims[4], int32_t p, const int32_t *ks, int32_t nlevels, int32_t order,
+                            int32_t *colors, int32_t *ncolors, int32_t *order_used) {
+    if (!dims) {
+        g_err = "build_coloring: null dims";
+        return DP_EINVAL;
+    }
+    try {
+        return build_coloring(dims, p, ks, nlevels, order, colors, ncolors, order_used, g_err);
+    } catch (const std::bad_alloc &) {
+        g_err = "build_coloring: out of host memory";
+        return DP_ENOMEM;
+    } catch (...) {
+        g_err = "build_coloring: internal error";
+        return DP_EINVAL;
+    }
+}
+
+dp_status dp_make_probes(dp_ctx *ctx, const dp_probe_spec *ps, int64_t rhs0, int64_t nrhs, void *out,
+                         hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!ps || (!out && nrhs > 0) || rhs0 < 0 || nrhs < 0) {
+        ctx->err = "make_probes: bad arguments";
+        return DP_EINVAL;
+    }
+    DP_TRY(check_spec(ctx, *ps, nullptr));
+    if (nrhs == 0) return DP_OK;
+    Lat lat{};
+    long long N = 1;
+    for (int d = 0; d < 4; ++d) {
+        lat.D[d] = ps->dims[d];
+        N *= ps->dims[d];
+    }
+    lat.N = (int)N;
+    launch_make_probes_abi(lat, ps->nc, make_gen(*ps, rhs0, nrhs, 0), nrhs, (double *)out, stream);
+    DP_HIP(hipGetLastError());
+    return DP_OK;
+}
+
+dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, const void *const *b, void *const *x,
+                         const int64_t *nrhs, const dp_solve_opts *o, dp_solve_stats *st, hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (ninst < 1 || !ops || !b || !x || !nrhs) {
+        ctx->err = "solve_batch: bad arguments";
+        return DP_EINVAL;
+    }
+    SolveCfg cfg;
+    DP_TRY(solve_cfg(ctx, o, cfg));
+    dp_status worst = DP_OK;
+    for (int i = 0; i < ninst; ++i) {
+        const double t0 = now_s();
+        dp_solve_stats s{};
+        if (nrhs[i] < 0 || (nrhs[i] > 0 && (!b[i] || !x[i]))) {
+            ctx->err = "solve_batch: bad right-hand sides";
+            return DP_EINVAL;
+        }
+        OpPrep op;
+        DP_TRY(prepare_operator(ctx, ops[i], cfg.inner, op, stream));
+        int W = 1;
+        DP_TRY(choose_width(ctx, op, cfg, nrhs[i], o->rhs_block, stream, W));
+        s.rhs_block = W;
+        Launch L;
+        Red rd;
+        CgState cs;
+        DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
+        for (long long r0 = 0; r0 < nrhs[i]; r0 += W) {
+            const long long nv = std::min<long long>(W, nrhs[i] - r0);
+            BlockStats bs;
+            bs.nvalid = (int)nv;
+            InitAbi init{&L, cfg.inner, (const double *)b[i], r0, nv, &rd, &cs, ctx};
+            double *x64 = (double *)ctx->at(kSlotX64);
+            DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s));
+            launch_to_abi(L, x64, (double *)x[i], r0, nv);
+            DP_HIP(hipGetLastError());
+        }
+        DP_HIP(hipStreamSynchronize(stream));
+        s.seconds = now_s() - t0;
+        if (st) st[i] = s;
+        dp_status fs = final_status(s);
+        if (fs != DP_OK && worst == DP_OK) worst = fs;
+    }
+    if (worst == DP_ENOCONV) ctx->err = "solve_batch: some right-hand sides did not converge";
+    if (worst == DP_EBREAKDOWN) ctx->err = "solve_batch: CG breakdown (operator not positive definite?)";
+    return worst;
+}
+
+static dp_status trace_one(dp_ctx *ctx, const dp_operator &opd, int32_t p, const dp_probe_spec &ps,
+                           const dp_solve_opts *o, const SolveCfg &cfg, dp_trace_result &out, hipStream_t stream) {
+    const double t0 = now_s();
+    DP_TRY(check_spec(ctx, ps, &opd));
+    if (p < 0) {
+        ctx->err = "trace_estimate: p must be >= 0";
+        return DP_EINVAL;
+    }
+    OpPrep op;
+    DP_TRY(prepare_operator(ctx, opd, cfg.inner, op, stream));
+    const int ndil = ps.dilute ? ps.nc : 1;
+    const long long nrhs = (long long)ps.nsamples * ps.ncolors * ndil;
+    int W = 1;
+    DP_TRY(choose_width(ctx, op, cfg, nrhs, o->rhs_block, stream, W));
+    Launch L;
+    Red rd;
+    CgState cs;
+    DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
+    dp_solve_stats s{};
+    s.rhs_block = W;
+    std::vector<double> tj(2 * nrhs, 0.0);
+    for (long long r0 = 0; r0 < nrhs; r0 += W) {
+        const long long nv = std::min<long long>(W, nrhs - r0);
+        BlockStats bs;
+        bs.nvalid = (int)nv;
+        InitProbe init{&L, cfg.inner, make_gen(ps, r0, nv, 0), &rd, &cs, ctx};
+        double *x64 = (double *)ctx->at(kSlotX64);
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s));
+        launch_displaced_dot(L, make_gen(ps, r0, nv, 0), p, x64, rd, cs);
+        DP_HIP(hipGetLastError());
+        DP_HIP(hipMemcpyAsync(tj.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    DP_HIP(hipStreamSynchronize(stream));
+    const double norm = noise_norm(ps.noise);
+    const long long per = (long long)ps.ncolors * ndil;
+    std::vector<double> Ts(2 * ps.nsamples, 0.0);
+    for (long long j = 0; j < nrhs; ++j) {
+        Ts[2 * (j / per)] += norm * tj[2 * j];
+        Ts[2 * (j / per) + 1] += norm * tj[2 * j + 1];
+    }
+    double Tr = 0, Ti = 0;
+    for (int s_ = 0; s_ < ps.nsamples; ++s_) {
+        Tr += Ts[2 * s_];
+        Ti += Ts[2 * s_ + 1];
+    }
+    Tr /= ps.nsamples;
+    Ti /= ps.nsamples;
+    double var = 0;
+    for (int s_ = 0; s_ < ps.nsamples; ++s_) {
+        const double dr = Ts[2 * s_] - Tr, di = Ts[2 * s_ + 1] - Ti;
+        var += dr * dr + di * di;
+    }
+    out.tr[0] = Tr;
+    out.tr[1] = Ti;
+    out.stderr_ = ps.nsamples > 1 ? std::sqrt(var / (ps.nsamples - 1) / ps.nsamples) : NAN;
+    if (out.per_sample) std::memcpy(out.per_sample, Ts.data(), Ts.size() * sizeof(double));
+    if (out.per_rhs) std::memcpy(out.per_rhs, tj.data(), tj.size() * sizeof(double));
+    s.seconds = now_s() - t0;
+    out.solve = s;
+    return final_status(s);
+}
+
+dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, const int32_t *p,
+                            const dp_probe_spec *ps, const dp_solve_opts *o, dp_trace_result *out,
+                            hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (ninst < 1 || !ops || !p || !ps || !out) {
+        ctx->err = "trace_estimate: bad arguments";
+        return DP_EINVAL;
+    }
+    SolveCfg cfg;
+    DP_TRY(solve_cfg(ctx, o, cfg));
+    dp_status worst = DP_OK;
+    for (int i = 0; i < ninst; ++i) {
+        dp_status s = trace_one(ctx, ops[i], p[i], ps[i], o, cfg, out[i], stream);
+        if (s == DP_EINVAL || s == DP_ENOMEM || s == DP_EHIP || s == DP_EUNSUPPORTED) return s;
+        if (s != DP_OK && worst == DP_OK) worst = s;
+    }
+    if (worst == DP_ENOCONV) ctx->err = "trace_estimate: some right-hand sides did not converge";
+    if (worst == DP_EBREAKDOWN) ctx->err = "trace_estimate: CG breakdown";
+    return worst;
+}
+
+dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *opd, int32_t p, const dp_probe_spec *ps,
+                        const dp_solve_opts *o, dp_trace_result *out, double dT_dm2[2], void *dT_dU,
+                        void *dT_dUbar, hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!opd || !ps || !out || !dT_dm2 || p < 0) {
+        ctx->err = "trace_grad: bad arguments";
+        return DP_EINVAL;
+    }
+    const double t0 = now_s();
+    SolveCfg cfg;
+    DP_TRY(solve_cfg(ctx, o, cfg));
+    DP_TRY(check_spec(ctx, *ps, opd));
+    OpPrep op;
+    DP_TRY(prepare_operator(ctx, *opd, cfg.inner, op, stream));
+    const int ndil = ps->dilute ? ps->nc : 1;
+    const long long nrhs = (long long)ps->nsamples * ps->ncolors * ndil;
+    int W = 1;
+    DP_TRY(choose_width(ctx, op, cfg, nrhs, o->rhs_block, stream, W));
+    Launch L;
+    Red rd;
+    CgState cs;
+    DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
+    DP_TRY(ctx->ensure(kSlotX64b, (size_t)op.lat.N * op.nc * W * 16));
+    double *xsol = (double *)ctx->at(kSlotX64b);
+    double *lsol = (double *)ctx->at(kSlotX64);
+    const double norm = noise_norm(ps->noise) / ps->nsamples;
+    dp_solve_stats s{};
+    s.rhs_block = W;
+    std::vector<double> tj(2 * nrhs, 0.0), lx(2 * nrhs, 0.0);
+    for (long long r0 = 0; r0 < nrhs; r0 += W) {
+        const long long nv = std::min<long long>(W, nrhs - r0);
+        BlockStats bs1, bs2;
+        bs1.nvalid = bs2.nvalid = (int)nv;
+        InitProbe ix{&L, cfg.inner, make_gen(*ps, r0, nv, 0), &rd, &cs, ctx};
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, xsol, ix, bs1, &s));
+        launch_displaced_dot(L, make_gen(*ps, r0, nv, 0), p, xsol, rd, cs);
+        DP_HIP(hipMemcpyAsync(tj.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        InitProbe il{&L, cfg.inner, make_gen(*ps, r0, nv, p), &rd, &cs, ctx};
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, lsol, il, bs2, &s));
+        launch_dot(L, lsol, xsol, rd, cs);
+        DP_HIP(hipMemcpyAsync(lx.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        if (dT_dU || dT_dUbar)
+            launch_force(L, xsol, lsol, op.nbr, norm, r0 == 0, (double *)dT_dU, (double *)dT_dUbar);
+        DP_HIP(hipGetLastError());
+    }
+    DP_HIP(hipStreamSynchronize(stream));
+    double Tr = 0, Ti = 0, gr = 0, gi = 0;
+    for (long long j = 0; j < nrhs; ++j) {
+        Tr += tj[2 * j];
+        Ti += tj[2 * j + 1];
+        gr += lx[2 * j];
+        gi += lx[2 * j + 1];
+    }
+    out->tr[0] = norm * Tr;
+    out->tr[1] = norm * Ti;
+    out->stderr_ = NAN;
+    if (out->per_rhs) std::memcpy(out->per_rhs, tj.data(), tj.size() * sizeof(double));
+    dT_dm2[0] = -norm * gr;
+    dT_dm2[1] = -norm * gi;
+    s.seconds = now_s() - t0;
+    out->solve = s;
+    dp_status fs = final_status(s);
+    if (fs == DP_ENOCONV) ctx->err = "trace_grad: some right-hand sides did not converge";
+    if (fs == DP_EBREAKDOWN) ctx->err = "trace_grad: CG breakdown";
+    return fs;
+}
+
+dp_status dp_apply(dp_ctx *ctx, const dp_operator *opd, int32_t prec, const void *v, void *y, int64_t nrhs,
+                   hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!opd || nrhs < 0 || (nrhs > 0 && (!v || !y))) {
+        ctx->err = "apply: bad arguments";
+        return DP_EINVAL;
+    }
+    if (nrhs == 0) return DP_OK;
+    OpPrep op;
+    DP_TRY(prepare_operator(ctx, *opd, prec, op, stream));
+    SolveCfg cfg;
+    cfg.inner = prec;
+    int W = 1;
+    while (W < nrhs && W < 64) W *= 2;
+    Launch L;
+    Red rd;
+    CgState cs;
+    DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
+    for (long long r0 = 0; r0 < nrhs; r0 += W) {
+        const long long nv = std::min<long long>(W, nrhs - r0);
+        launch_abi_to_internal(L, prec, (const double *)v, r0, nv, ctx->at(kSlotP));
+        launch_stencil(L, prec, op.links, op.m2 + 8.0, ctx->at(kSlotP), ctx->at(kSlotQ), op.ULo, op.nbr, false, rd,
+                       cs);
+        launch_internal_to_abi_prec(L, prec, ctx->at(kSlotQ), (double *)y, r0, nv);
+        DP_HIP(hipGetLastError());
+    }
+    DP_HIP(hipStreamSynchronize(stream));
+    return DP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// The dp_ctx object and the solver driver shared by the ABI entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "dp_internal.h"
+
+#define DP_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);         \
+            return DP_EHIP;                                                       \
+        }                                                                         \
+    } while (0)
+
+#define DP_TRY(expr)                  \
+    do {                              \
+        dp_status s_ = (expr);        \
+        if (s_ != DP_OK) return s_;   \
+    } while (0)
+
+namespace dp {
+
+enum Slot {
+    kSlotNbr, kSlotU64, kSlotULo, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotXLo,
+    kSlotPart1, kSlotState, kSlotColors, kSlotVec, kNumSlots
+};
+
+// A prepared operator: neighbour table and links in the internal layout.
+struct OpPrep {
+    Lat lat{};
+    int nc = 1;
+    double m2 = 0;
+    bool links = false;
+    const void *U64 = nullptr;  // FP64 links [N][4][nc][nc]
+    const void *ULo = nullptr;  // inner-precision links
+    const int *nbr = nullptr;
+    int inner = kF64;
+};
+
+struct BlockStats {
+    long long iters_sum = 0;
+    int iters_max = 0, nconv = 0, nbreak = 0, nvalid = 0, ru = 0;
+    double max_rel = 0;
+};
+
+}  // namespace dp
+
+struct dp_ctx {
+    int device = 0;
+    std::string err;
+    void *slot[dp::kNumSlots] = {};
+    size_t slot_bytes[dp::kNumSlots] = {};
+    int *ctrl_host = nullptr;        // pinned [8]
+    double *state_host = nullptr;    // pinned staging of per-lane results
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    std::map<std::string, int> tuned_w;
+    int check_every = 8;
+
+    dp_status ensure(int s, size_t bytes, bool zero = false);
+    void *at(int s) const { return slot[s]; }
+};
+
+namespace dp {
+
+struct SolveCfg {
+    double tol = 1e-10;
+    int max_iter = 100000;
+    int inner = kF64;
+    double delta = 0.1;
+    int profile = 0;
+    int W = 0, logW = 0;
+};
+
+dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep &out, hipStream_t s);
+dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launch &L, Red &rd, CgState &cs,
+                      const SolveCfg &cfg);
+// Runs CG on the block initialised by `init` (a callable launching the init
+// kernel).  On return the FP64 solution is in x64_dst (internal layout).
+template <typename Init>
+dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
+                      const CgState &cs, double *x64_dst, Init init, BlockStats &bs, dp_solve_stats *acc);
+dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
+                       hipStream_t s, int &W);
+dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
+
+// Initialisers of a block: probes generated on the device, or ABI vectors.
+struct InitProbe {
+    const Launch *L;
+    int prec;
+    ProbeGen g;
+    const Red *rd;
+    const CgState *cs;
+    dp_ctx *ctx;
+    void operator()(void *xlo, double *x64) const {
+        launch_init_probe(*L, prec, g, (double *)ctx->at(kSlotB64), ctx->at(kSlotR), ctx->at(kSlotP), xlo, x64,
+                          prec != kF64, *rd, *cs);
+    }
+};
+
+struct InitAbi {
+    const Launch *L;
+    int prec;
+    const double *babi;
+    long long rhs0, nvalid;
+    const Red *rd;
+    const CgState *cs;
+    dp_ctx *ctx;
+    void operator()(void *xlo, double *x64) const {
+        launch_init_abi(*L, prec, babi, rhs0, nvalid, (double *)ctx->at(kSlotB64), ctx->at(kSlotR),
+                        ctx->at(kSlotP), xlo, x64, prec != kF64, *rd, *cs);
+    }
+};
+
+
+}  // namespace dp

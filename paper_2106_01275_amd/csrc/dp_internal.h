@@ -1,0 +1,101 @@
+// Internal declarations of the dp library (not part of the ABI).
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dp.h"
+
+namespace dp {
+
+// ---------------------------------------------------------------- colouring
+std::vector<std::array<int32_t, 4>> displaced_stencil(int32_t p, int32_t k);
+dp_status build_coloring(const int32_t dims[4], int32_t p, const int32_t *ks, int32_t nlevels,
+                         int32_t order, int32_t *colors, int32_t *ncolors, int32_t *order_used,
+                         std::string &err);
+
+// ---------------------------------------------------------------- device side
+constexpr int kBlock = 256;      // threads per workgroup of every lattice kernel
+constexpr int kMaxW = 256;       // largest right-hand-side block width
+
+// Per-workgroup partial sums of a reduction, [W][nblk][NV].
+struct Red {
+    double *part1;
+    int nblk;
+};
+
+// Per-right-hand-side CG state of one block of W right-hand sides (device).
+struct CgState {
+    double *rr, *rr_prev, *rr_ref, *bb, *alpha, *beta, *true_rr;
+    double *tj;          // [W][2] contraction results / dot products
+    int *active, *iters, *flags;
+    int *ctrl;           // [0] active, [1] candidates, [2] need reliable update, [3] breakdowns
+    double tol2, delta2;
+    int exact;           // 1: FP64 inner solve (no reliable updates)
+};
+
+enum { kFlagBreakdown = 1, kFlagConverged = 2 };
+
+// Geometry of a lattice on the device.
+struct Lat {
+    int D[4];
+    int N;
+};
+
+// How probing vectors are enumerated (device copy of dp_probe_spec fields).
+struct ProbeGen {
+    const int *colors;
+    unsigned long long seed;
+    int ncolors, sample0, noise, dilute;
+    long long rhs0;      // enumeration index of lane 0
+    long long nvalid;    // lanes [0, nvalid) carry probes
+    int shift;           // 0: v_j; p: (P^T v_j)(y) = v_j(y - p e0)
+};
+
+enum Prec { kF64 = 0, kF32 = 1, kBF16 = 2 };
+
+// Launch helpers (kernels.hip).  All vectors in the internal layout
+// [site][nc][W] complex of the given precision; W a power of two.
+struct Launch {
+    Lat lat;
+    int nc, W, logW;
+    int nblk, ntiles;   // grid size and number of site tiles
+    hipStream_t stream;
+};
+
+int grid_blocks(int ntiles);
+void build_neighbours(const Lat &lat, int *nbr, hipStream_t s);
+void convert_links(int prec, const Lat &lat, int nc, const void *abi_links, void *out, hipStream_t s);
+
+void launch_init_probe(const Launch &L, int prec, const ProbeGen &g, double *b64, void *r, void *p,
+                       void *xlo, double *x64, int mixed, const Red &rd, const CgState &cs);
+void launch_init_abi(const Launch &L, int prec, const double *babi, long long rhs0, long long nvalid,
+                     double *b64, void *r, void *p, void *xlo, double *x64, int mixed, const Red &rd,
+                     const CgState &cs);
+void launch_stencil(const Launch &L, int prec, bool links, double diag, const void *p, void *q,
+                    const void *U, const int *nbr, bool cg, const Red &rd, const CgState &cs);
+void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r, const void *q,
+                    const Red &rd, const CgState &cs);
+void launch_update2(const Launch &L, int prec, const void *r, void *p, const CgState &cs);
+void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
+void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
+                       const double *x64, const void *U64, const int *nbr, void *r, int ru_mode,
+                       const Red &rd, const CgState &cs);
+void launch_displaced_dot(const Launch &L, const ProbeGen &g, int p, const double *x64, const Red &rd,
+                          const CgState &cs);
+void launch_dot(const Launch &L, const double *a64, const double *b64, const Red &rd,
+                const CgState &cs);
+void launch_force(const Launch &L, const double *x64, const double *l64, const int *nbr, double scale,
+                  int first, double *dU, double *dUbar);
+void launch_ctrl(const CgState &cs, int W, hipStream_t s);
+void launch_to_abi(const Launch &L, const double *x64, double *xabi, long long rhs0, long long nvalid);
+void launch_abi_to_internal(const Launch &L, int prec, const double *vabi, long long rhs0,
+                            long long nvalid, void *out);
+void launch_internal_to_abi_prec(const Launch &L, int prec, const void *in, double *yabi,
+                                 long long rhs0, long long nvalid);
+void launch_make_probes_abi(const Lat &lat, int nc, const ProbeGen &g, long long nrhs, double *out,
+                            hipStream_t s);
+
+}  // namespace dp

@@ -1,0 +1,934 @@
+// gfx950 kernels of the displaced-probing hot path (arXiv:2106.01275):
+// probe generation (eqs. (3)-(4)), the gauge-covariant stencil A p, the CG
+// vector updates with FP64 reductions, FP64 reliable updates, the displaced
+// contraction z^H P x (Sec. 3) and the adjoint force.
+//
+// Data layout.  A block of W right-hand sides (W a power of two) is stored
+// site-major with the right-hand side innermost: element (site, colour a,
+// lane j) at ((site * nc + a) * W + j), complex.  A workgroup of 256 threads
+// covers a tile of 256 / W sites; thread (site, j) = (tid / W, tid % W).  The
+// W lanes of a site read consecutive addresses (coalesced) and share the
+// site's links, which are staged once per tile in LDS (W >= 16) and reused by
+// all W right-hand sides.  Consecutive tiles form one contiguous chunk per
+// workgroup, and chunks are assigned so that each XCD owns a contiguous part
+// of the lattice (its L2 then serves the x1/x2/x3 neighbour re-reads).
+//
+// Reductions (dot products per right-hand side) accumulate in FP64: every
+// workgroup writes its partial sums, and a finishing kernel with one
+// workgroup per right-hand side adds them in a fixed order (deterministic)
+// and runs the CG scalar epilogue (alpha, beta, convergence flags) on the
+// device, so the host only reads a control word now and then.  The kernel
+// boundary makes the partials visible; no device-scope fence is used (on
+// this multi-XCD part such a fence writes back the whole L2 of the XCD).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "dp_internal.h"
+
+namespace dp {
+
+// ============================================================ storage types
+
+struct bf16x2 {
+    uint32_t v;  // low half: real part, high half: imaginary part
+};
+
+__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return u >> 16;
+}
+
+template <typename S>
+struct St;
+
+template <>
+struct St<double2> {
+    using R = double;
+    __device__ static __forceinline__ void ld(const double2 *__restrict__ a, size_t i, R &re, R &im) {
+        double2 v = a[i];
+        re = v.x;
+        im = v.y;
+    }
+    __device__ static __forceinline__ void st(double2 *__restrict__ a, size_t i, R re, R im) {
+        a[i] = make_double2(re, im);
+    }
+};
+
+template <>
+struct St<float2> {
+    using R = float;
+    __device__ static __forceinline__ void ld(const float2 *__restrict__ a, size_t i, R &re, R &im) {
+        float2 v = a[i];
+        re = v.x;
+        im = v.y;
+    }
+    __device__ static __forceinline__ void st(float2 *__restrict__ a, size_t i, R re, R im) {
+        a[i] = make_float2(re, im);
+    }
+};
+
+template <>
+struct St<bf16x2> {
+    using R = float;
+    __device__ static __forceinline__ void ld(const bf16x2 *__restrict__ a, size_t i, R &re, R &im) {
+        uint32_t v = a[i].v;
+        re = __uint_as_float(v << 16);
+        im = __uint_as_float(v & 0xffff0000u);
+    }
+    __device__ static __forceinline__ void st(bf16x2 *__restrict__ a, size_t i, R re, R im) {
+        bf16x2 o;
+        o.v = f32_to_bf16(re) | (f32_to_bf16(im) << 16);
+        a[i] = o;
+    }
+};
+
+// ============================================================ helpers
+
+__device__ __forceinline__ int logical_block() {
+    // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
+    // that XCD x runs the contiguous range of logical blocks [x*n/8, (x+1)*n/8).
+    const int n = gridDim.x, b = blockIdx.x;
+    if (n % 8) return b;
+    return (b % 8) * (n / 8) + b / 8;
+}
+
+__device__ __forceinline__ void tile_range(int ntiles, int &t0, int &t1) {
+    const int lb = logical_block(), n = gridDim.x;
+    t0 = (int)(((long long)lb * ntiles) / n);
+    t1 = (int)(((long long)(lb + 1) * ntiles) / n);
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    // SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014)
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// noise value z0(s, site, b) as (re, im) in {-1, 0, 1}
+__device__ __forceinline__ void noise(unsigned long long seedmix, long long s, int N, int site, int nc,
+                                      int b, int kind, double &re, double &im) {
+    const unsigned long long ctr =
+        ((unsigned long long)s * (unsigned long long)N + (unsigned long long)site) * (unsigned long long)nc +
+        (unsigned long long)b;
+    const unsigned long long h = mix64(seedmix ^ ctr);
+    const int top = (int)(h >> 63), nxt = (int)((h >> 62) & 1ull);
+    if (kind == DP_NOISE_REAL_Z2) {
+        re = top ? -1.0 : 1.0;
+        im = 0.0;
+    } else if (kind == DP_NOISE_Z2_COMPLEX) {
+        re = top ? -1.0 : 1.0;
+        im = nxt ? -1.0 : 1.0;
+    } else {
+        const int q = (int)(h >> 62);
+        re = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+        im = q == 1 ? 1.0 : (q == 3 ? -1.0 : 0.0);
+    }
+}
+
+__device__ __forceinline__ int shift0(const Lat &L, int site, int p) {
+    // site + p e0 on the torus (p may be negative)
+    const int stride0 = L.D[1] * L.D[2] * L.D[3];
+    const int x0 = site / stride0;
+    int y0 = (x0 + p) % L.D[0];
+    if (y0 < 0) y0 += L.D[0];
+    return site + (y0 - x0) * stride0;
+}
+
+// probe value of lane-enumeration index J at (site, colour b); 0 outside
+__device__ __forceinline__ void probe_value(const ProbeGen &g, unsigned long long seedmix, const Lat &L,
+                                            int nc, long long J, int site, int b, double &re, double &im) {
+    re = 0.0;
+    im = 0.0;
+    const int ndil = g.dilute ? nc : 1;
+    const long long s = g.sample0 + J / ((long long)g.ncolors * ndil);
+    const int c = (int)((J / ndil) % g.ncolors);
+    const int a = (int)(J % ndil);
+    const int x = g.shift ? shift0(L, site, -g.shift) : site;
+    if (g.colors[x] != c) return;
+    if (g.dilute && b != a) return;
+    noise(seedmix, s, L.N, x, nc, b, g.noise, re, im);
+}
+
+// ------------------------------------------------------------ reductions
+
+// Writes this workgroup's sums of NV values per lane to
+// part[(lane * nblk + blockIdx.x) * NV + v] (all threads call it once).
+template <int NV>
+__device__ void block_partials(const double (&val)[NV], int W, int logW, const Red &rd, double *sm) {
+    const int tid = threadIdx.x;
+    const int spl = kBlock >> logW;  // threads per lane
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sm[v * kBlock + tid] = val[v];
+    __syncthreads();
+    if (tid < W) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+            for (int k = 0; k < spl; ++k) s += sm[v * kBlock + k * W + tid];
+            rd.part1[((size_t)tid * rd.nblk + blockIdx.x) * NV + v] = s;
+        }
+    }
+}
+
+enum Epi { kEpiInit, kEpiAlpha, kEpiBeta, kEpiRU, kEpiStats, kEpiTj };
+
+// One workgroup per lane: total of the lane's partials (fixed order), then
+// the scalar epilogue of that lane.
+template <int NV, int EPI>
+__global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
+    __shared__ double sm[NV * kBlock];
+    const int lane = blockIdx.x, tid = threadIdx.x;
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    for (int b = tid; b < rd.nblk; b += kBlock) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[v] += rd.part1[((size_t)lane * rd.nblk + b) * NV + v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sm[v * kBlock + tid] = s[v];
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sm[v * kBlock + tid] += sm[v * kBlock + tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const int j = lane;
+    const double t = sm[0];
+    if (EPI == kEpiInit) {
+        cs.bb[j] = t;
+        cs.rr[j] = t;
+        cs.rr_prev[j] = t;
+        cs.rr_ref[j] = t;
+        cs.true_rr[j] = t;
+        cs.alpha[j] = 0.0;
+        cs.beta[j] = 0.0;
+        cs.iters[j] = 0;
+        cs.active[j] = t > 0.0;
+        cs.flags[j] = t > 0.0 ? 0 : kFlagConverged;
+    } else if (EPI == kEpiAlpha) {
+        if (cs.active[j]) {
+            if (!(t > 0.0) || !isfinite(t)) {
+                cs.flags[j] |= kFlagBreakdown;
+                cs.active[j] = 0;
+                cs.alpha[j] = 0.0;
+            } else {
+                cs.alpha[j] = cs.rr[j] / t;
+            }
+        } else {
+            cs.alpha[j] = 0.0;
+        }
+    } else if (EPI == kEpiBeta) {
+        if (cs.active[j]) {
+            cs.iters[j] += 1;
+            cs.rr_prev[j] = cs.rr[j];
+            cs.beta[j] = t / cs.rr[j];
+            cs.rr[j] = t;
+            if (cs.exact && t <= cs.tol2 * cs.bb[j]) {
+                cs.active[j] = 0;
+                cs.flags[j] |= kFlagConverged;
+            }
+        } else {
+            cs.beta[j] = 0.0;
+        }
+    } else if (EPI == kEpiRU || EPI == kEpiStats) {
+        cs.true_rr[j] = t;
+        if (EPI == kEpiRU && cs.active[j]) {
+            cs.beta[j] = t / cs.rr_prev[j];
+            cs.rr[j] = t;
+            cs.rr_ref[j] = t;
+            if (t <= cs.tol2 * cs.bb[j]) {
+                cs.active[j] = 0;
+                cs.flags[j] |= kFlagConverged;
+            }
+        }
+    } else {
+        cs.tj[2 * j] = sm[0];
+        cs.tj[2 * j + 1] = NV > 1 ? sm[kBlock] : 0.0;
+    }
+}
+
+// Control word for the host: [0] active lanes, [1] active lanes whose
+// recursive residual meets tol, [2] active lanes due a reliable update,
+// [3] lanes that broke down.
+__global__ void k_ctrl(CgState cs, int W) {
+    if (threadIdx.x != 0) return;
+    int na = 0, nk = 0, nru = 0, nb = 0;
+    for (int k = 0; k < W; ++k) {
+        nb += (cs.flags[k] & kFlagBreakdown) ? 1 : 0;
+        if (!cs.active[k]) continue;
+        ++na;
+        if (cs.rr[k] <= cs.tol2 * cs.bb[k]) ++nk;
+        if (cs.rr[k] < cs.delta2 * cs.rr_ref[k]) ++nru;
+    }
+    cs.ctrl[0] = na;
+    cs.ctrl[1] = nk;
+    cs.ctrl[2] = nru;
+    cs.ctrl[3] = nb;
+}
+
+// ============================================================ kernels
+
+// neighbour table nbr[site][8]: x+mu (mu = 0..3), then x-mu
+__global__ void k_neighbours(Lat L, int *__restrict__ nbr) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= L.N) return;
+    int x[4], r = site;
+    for (int d = 3; d >= 0; --d) {
+        x[d] = r % L.D[d];
+        r /= L.D[d];
+    }
+    int stride[4] = {L.D[1] * L.D[2] * L.D[3], L.D[2] * L.D[3], L.D[3], 1};
+    for (int mu = 0; mu < 4; ++mu) {
+        const int up = x[mu] + 1 == L.D[mu] ? -(L.D[mu] - 1) : 1;
+        const int dn = x[mu] == 0 ? L.D[mu] - 1 : -1;
+        nbr[site * 8 + mu] = site + up * stride[mu];
+        nbr[site * 8 + 4 + mu] = site + dn * stride[mu];
+    }
+}
+
+// ABI links complex128 [4][N][nc][nc] -> internal [N][4][nc][nc] of storage LS
+template <typename LS>
+__global__ void k_convert_links(Lat L, int nc, const double2 *__restrict__ in, LS *__restrict__ out) {
+    const long long n = 4LL * L.N * nc * nc;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ab = (int)(e % (nc * nc));
+    const long long t = e / (nc * nc);
+    const int site = (int)(t % L.N), mu = (int)(t / L.N);
+    const double2 v = in[e];
+    St<LS>::st(out, ((size_t)site * 4 + mu) * nc * nc + ab, (typename St<LS>::R)v.x,
+               (typename St<LS>::R)v.y);
+}
+
+// Initialise one block of W right-hand sides: b (FP64), r = p = b (storage
+// precision), x = 0, and |b|^2 per lane; the finishing workgroup sets up
+// the CG scalars.  SRC 0: probes generated from ProbeGen; 1: from ABI b.
+template <typename S, int SRC>
+__global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const double2 *__restrict__ babi,
+                                                 long long rhs0, long long nvalid, double2 *__restrict__ b64,
+                                                 S *__restrict__ r, S *__restrict__ p, S *__restrict__ xlo,
+                                                 double2 *__restrict__ x64, int mixed, Red rd, CgState cs) {
+    __shared__ double sm[kBlock];
+    const int tid = threadIdx.x, W = L.W, logW = L.logW;
+    const int j = tid & (W - 1);
+    const int nc = L.nc;
+    const unsigned long long seedmix = SRC == 0 ? mix64(g.seed) : 0ull;
+    double acc[1] = {0.0};
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int site = t * (kBlock >> logW) + (tid >> logW);
+        if (site >= L.lat.N) continue;
+        for (int a = 0; a < nc; ++a) {
+            double re = 0.0, im = 0.0;
+            if (SRC == 0) {
+                if (j < g.nvalid) probe_value(g, seedmix, L.lat, nc, g.rhs0 + j, site, a, re, im);
+            } else if (j < nvalid) {
+                const double2 v = babi[((size_t)(rhs0 + j) * L.lat.N + site) * nc + a];
+                re = v.x;
+                im = v.y;
+            }
+            const size_t i = ((size_t)(site * nc + a) << logW) + j;
+            b64[i] = make_double2(re, im);
+            St<S>::st(r, i, (typename St<S>::R)re, (typename St<S>::R)im);
+            St<S>::st(p, i, (typename St<S>::R)re, (typename St<S>::R)im);
+            St<S>::st(xlo, i, 0, 0);
+            if (mixed) x64[i] = make_double2(0.0, 0.0);
+            acc[0] += re * re + im * im;
+        }
+    }
+    block_partials<1>(acc, W, logW, rd, sm);
+}
+
+// q = A p for one block of right-hand sides; with CG, also p^H q per lane
+// and, in the finishing workgroup, alpha = rr / p^H q.
+// STAGE: links of the tile's sites staged in LDS (W >= 16).
+template <typename S, typename LS, int NC, bool LINKS, bool STAGE>
+__global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ p,
+                                                    S *__restrict__ q, const LS *__restrict__ U,
+                                                    const int *__restrict__ nbr, int cg, Red rd, CgState cs) {
+    using R = typename St<S>::R;
+    constexpr int kMaxSites = kBlock / 16;
+    __shared__ R su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
+    __shared__ int snb[STAGE ? kMaxSites * 8 : 1];
+    __shared__ double sm[kBlock];
+    const int tid = threadIdx.x, logW = L.logW, W = L.W;
+    const int j = tid & (W - 1), sl = tid >> logW;
+    const int sites_per_tile = kBlock >> logW;
+    const int N = L.lat.N;
+    double acc_pq[1] = {0.0};
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int site0 = t * sites_per_tile;
+        const int site = site0 + sl;
+        if (STAGE) {
+            __syncthreads();
+            const int ne = sites_per_tile * 8 * NC * NC;
+            for (int e = tid; e < ne; e += kBlock) {
+                const int s_l = e / (8 * NC * NC);
+                const int rem = e - s_l * 8 * NC * NC;
+                const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
+                const int gs = site0 + s_l;
+                R re = 0, im = 0;
+                if (LINKS && gs < N) {
+                    const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
+                    St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, re, im);
+                }
+                su[2 * e] = re;
+                su[2 * e + 1] = im;
+            }
+            for (int e = tid; e < sites_per_tile * 8; e += kBlock) {
+                const int gs = site0 + e / 8;
+                snb[e] = gs < N ? nbr[site0 * 8 + e] : 0;
+            }
+            __syncthreads();
+        }
+        if (site >= N) continue;
+        R ar[NC], ai[NC], pr[NC], pi[NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            St<S>::ld(p, ((size_t)(site * NC + a) << logW) + j, pr[a], pi[a]);
+            ar[a] = diag * pr[a];
+            ai[a] = diag * pi[a];
+        }
+#pragma unroll
+        for (int dir = 0; dir < 8; ++dir) {
+            const int y = STAGE ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
+            R vr[NC], vi[NC];
+#pragma unroll
+            for (int b = 0; b < NC; ++b) St<S>::ld(p, ((size_t)(y * NC + b) << logW) + j, vr[b], vi[b]);
+            if (!LINKS) {
+#pragma unroll
+                for (int a = 0; a < NC; ++a) {
+                    ar[a] -= vr[a];
+                    ai[a] -= vi[a];
+                }
+                continue;
+            }
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+#pragma unroll
+                for (int b = 0; b < NC; ++b) {
+                    // forward: U_mu(x)[a][b];  backward: conj(U_mu(x-mu)[b][a])
+                    const int ab = dir < 4 ? a * NC + b : b * NC + a;
+                    R ur, ui;
+                    if (STAGE) {
+                        const int e = (sl * 8 + dir) * NC * NC + ab;
+                        ur = su[2 * e];
+                        ui = su[2 * e + 1];
+                    } else {
+                        const int src = dir < 4 ? site : y;
+                        St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, ur, ui);
+                    }
+                    if (dir >= 4) ui = -ui;
+                    ar[a] -= ur * vr[b] - ui * vi[b];
+                    ai[a] -= ur * vi[b] + ui * vr[b];
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            St<S>::st(q, ((size_t)(site * NC + a) << logW) + j, ar[a], ai[a]);
+            acc_pq[0] += (double)pr[a] * (double)ar[a] + (double)pi[a] * (double)ai[a];
+        }
+    }
+    if (!cg) return;
+    block_partials<1>(acc_pq, W, logW, rd, sm);
+}
+
+// x += alpha p; r -= alpha q; |r|^2 per lane; epilogue: beta, convergence.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xlo, const S *__restrict__ p,
+                                                    S *__restrict__ r, const S *__restrict__ q, Red rd,
+                                                    CgState cs) {
+    using R = typename St<S>::R;
+    __shared__ double sm[kBlock];
+    const int tid = threadIdx.x, logW = L.logW, W = L.W;
+    const int j = tid & (W - 1), sl = tid >> logW;
+    const int sites_per_tile = kBlock >> logW;
+    const int nc = L.nc;
+    const R alpha = (R)cs.alpha[j];
+    double acc[1] = {0.0};
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    const size_t e0 = (size_t)t0 * sites_per_tile * nc * W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * nc * W;
+    // element e = ((site * nc + a) << logW) + j: lane j is tid & (W-1) for
+    // every e = e0 + tid + k * kBlock since kBlock is a multiple of W
+    for (size_t e = e0 + tid; e < e1; e += kBlock) {
+        (void)sl;
+        R xr, xi, pr, pi, rr_, ri, qr, qi;
+        St<S>::ld(xlo, e, xr, xi);
+        St<S>::ld(p, e, pr, pi);
+        St<S>::ld(r, e, rr_, ri);
+        St<S>::ld(q, e, qr, qi);
+        xr += alpha * pr;
+        xi += alpha * pi;
+        rr_ -= alpha * qr;
+        ri -= alpha * qi;
+        St<S>::st(xlo, e, xr, xi);
+        St<S>::st(r, e, rr_, ri);
+        // the stored (rounded) residual is what the next iteration uses
+        St<S>::ld(r, e, rr_, ri);
+        acc[0] += (double)rr_ * rr_ + (double)ri * ri;
+    }
+    block_partials<1>(acc, W, logW, rd, sm);
+}
+
+// p = r + beta p
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restrict__ r, S *__restrict__ p,
+                                                    CgState cs) {
+    using R = typename St<S>::R;
+    const int tid = threadIdx.x, W = L.W;
+    const int j = tid & (W - 1);
+    const int sites_per_tile = kBlock >> L.logW;
+    const R beta = (R)cs.beta[j];
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
+    for (size_t e = e0 + tid; e < e1; e += kBlock) {
+        R rr_, ri, pr, pi;
+        St<S>::ld(r, e, rr_, ri);
+        St<S>::ld(p, e, pr, pi);
+        St<S>::st(p, e, rr_ + beta * pr, ri + beta * pi);
+    }
+}
+
+// x64 += xlo; xlo = 0
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
+    using R = typename St<S>::R;
+    const int tid = threadIdx.x;
+    const int sites_per_tile = kBlock >> L.logW;
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * L.W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * L.W;
+    for (size_t e = e0 + tid; e < e1; e += kBlock) {
+        R xr, xi;
+        St<S>::ld(xlo, e, xr, xi);
+        double2 v = x64[e];
+        v.x += (double)xr;
+        v.y += (double)xi;
+        x64[e] = v;
+        St<S>::st(xlo, e, 0, 0);
+    }
+}
+
+// FP64 true residual r = b - A x (FP64 links); stores r in the storage
+// precision and |r|^2 per lane.  ru_mode 1 (reliable update): the residual
+// replaces the recursive one, beta is recomputed from it and lanes whose
+// true residual meets tol are retired.  ru_mode 0: statistics only.
+template <typename S, int NC, bool LINKS>
+__global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
+                                                       const double2 *__restrict__ x64,
+                                                       const double2 *__restrict__ U, const int *__restrict__ nbr,
+                                                       S *__restrict__ rout, int ru_mode, Red rd, CgState cs) {
+    __shared__ double sm[kBlock];
+    const int tid = threadIdx.x, logW = L.logW, W = L.W;
+    const int j = tid & (W - 1), sl = tid >> logW;
+    const int sites_per_tile = kBlock >> logW;
+    double acc[1] = {0.0};
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int site = t * sites_per_tile + sl;
+        if (site >= L.lat.N) continue;
+        double ar[NC], ai[NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            const size_t i = ((size_t)(site * NC + a) << logW) + j;
+            const double2 xv = x64[i], bv = b64[i];
+            ar[a] = bv.x - diag * xv.x;
+            ai[a] = bv.y - diag * xv.y;
+        }
+#pragma unroll
+        for (int dir = 0; dir < 8; ++dir) {
+            const int y = nbr[site * 8 + dir];
+            double vr[NC], vi[NC];
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                const double2 v = x64[((size_t)(y * NC + b) << logW) + j];
+                vr[b] = v.x;
+                vi[b] = v.y;
+            }
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                if (!LINKS) {
+                    ar[a] += vr[a];
+                    ai[a] += vi[a];
+                    continue;
+                }
+#pragma unroll
+                for (int b = 0; b < NC; ++b) {
+                    const int src = dir < 4 ? site : y;
+                    const int ab = dir < 4 ? a * NC + b : b * NC + a;
+                    const double2 u = U[((size_t)src * 4 + (dir & 3)) * NC * NC + ab];
+                    const double ui = dir < 4 ? u.y : -u.y;
+                    ar[a] += u.x * vr[b] - ui * vi[b];
+                    ai[a] += u.x * vi[b] + ui * vr[b];
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            const size_t i = ((size_t)(site * NC + a) << logW) + j;
+            St<S>::st(rout, i, (typename St<S>::R)ar[a], (typename St<S>::R)ai[a]);
+            acc[0] += ar[a] * ar[a] + ai[a] * ai[a];
+        }
+    }
+    block_partials<1>(acc, W, logW, rd, sm);
+}
+
+// t_j = sum_x sum_b conj(v_j(x,b)) x_j(x + p e0, b), probes regenerated.
+__global__ __launch_bounds__(kBlock) void k_displaced_dot(Launch L, ProbeGen g, int p,
+                                                         const double2 *__restrict__ x64, Red rd, CgState cs) {
+    __shared__ double sm[2 * kBlock];
+    const int tid = threadIdx.x, logW = L.logW, W = L.W;
+    const int j = tid & (W - 1), sl = tid >> logW;
+    const int sites_per_tile = kBlock >> logW, nc = L.nc;
+    const unsigned long long seedmix = mix64(g.seed);
+    double acc[2] = {0.0, 0.0};
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    if (j < g.nvalid) {
+        const long long J = g.rhs0 + j;
+        const int ndil = g.dilute ? nc : 1;
+        const int c = (int)((J / ndil) % g.ncolors);
+        for (int t = t0; t < t1; ++t) {
+            const int site = t * sites_per_tile + sl;
+            if (site >= L.lat.N || g.colors[site] != c) continue;
+            const int y = shift0(L.lat, site, p);
+            for (int b = 0; b < nc; ++b) {
+                double zr, zi;
+                probe_value(g, seedmix, L.lat, nc, J, site, b, zr, zi);
+                if (zr == 0.0 && zi == 0.0) continue;
+                const double2 xv = x64[((size_t)(y * nc + b) << logW) + j];
+                acc[0] += zr * xv.x + zi * xv.y;  // conj(z) * x
+                acc[1] += zr * xv.y - zi * xv.x;
+            }
+        }
+    }
+    block_partials<2>(acc, W, logW, rd, sm);
+}
+
+// t_j = a_j^H b_j (FP64 vectors)
+__global__ __launch_bounds__(kBlock) void k_dot(Launch L, const double2 *__restrict__ a64,
+                                               const double2 *__restrict__ b64, Red rd, CgState cs) {
+    __shared__ double sm[2 * kBlock];
+    const int tid = threadIdx.x, W = L.W;
+    const int sites_per_tile = kBlock >> L.logW;
+    double acc[2] = {0.0, 0.0};
+    int t0, t1;
+    tile_range(L.ntiles, t0, t1);
+    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
+    for (size_t e = e0 + tid; e < e1; e += kBlock) {
+        const double2 u = a64[e], v = b64[e];
+        acc[0] += u.x * v.x + u.y * v.y;
+        acc[1] += u.x * v.y - u.y * v.x;
+    }
+    block_partials<2>(acc, W, L.logW, rd, sm);
+}
+
+// Adjoint force of one block of right-hand sides, one thread per output
+// entry (site, mu, a, b):
+//   dU[mu][x][a][b]    (+)= scale * sum_j conj(l_j(x)_a) x_j(x+mu)_b
+//   dUbar[mu][x][a][b] (+)= scale * sum_j x_j(x)_a conj(l_j(x+mu)_b)
+__global__ __launch_bounds__(kBlock) void k_force(Launch L, const double2 *__restrict__ x64,
+                                                 const double2 *__restrict__ l64, const int *__restrict__ nbr,
+                                                 double scale, int first, double2 *__restrict__ dU,
+                                                 double2 *__restrict__ dUbar) {
+    const int nc = L.nc, W = L.W, logW = L.logW;
+    const long long n = (long long)L.lat.N * 4 * nc * nc;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int b = (int)(e % nc);
+    const int a = (int)((e / nc) % nc);
+    const int mu = (int)((e / (nc * nc)) % 4);
+    const int site = (int)(e / (4 * nc * nc));
+    const int y = nbr[site * 8 + mu];
+    double ur = 0, ui = 0, vr = 0, vi = 0;
+    const double2 *la = l64 + ((size_t)(site * nc + a) << logW);
+    const double2 *xb = x64 + ((size_t)(y * nc + b) << logW);
+    const double2 *xa = x64 + ((size_t)(site * nc + a) << logW);
+    const double2 *lb = l64 + ((size_t)(y * nc + b) << logW);
+    for (int j = 0; j < W; ++j) {
+        const double2 l1 = la[j], x1 = xb[j], x2 = xa[j], l2 = lb[j];
+        ur += l1.x * x1.x + l1.y * x1.y;  // conj(l) x
+        ui += l1.x * x1.y - l1.y * x1.x;
+        vr += x2.x * l2.x + x2.y * l2.y;  // x conj(l)
+        vi += x2.y * l2.x - x2.x * l2.y;
+    }
+    const size_t o = ((size_t)mu * L.lat.N + site) * nc * nc + a * nc + b;
+    double2 du = make_double2(scale * ur, scale * ui), db = make_double2(scale * vr, scale * vi);
+    if (!first) {
+        if (dU) {
+            const double2 t = dU[o];
+            du.x += t.x;
+            du.y += t.y;
+        }
+        if (dUbar) {
+            const double2 t = dUbar[o];
+            db.x += t.x;
+            db.y += t.y;
+        }
+    }
+    if (dU) dU[o] = du;
+    if (dUbar) dUbar[o] = db;
+}
+
+// internal FP64 -> ABI [rhs][site][nc] for lanes < nvalid
+__global__ void k_to_abi(Launch L, const double2 *__restrict__ x64, double2 *__restrict__ xabi, long long rhs0,
+                         long long nvalid) {
+    const long long n = (long long)L.lat.N * L.nc * L.W;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int j = (int)(e & (L.W - 1));
+    const long long sa = e >> L.logW;  // site * nc + a
+    if (j >= nvalid) return;
+    xabi[(size_t)(rhs0 + j) * L.lat.N * L.nc + sa] = x64[e];
+}
+
+template <typename S>
+__global__ void k_abi_to_internal(Launch L, const double2 *__restrict__ vabi, long long rhs0, long long nvalid,
+                                  S *__restrict__ out) {
+    const long long n = (long long)L.lat.N * L.nc * L.W;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int j = (int)(e & (L.W - 1));
+    const long long sa = e >> L.logW;
+    double re = 0, im = 0;
+    if (j < nvalid) {
+        const double2 v = vabi[(size_t)(rhs0 + j) * L.lat.N * L.nc + sa];
+        re = v.x;
+        im = v.y;
+    }
+    St<S>::st(out, e, (typename St<S>::R)re, (typename St<S>::R)im);
+}
+
+template <typename S>
+__global__ void k_internal_to_abi(Launch L, const S *__restrict__ in, double2 *__restrict__ yabi, long long rhs0,
+                                  long long nvalid) {
+    const long long n = (long long)L.lat.N * L.nc * L.W;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int j = (int)(e & (L.W - 1));
+    if (j >= nvalid) return;
+    typename St<S>::R re, im;
+    St<S>::ld(in, e, re, im);
+    yabi[(size_t)(rhs0 + j) * L.lat.N * L.nc + (e >> L.logW)] = make_double2((double)re, (double)im);
+}
+
+// probes in the ABI layout [rhs][site][nc]
+__global__ void k_probes_abi(Lat lat, int nc, ProbeGen g, long long nrhs, double2 *__restrict__ out) {
+    const long long n = nrhs * lat.N * nc;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int b = (int)(e % nc);
+    const int site = (int)((e / nc) % lat.N);
+    const long long jj = e / ((long long)nc * lat.N);
+    double re, im;
+    probe_value(g, mix64(g.seed), lat, nc, g.rhs0 + jj, site, b, re, im);
+    out[e] = make_double2(re, im);
+}
+
+// ============================================================ launchers
+
+static int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+int grid_blocks(int ntiles) {
+    // enough workgroups to fill 256 CUs several times over, a multiple of 8
+    // (one contiguous share per XCD); never more than there are tiles
+    const int cap = 2048;
+    if (ntiles <= 8) return ntiles;
+    int n = ntiles < cap ? ntiles : cap;
+    return n - n % 8;
+}
+
+void build_neighbours(const Lat &lat, int *nbr, hipStream_t s) {
+    k_neighbours<<<blocks_for(lat.N), kBlock, 0, s>>>(lat, nbr);
+}
+
+void convert_links(int prec, const Lat &lat, int nc, const void *abi, void *out, hipStream_t s) {
+    const long long n = 4LL * lat.N * nc * nc;
+    const double2 *in = (const double2 *)abi;
+    if (prec == kF64)
+        k_convert_links<double2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, (double2 *)out);
+    else if (prec == kF32)
+        k_convert_links<float2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, (float2 *)out);
+    else
+        k_convert_links<bf16x2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, (bf16x2 *)out);
+}
+
+#define DP_DISPATCH_PREC(prec, S, ...)          \
+    do {                                        \
+        if ((prec) == kF64) {                   \
+            using S = double2;                  \
+            __VA_ARGS__;                        \
+        } else if ((prec) == kF32) {            \
+            using S = float2;                   \
+            __VA_ARGS__;                        \
+        } else {                                \
+            using S = bf16x2;                   \
+            __VA_ARGS__;                        \
+        }                                       \
+    } while (0)
+
+void launch_init_probe(const Launch &L, int prec, const ProbeGen &g, double *b64, void *r, void *p, void *xlo,
+                       double *x64, int mixed, const Red &rd, const CgState &cs) {
+    DP_DISPATCH_PREC(prec, S,
+                     k_init<S, 0><<<L.nblk, kBlock, 0, L.stream>>>(L, g, nullptr, 0, 0, (double2 *)b64, (S *)r,
+                                                                   (S *)p, (S *)xlo, (double2 *)x64, mixed, rd,
+                                                                   cs));
+    k_finish<1, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_init_abi(const Launch &L, int prec, const double *babi, long long rhs0, long long nvalid, double *b64,
+                     void *r, void *p, void *xlo, double *x64, int mixed, const Red &rd, const CgState &cs) {
+    ProbeGen g{};
+    DP_DISPATCH_PREC(prec, S,
+                     k_init<S, 1><<<L.nblk, kBlock, 0, L.stream>>>(L, g, (const double2 *)babi, rhs0, nvalid,
+                                                                   (double2 *)b64, (S *)r, (S *)p, (S *)xlo,
+                                                                   (double2 *)x64, mixed, rd, cs));
+    k_finish<1, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+template <typename S, typename LS>
+static void stencil_t(const Launch &L, bool links, double diag, const void *p, void *q, const void *U,
+                      const int *nbr, bool cg, const Red &rd, const CgState &cs) {
+    using R = typename St<S>::R;
+    const bool stage = L.W >= 16;
+    const S *pp = (const S *)p;
+    S *qq = (S *)q;
+    const LS *uu = (const LS *)U;
+    dim3 grid(L.nblk), blk(kBlock);
+    if (L.nc == 3) {
+        if (links) {
+            if (stage)
+                k_stencil<S, LS, 3, true, true><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
+            else
+                k_stencil<S, LS, 3, true, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
+        } else {
+            k_stencil<S, LS, 3, false, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
+        }
+    } else {
+        if (links) {
+            if (stage)
+                k_stencil<S, LS, 1, true, true><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
+            else
+                k_stencil<S, LS, 1, true, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
+        } else {
+            k_stencil<S, LS, 1, false, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
+        }
+    }
+}
+
+void launch_stencil(const Launch &L, int prec, bool links, double diag, const void *p, void *q, const void *U,
+                    const int *nbr, bool cg, const Red &rd, const CgState &cs) {
+    if (prec == kF64)
+        stencil_t<double2, double2>(L, links, diag, p, q, U, nbr, cg, rd, cs);
+    else if (prec == kF32)
+        stencil_t<float2, float2>(L, links, diag, p, q, U, nbr, cg, rd, cs);
+    else
+        stencil_t<bf16x2, bf16x2>(L, links, diag, p, q, U, nbr, cg, rd, cs);
+    if (cg) k_finish<1, kEpiAlpha><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r, const void *q, const Red &rd,
+                    const CgState &cs) {
+    DP_DISPATCH_PREC(prec, S,
+                     k_update1<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)xlo, (const S *)p, (S *)r,
+                                                                   (const S *)q, rd, cs));
+    k_finish<1, kEpiBeta><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_update2(const Launch &L, int prec, const void *r, void *p, const CgState &cs) {
+    DP_DISPATCH_PREC(prec, S, k_update2<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (const S *)r, (S *)p, cs));
+}
+
+void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {
+    DP_DISPATCH_PREC(prec, S, k_fold<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (double2 *)x64, (S *)xlo));
+}
+
+void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64, const double *x64,
+                       const void *U64, const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs) {
+    const double2 *b = (const double2 *)b64, *x = (const double2 *)x64, *u = (const double2 *)U64;
+    DP_DISPATCH_PREC(prec, S, {
+        if (L.nc == 3) {
+            if (links)
+                k_true_resid<S, 3, true><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
+            else
+                k_true_resid<S, 3, false><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
+        } else {
+            if (links)
+                k_true_resid<S, 1, true><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
+            else
+                k_true_resid<S, 1, false><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
+        }
+    });
+    if (ru_mode)
+        k_finish<1, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+    else
+        k_finish<1, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_displaced_dot(const Launch &L, const ProbeGen &g, int p, const double *x64, const Red &rd,
+                          const CgState &cs) {
+    k_displaced_dot<<<L.nblk, kBlock, 0, L.stream>>>(L, g, p, (const double2 *)x64, rd, cs);
+    k_finish<2, kEpiTj><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_dot(const Launch &L, const double *a64, const double *b64, const Red &rd, const CgState &cs) {
+    k_dot<<<L.nblk, kBlock, 0, L.stream>>>(L, (const double2 *)a64, (const double2 *)b64, rd, cs);
+    k_finish<2, kEpiTj><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_ctrl(const CgState &cs, int W, hipStream_t s) { k_ctrl<<<1, 64, 0, s>>>(cs, W); }
+
+void launch_force(const Launch &L, const double *x64, const double *l64, const int *nbr, double scale, int first,
+                  double *dU, double *dUbar) {
+    const long long n = (long long)L.lat.N * 4 * L.nc * L.nc;
+    k_force<<<blocks_for(n), kBlock, 0, L.stream>>>(L, (const double2 *)x64, (const double2 *)l64, nbr, scale,
+                                                    first, (double2 *)dU, (double2 *)dUbar);
+}
+
+void launch_to_abi(const Launch &L, const double *x64, double *xabi, long long rhs0, long long nvalid) {
+    const long long n = (long long)L.lat.N * L.nc * L.W;
+    k_to_abi<<<blocks_for(n), kBlock, 0, L.stream>>>(L, (const double2 *)x64, (double2 *)xabi, rhs0, nvalid);
+}
+
+void launch_abi_to_internal(const Launch &L, int prec, const double *vabi, long long rhs0, long long nvalid,
+                            void *out) {
+    const long long n = (long long)L.lat.N * L.nc * L.W;
+    DP_DISPATCH_PREC(prec, S,
+                     k_abi_to_internal<S><<<blocks_for(n), kBlock, 0, L.stream>>>(L, (const double2 *)vabi, rhs0,
+                                                                                  nvalid, (S *)out));
+}
+
+void launch_internal_to_abi_prec(const Launch &L, int prec, const void *in, double *yabi, long long rhs0,
+                                 long long nvalid) {
+    const long long n = (long long)L.lat.N * L.nc * L.W;
+    DP_DISPATCH_PREC(prec, S,
+                     k_internal_to_abi<S><<<blocks_for(n), kBlock, 0, L.stream>>>(L, (const S *)in, (double2 *)yabi,
+                                                                                  rhs0, nvalid));
+}
+
+void launch_make_probes_abi(const Lat &lat, int nc, const ProbeGen &g, long long nrhs, double *out, hipStream_t s) {
+    const long long n = nrhs * lat.N * nc;
+    k_probes_abi<<<blocks_for(n), kBlock, 0, s>>>(lat, nc, g, nrhs, (double2 *)out);
+}
+
+}  // namespace dp

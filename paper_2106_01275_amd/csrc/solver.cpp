@@ -1,0 +1,291 @@
+// Solver driver: operator preparation, workspace, the batched CG loop with
+// FP64 reliable updates, and the right-hand-side block width choice.
+//
+// CG (Hestenes-Stiefel, x0 = 0) runs on a block of W right-hand sides at
+// once; every right-hand side keeps its own scalars on the device (alpha,
+// beta, |r|^2), and right-hand sides that have converged are frozen
+// (alpha = 0) while the others continue.  One iteration is three kernels:
+//   stencil   q = A p, p^H q            -> alpha (finishing workgroup)
+//   update1   x += alpha p, r -= alpha q, |r|^2 -> beta, convergence flags
+//   update2   p = r + beta p
+// The host reads a 16-byte control word every `check_every` iterations.
+//
+// Mixed precision (inner = F32 or BF16): x, r, p, q are stored in the inner
+// precision and the stencil accumulates in FP32; the solution is kept in
+// FP64 (x64) and the residual is replaced by the FP64 true residual b - A x64
+// (FP64 links) whenever it has dropped by reliable_delta since the last
+// replacement, or when every active right-hand side believes it has
+// converged.  Convergence is then decided on the FP64 true residual.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "context.h"
+
+dp_status dp_ctx::ensure(int s, size_t bytes, bool zero) {
+    if (bytes == 0) bytes = 256;
+    if (slot_bytes[s] >= bytes) return DP_OK;
+    dp_ctx *ctx = this;
+    if (slot[s]) DP_HIP(hipFree(slot[s]));
+    slot[s] = nullptr;
+    slot_bytes[s] = 0;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        err = "out of device memory (" + std::to_string(bytes) + " bytes)";
+        return DP_ENOMEM;
+    }
+    if (zero) DP_HIP(hipMemset(p, 0, bytes));
+    slot[s] = p;
+    slot_bytes[s] = bytes;
+    return DP_OK;
+}
+
+namespace dp {
+
+static size_t prec_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
+
+dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep &out, hipStream_t s) {
+    for (int d = 0; d < 4; ++d)
+        if (op.dims[d] < 1) {
+            ctx->err = "operator dims must be >= 1";
+            return DP_EINVAL;
+        }
+    if (op.nc != 1 && op.nc != 3) {
+        ctx->err = "operator nc must be 1 or 3";
+        return DP_EINVAL;
+    }
+    if (inner != kF64 && inner != kF32 && inner != kBF16) {
+        ctx->err = "unknown precision";
+        return DP_EINVAL;
+    }
+    const long long N = (long long)op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3];
+    if (N > (1LL << 30) / 8) {
+        ctx->err = "lattice too large";
+        return DP_EUNSUPPORTED;
+    }
+    if (!std::isfinite(op.m2)) {
+        ctx->err = "m2 must be finite";
+        return DP_EINVAL;
+    }
+    out.lat.N = (int)N;
+    for (int d = 0; d < 4; ++d) out.lat.D[d] = op.dims[d];
+    out.nc = op.nc;
+    out.m2 = op.m2;
+    out.links = op.links != nullptr;
+    out.inner = inner;
+    DP_TRY(ctx->ensure(kSlotNbr, (size_t)N * 8 * sizeof(int)));
+    build_neighbours(out.lat, (int *)ctx->at(kSlotNbr), s);
+    out.nbr = (const int *)ctx->at(kSlotNbr);
+    if (out.links) {
+        const size_t nl = (size_t)N * 4 * op.nc * op.nc;
+        DP_TRY(ctx->ensure(kSlotU64, nl * 16));
+        convert_links(kF64, out.lat, op.nc, op.links, ctx->at(kSlotU64), s);
+        out.U64 = ctx->at(kSlotU64);
+        if (inner == kF64) {
+            out.ULo = out.U64;
+        } else {
+            DP_TRY(ctx->ensure(kSlotULo, nl * prec_bytes(inner)));
+            convert_links(inner, out.lat, op.nc, op.links, ctx->at(kSlotULo), s);
+            out.ULo = ctx->at(kSlotULo);
+        }
+    }
+    DP_HIP(hipGetLastError());
+    return DP_OK;
+}
+
+dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launch &L, Red &rd, CgState &cs,
+                      const SolveCfg &cfg) {
+    int logW = 0;
+    while ((1 << logW) < W) ++logW;
+    L.lat = op.lat;
+    L.nc = op.nc;
+    L.W = W;
+    L.logW = logW;
+    L.ntiles = (op.lat.N + (kBlock >> logW) - 1) / (kBlock >> logW);
+    L.nblk = grid_blocks(L.ntiles);
+    L.stream = s;
+    const size_t vec = (size_t)op.lat.N * op.nc * W;
+    const size_t lo = vec * prec_bytes(cfg.inner);
+    DP_TRY(ctx->ensure(kSlotB64, vec * 16));
+    DP_TRY(ctx->ensure(kSlotX64, vec * 16));
+    DP_TRY(ctx->ensure(kSlotR, lo));
+    DP_TRY(ctx->ensure(kSlotP, lo));
+    DP_TRY(ctx->ensure(kSlotQ, lo));
+    if (cfg.inner != kF64) DP_TRY(ctx->ensure(kSlotXLo, lo));
+    DP_TRY(ctx->ensure(kSlotPart1, (size_t)L.nblk * W * 2 * sizeof(double)));
+    rd.part1 = (double *)ctx->at(kSlotPart1);
+    rd.nblk = L.nblk;
+    const size_t nd = 9 * kMaxW, ni = 3 * kMaxW + 8;
+    DP_TRY(ctx->ensure(kSlotState, nd * sizeof(double) + ni * sizeof(int)));
+    double *d = (double *)ctx->at(kSlotState);
+    cs.rr = d;
+    cs.rr_prev = d + kMaxW;
+    cs.rr_ref = d + 2 * kMaxW;
+    cs.bb = d + 3 * kMaxW;
+    cs.alpha = d + 4 * kMaxW;
+    cs.beta = d + 5 * kMaxW;
+    cs.true_rr = d + 6 * kMaxW;
+    cs.tj = d + 7 * kMaxW;
+    int *iv = (int *)(d + nd);
+    cs.active = iv;
+    cs.iters = iv + kMaxW;
+    cs.flags = iv + 2 * kMaxW;
+    cs.ctrl = iv + 3 * kMaxW;
+    cs.tol2 = cfg.tol * cfg.tol;
+    cs.delta2 = cfg.delta * cfg.delta;
+    cs.exact = cfg.inner == kF64;
+    return DP_OK;
+}
+
+static dp_status read_ctrl(dp_ctx *ctx, const CgState &cs, int W, hipStream_t s) {
+    launch_ctrl(cs, W, s);
+    DP_HIP(hipMemcpyAsync(ctx->ctrl_host, cs.ctrl, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    DP_HIP(hipStreamSynchronize(s));
+    return DP_OK;
+}
+
+static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L, const OpPrep &op,
+                               const Red &rd, const CgState &cs) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (cfg.profile) {
+        if (ctx->ev_pool.size() < 2) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                DP_HIP(hipEventCreate(&e));
+                ctx->ev_pool.push_back(e);
+            }
+        }
+        e0 = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        e1 = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        DP_HIP(hipEventRecord(e0, L.stream));
+    }
+    launch_stencil(L, cfg.inner, op.links, op.m2 + 8.0, ctx->at(kSlotP), ctx->at(kSlotQ), op.ULo, op.nbr, true, rd,
+                   cs);
+    if (cfg.profile) {
+        DP_HIP(hipEventRecord(e1, L.stream));
+        ctx->ev_pending.emplace_back(e0, e1);
+    }
+    return DP_OK;
+}
+
+dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
+    if (ctx->ev_pending.empty()) return DP_OK;
+    double ms_sum = 0;
+    for (auto &pr : ctx->ev_pending) {
+        DP_HIP(hipEventSynchronize(pr.second));
+        float ms = 0;
+        DP_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        ms_sum += ms;
+        ctx->ev_pool.push_back(pr.first);
+        ctx->ev_pool.push_back(pr.second);
+    }
+    if (st) {
+        st->stencil_ms += ms_sum;
+        st->stencil_launches += (int)ctx->ev_pending.size();
+    }
+    ctx->ev_pending.clear();
+    return DP_OK;
+}
+
+template <typename Init>
+dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
+                      const CgState &cs, double *x64, Init init, BlockStats &bs, dp_solve_stats *acc) {
+    const bool mixed = cfg.inner != kF64;
+    void *xlo = mixed ? ctx->at(kSlotXLo) : (void *)x64;
+    void *r = ctx->at(kSlotR), *p = ctx->at(kSlotP), *q = ctx->at(kSlotQ);
+    const double *b64 = (const double *)ctx->at(kSlotB64);
+    init(xlo, x64);
+    DP_HIP(hipGetLastError());
+    DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
+    int nactive = ctx->ctrl_host[0];
+    int it = 0;
+    bool pending = false;
+    const int check = std::max(1, ctx->check_every);
+    while (nactive > 0 && it < cfg.max_iter) {
+        const int steps = std::min(check, cfg.max_iter - it);
+        for (int c = 0; c < steps; ++c) {
+            if (pending) launch_update2(L, cfg.inner, r, p, cs);
+            DP_TRY(timed_stencil(ctx, cfg, L, op, rd, cs));
+            launch_update1(L, cfg.inner, xlo, p, r, q, rd, cs);
+            pending = true;
+        }
+        DP_HIP(hipGetLastError());
+        it += steps;
+        DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
+        nactive = ctx->ctrl_host[0];
+        if (mixed && nactive > 0 &&
+            (ctx->ctrl_host[2] > 0 || ctx->ctrl_host[1] == nactive || it >= cfg.max_iter)) {
+            launch_fold(L, cfg.inner, x64, xlo);
+            launch_true_resid(L, cfg.inner, op.links, op.m2 + 8.0, b64, x64, op.U64, op.nbr, r, 1, rd, cs);
+            DP_HIP(hipGetLastError());
+            ++bs.ru;
+            DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
+            nactive = ctx->ctrl_host[0];
+        }
+    }
+    if (mixed) launch_fold(L, cfg.inner, x64, xlo);
+    // final FP64 true residual (statistics only)
+    launch_true_resid(L, cfg.inner, op.links, op.m2 + 8.0, b64, x64, op.U64, op.nbr, r, 0, rd, cs);
+    DP_HIP(hipGetLastError());
+    const int W = L.W;
+    double *h = ctx->state_host;
+    DP_HIP(hipMemcpyAsync(h, cs.true_rr, W * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+    DP_HIP(hipMemcpyAsync(h + kMaxW, cs.bb, W * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+    int *hi = (int *)(h + 2 * kMaxW);
+    DP_HIP(hipMemcpyAsync(hi, cs.iters, W * sizeof(int), hipMemcpyDeviceToHost, L.stream));
+    DP_HIP(hipMemcpyAsync(hi + kMaxW, cs.flags, W * sizeof(int), hipMemcpyDeviceToHost, L.stream));
+    DP_HIP(hipStreamSynchronize(L.stream));
+    DP_TRY(finish_profile(ctx, acc));
+    for (int j = 0; j < bs.nvalid; ++j) {
+        const double bb = h[kMaxW + j];
+        const double rel = bb > 0 ? std::sqrt(h[j] / bb) : 0.0;
+        bs.max_rel = std::max(bs.max_rel, rel);
+        bs.iters_sum += hi[j];
+        bs.iters_max = std::max(bs.iters_max, hi[j]);
+        if (hi[kMaxW + j] & kFlagBreakdown) ++bs.nbreak;
+        else if (hi[kMaxW + j] & kFlagConverged) ++bs.nconv;
+    }
+    if (acc) {
+        acc->rhs_iters += bs.iters_sum;
+        acc->max_iters = std::max(acc->max_iters, bs.iters_max);
+        acc->nconverged += bs.nconv;
+        acc->nbreakdown += bs.nbreak;
+        acc->reliable_updates += bs.ru;
+        acc->max_true_resid = std::max(acc->max_true_resid, bs.max_rel);
+        acc->nrhs += bs.nvalid;
+    }
+    return DP_OK;
+}
+
+dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
+                       hipStream_t s, int &W) {
+    (void)s;
+    if (requested > 0) {
+        if (requested > kMaxW || (requested & (requested - 1))) {
+            ctx->err = "rhs_block must be a power of two <= 256";
+            return DP_EINVAL;
+        }
+        W = requested;
+        return DP_OK;
+    }
+    // default: the smallest power of two covering nrhs, capped at 64
+    int w = 1;
+    while (w < nrhs && w < 64) w *= 2;
+    (void)op;
+    (void)cfg;
+    W = w;
+    return DP_OK;
+}
+
+// explicit instantiations used by api.cpp
+template dp_status solve_block<InitProbe>(dp_ctx *, const OpPrep &, const SolveCfg &, const Launch &, const Red &,
+                                          const CgState &, double *, InitProbe, BlockStats &, dp_solve_stats *);
+template dp_status solve_block<InitAbi>(dp_ctx *, const OpPrep &, const SolveCfg &, const Launch &, const Red &,
+                                        const CgState &, double *, InitAbi, BlockStats &, dp_solve_stats *);
+
+}  // namespace dp

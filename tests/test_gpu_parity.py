@@ -1,0 +1,311 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: probes bit-exact; FP64 operator 1e-14, FP32 1e-6, BF16 1e-2
+(relative, from the unit roundoff of the storage format times the few
+operations per entry); FP64 solves and traces 1e-10 relative at CG tol
+<= 1e-12; mixed precision 1e-6 relative after FP64 refinement.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2106_01275_amd as dp  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return dp.context(0)
+
+
+def cuda(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _probe_setup(ctx, dims, nc, p, k, order, seed, s0, ns, noise, dilute):
+    col, n, _ = oracle.coloring(dims, p, k, {"natural": 0, "redblack": 1, "best": 2}[order])
+    colg = cuda(col)
+    ps = ctx.probe_spec(dims, nc, colg, n, seed, s0, ns, noise, dilute)
+    return col, n, colg, ps
+
+
+# ------------------------------------------------------------------ probes
+
+
+@pytest.mark.parametrize("dims,nc,noise,dilute,p,k", [((4, 4, 4, 4), 1, "real_z2", False, 1, 2),
+                                                      ((8, 8, 8, 8), 3, "z2_complex", True, 2, 4),
+                                                      ((6, 4, 5, 3), 3, "z4", False, 1, 2),
+                                                      ((5, 3, 4, 2), 3, "z4", True, 3, 1)])
+def test_make_probes_bit_exact(ctx, dims, nc, noise, dilute, p, k):
+    _say("probes", dims, nc, noise, dilute)
+    col, n, colg, ps = _probe_setup(ctx, dims, nc, p, k, "natural", 12345, 2, 2, noise, dilute)
+    kind = {"real_z2": 0, "z2_complex": 1, "z4": 2}[noise]
+    want = oracle.probes(dims, nc, col, n, 12345, 2, 2, kind, dilute)
+    got = ctx.make_probes(ps, 0, want.shape[0]).cpu().numpy()
+    assert np.array_equal(got, want)
+    # an offset window of the enumeration
+    got2 = ctx.make_probes(ps, 3, 5).cpu().numpy()
+    assert np.array_equal(got2, want[3:8])
+
+
+# ------------------------------------------------------------------ operator
+
+
+@pytest.mark.parametrize("prec,rtol", [("f64", 1e-14), ("f32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("dims,nc,links,nrhs", [((4, 4, 4, 4), 1, False, 3), ((4, 4, 4, 4), 3, True, 1),
+                                                ((6, 4, 5, 3), 3, True, 17), ((4, 6, 2, 5), 3, True, 64),
+                                                ((3, 4, 4, 5), 3, True, 100), ((5, 4, 3, 4), 1, True, 20),
+                                                ((2, 2, 2, 2), 3, False, 5)])
+def test_apply_matches_oracle(ctx, prec, rtol, dims, nc, links, nrhs):
+    _say("apply", prec, dims, nc, links, nrhs)
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(7)
+    U = workloads.random_links(dims, 0.7, 3, nc) if links else None
+    V = rng.standard_normal((nrhs, N, nc)) + 1j * rng.standard_normal((nrhs, N, nc))
+    op = ctx.operator(dims, nc, 0.3, None if U is None else cuda(U))
+    got = ctx.apply(op, cuda(V), prec).cpu().numpy()
+    want = np.stack([oracle.apply(dims, nc, 0.3, U, v) for v in V])
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err < rtol, err
+
+
+# ------------------------------------------------------------------ solves
+
+
+@pytest.mark.parametrize("dims,nc,nrhs,block", [((4, 4, 4, 4), 3, 5, 0), ((6, 4, 5, 3), 3, 33, 16),
+                                                ((4, 4, 4, 4), 1, 1, 1), ((3, 5, 4, 4), 3, 70, 64)])
+def test_solve_batch_fp64_matches_oracle(ctx, dims, nc, nrhs, block):
+    _say("solve f64", dims, nc, nrhs, block)
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(11)
+    U = workloads.random_links(dims, 0.5, 5, nc)
+    B = rng.standard_normal((nrhs, N, nc)) + 1j * rng.standard_normal((nrhs, N, nc))
+    op = ctx.operator(dims, nc, 0.2, cuda(U))
+    (X,), (st,) = ctx.solve_batch([op], [cuda(B)], ctx.opts(tol=1e-12, rhs_block=block))
+    Xo, it, rel = oracle.cg_many(dims, nc, 0.2, U, B, tol=1e-12)
+    X = X.cpu().numpy()
+    assert st["nconverged"] == nrhs and st["max_true_resid"] < 1e-11
+    assert np.abs(X - Xo).max() < 1e-10 * np.abs(Xo).max()
+    assert abs(st["max_iters"] - it.max()) <= 2
+
+
+@pytest.mark.parametrize("inner,block", [("f32", 32), ("f32", 64), ("bf16", 64), ("f32", 128)])
+def test_solve_batch_mixed_matches_oracle(ctx, inner, block):
+    _say("solve mixed", inner, block)
+    dims, nc, nrhs = (6, 4, 5, 4), 3, 70
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(12)
+    U = workloads.random_links(dims, 0.4, 6, nc)
+    B = rng.standard_normal((nrhs, N, nc)) + 1j * rng.standard_normal((nrhs, N, nc))
+    op = ctx.operator(dims, nc, 0.1, cuda(U))
+    (X,), (st,) = ctx.solve_batch([op], [cuda(B)], ctx.opts(tol=1e-10, inner=inner, rhs_block=block))
+    Xo, it, rel = oracle.cg_many(dims, nc, 0.1, U, B, tol=1e-13)
+    X = X.cpu().numpy()
+    assert st["nconverged"] == nrhs and st["max_true_resid"] <= 1e-10
+    assert st["reliable_updates"] >= 1
+    err = np.abs(X - Xo).max() / np.abs(Xo).max()
+    assert err < 1e-8, err
+
+
+def test_solve_empty_and_zero_rhs(ctx):
+    dims, nc = (4, 4, 4, 4), 3
+    op = ctx.operator(dims, nc, 0.5, None)
+    B = torch.zeros((0, 256, 3), dtype=torch.complex128, device="cuda")
+    (X,), (st,) = ctx.solve_batch([op], [B], ctx.opts(tol=1e-10))
+    assert st["nrhs"] == 0
+    B = torch.zeros((3, 256, 3), dtype=torch.complex128, device="cuda")
+    (X,), (st,) = ctx.solve_batch([op], [B], ctx.opts(tol=1e-10))
+    assert st["nconverged"] == 3 and torch.all(X == 0)
+
+
+def test_solve_failure_statuses(ctx):
+    dims = (4, 4, 4, 4)
+    # not an eigenvector: a constant vector would converge in one step
+    B = cuda(np.random.default_rng(2).standard_normal((2, 256, 1)).astype(np.complex128))
+    op = ctx.operator(dims, 1, 0.5, None)
+    (X,), (st,) = ctx.solve_batch([op], [B], ctx.opts(tol=1e-12, max_iter=1), check=False)
+    assert st["nconverged"] == 0 and st["max_iters"] == 1
+    with pytest.raises(dp.DPError) as e:
+        ctx.solve_batch([op], [B], ctx.opts(tol=1e-12, max_iter=1))
+    assert e.value.status == dp.ENOCONV
+    bad = ctx.operator(dims, 1, -9.0, None)  # negative definite
+    with pytest.raises(dp.DPError) as e:
+        ctx.solve_batch([bad], [B], ctx.opts(tol=1e-12))
+    assert e.value.status == dp.EBREAKDOWN
+    with pytest.raises(dp.DPError) as e:
+        ctx.solve_batch([op], [B], ctx.opts(tol=1e-12, rhs_block=3))
+    assert e.value.status == dp.EINVAL
+    with pytest.raises(dp.DPError) as e:
+        ctx.solve_batch([ctx.operator((4, 4, 0, 4), 1, 0.5, None)], [B], ctx.opts(tol=1e-12))
+    assert e.value.status == dp.EINVAL
+
+
+# ------------------------------------------------------------------ traces
+
+
+def test_trace_free_field_4(ctx):
+    """4^4 free field, m2 = 0.5, p = 1, distance-2 colouring (8 colours), real
+    Rademacher probes from seed 0, CG tol 1e-12: the GPU estimate equals the
+    oracle's; with one colour per site it equals the Fourier closed form."""
+    _say("trace free 4^4")
+    dims = (4, 4, 4, 4)
+    col, n, colg, ps = _probe_setup(ctx, dims, 1, 1, 2, "best", 0, 0, 4, "real_z2", False)
+    assert n == 8
+    op = ctx.operator(dims, 1, 0.5, None)
+    r = ctx.trace_estimate([op], [ps], [1], ctx.opts(tol=1e-12))[0]
+    o = oracle.trace(dims, 1, 0.5, None, 1, col, n, 0, 0, 4, oracle.REAL_Z2, False, tol=1e-12)
+    assert abs(r["T"] - o["T"]) < 1e-10 * abs(o["T"])
+    assert np.abs(r["per_sample"] - o["per_sample"]).max() < 1e-10 * abs(o["T"])
+    assert abs(r["stderr"] - o["stderr"]) < 1e-8 * o["stderr"]
+    assert r["solve"]["max_iters"] <= 10
+    exact, _ = workloads.free_field_trace(dims, 0.5, 1)
+    alld = cuda(np.arange(256, dtype=np.int32))
+    ps2 = ctx.probe_spec(dims, 1, alld, 256, 3, 0, 1, "real_z2", False)
+    r2 = ctx.trace_estimate([op], [ps2], [1], ctx.opts(tol=1e-13))[0]
+    assert abs(r2["T"] - exact) < 1e-11 * exact
+
+
+@pytest.mark.parametrize("inner,block", [("f64", 1), ("f64", 64), ("f32", 64), ("bf16", 64)])
+def test_trace_gauge_8(ctx, inner, block):
+    """8^4 x 3 gauge Laplacian, eps = 0.3 (links seed 1), m2 = 0.1, p = 2,
+    distance-4 colouring (best order: 64 colours), diluted Z2 complex noise,
+    192 right-hand sides.  Plain FP64 single-RHS (W = 1), batched FP64 and
+    mixed precision all agree with the oracle."""
+    _say("trace gauge 8^4", inner, block)
+    w = workloads.GAUGE_8
+    U = w.links()
+    col, n, colg, ps = _probe_setup(ctx, w.dims, 3, 2, 4, "best", 0, 0, 1, "z2_complex", True)
+    assert n == 64
+    op = ctx.operator(w.dims, 3, w.m2, cuda(U))
+    r = ctx.trace_estimate([op], [ps], [2], ctx.opts(tol=1e-11, inner=inner, rhs_block=block))[0]
+    o = _oracle_gauge8(col, n, U)
+    tol = 1e-10 if inner == "f64" else 1e-6
+    assert abs(r["T"] - o["T"]) < tol * abs(o["T"]), (r["T"], o["T"])
+    scale = np.abs(o["tj"]).max()
+    assert np.abs(r["tj"] - o["tj"]).max() < tol * scale
+    assert r["solve"]["max_true_resid"] < 1e-10
+
+
+_GAUGE8 = {}
+
+
+def _oracle_gauge8(col, n, U):
+    if "r" not in _GAUGE8:
+        w = workloads.GAUGE_8
+        _GAUGE8["r"] = oracle.trace(w.dims, 3, w.m2, U, 2, col, n, 0, 0, 1, oracle.Z2_COMPLEX, True,
+                                    tol=1e-12)
+    return _GAUGE8["r"]
+
+
+@pytest.mark.parametrize("dims,nc,p,k,noise,dilute,ns", [((4, 4, 4, 4), 3, 1, 2, "z4", False, 2),
+                                                         ((6, 4, 5, 3), 3, 2, 1, "z2_complex", True, 1),
+                                                         ((5, 4, 4, 4), 1, 0, 1, "real_z2", False, 3)])
+def test_trace_small_cases(ctx, dims, nc, p, k, noise, dilute, ns):
+    _say("trace small", dims, nc, p, k, noise)
+    U = workloads.random_links(dims, 0.5, 9, nc)
+    col, n, colg, ps = _probe_setup(ctx, dims, nc, p, k, "natural", 77, 1, ns, noise, dilute)
+    op = ctx.operator(dims, nc, 0.25, cuda(U))
+    r = ctx.trace_estimate([op], [ps], [p], ctx.opts(tol=1e-12))[0]
+    kind = {"real_z2": 0, "z2_complex": 1, "z4": 2}[noise]
+    o = oracle.trace(dims, nc, 0.25, U, p, col, n, 77, 1, ns, kind, dilute, tol=1e-12)
+    assert abs(r["T"] - o["T"]) < 1e-10 * abs(o["T"])
+
+
+def test_trace_single_colour_is_hutchinson(ctx):
+    dims = (4, 4, 4, 4)
+    col = np.zeros(256, dtype=np.int32)
+    colg = cuda(col)
+    ps = ctx.probe_spec(dims, 1, colg, 1, 5, 0, 6, "real_z2", False)
+    op = ctx.operator(dims, 1, 0.5, None)
+    r = ctx.trace_estimate([op], [ps], [1], ctx.opts(tol=1e-12))[0]
+    o = oracle.trace(dims, 1, 0.5, None, 1, col, 1, 5, 0, 6, oracle.REAL_Z2, False, tol=1e-12)
+    assert abs(r["T"] - o["T"]) < 1e-10 * abs(o["T"])
+
+
+# ------------------------------------------------------------------ gradient
+
+
+@pytest.mark.parametrize("dims,inner", [((4, 4, 4, 4), "f64"), ((2, 4, 2, 4), "f64"), ((4, 4, 4, 4), "f32")])
+def test_trace_grad_matches_oracle(ctx, dims, inner):
+    _say("grad", dims, inner)
+    U = workloads.random_links(dims, 0.5, 3)
+    col, n, colg, ps = _probe_setup(ctx, dims, 3, 1, 2, "natural", 17, 0, 2, "z2_complex", True)
+    op = ctx.operator(dims, 3, 0.2, cuda(U))
+    T, g, dU, dUb, st = ctx.trace_grad(op, ps, 1, ctx.opts(tol=1e-12 if inner == "f64" else 1e-11,
+                                                           inner=inner))
+    To, go, dUo, dUbo = oracle.trace_grad(dims, 3, 0.2, U, 1, col, n, 17, 0, 2, oracle.Z2_COMPLEX, True,
+                                          tol=1e-13)
+    tol = 1e-9 if inner == "f64" else 1e-6
+    assert abs(T - To) < tol * abs(To)
+    assert abs(g - go) < tol * abs(go)
+    s = np.abs(dUo).max()
+    assert np.abs(dU.cpu().numpy() - dUo).max() < tol * s
+    assert np.abs(dUb.cpu().numpy() - dUbo).max() < tol * s
+
+
+def test_grad_free_field_closed_form(ctx):
+    """All-distinct colouring on the 4^4 free field: dT/dm2 equals the
+    closed-form derivative -sum_k cos(k0 p)/lambda(k)^2."""
+    dims = (4, 4, 4, 4)
+    _, dexact = workloads.free_field_trace(dims, 0.5, 1)
+    colg = cuda(np.arange(256, dtype=np.int32))
+    ps = ctx.probe_spec(dims, 1, colg, 256, 1, 0, 1, "real_z2", False)
+    op = ctx.operator(dims, 1, 0.5, None)
+    T, g, _, _, _ = ctx.trace_grad(op, ps, 1, ctx.opts(tol=1e-13), want_links=False)
+    assert abs(g.real - dexact) < 1e-10 * abs(dexact) and abs(g.imag) < 1e-12
+
+
+def test_autograd_function_matches_finite_differences(ctx):
+    """The torch.autograd.Function maps the Wirtinger pair to PyTorch's
+    convention: check a real loss against central differences in m2 and
+    along a random su(3) direction of the links."""
+    dims = (2, 4, 2, 4)
+    N = 64
+    U0 = workloads.random_links(dims, 0.5, 8)
+    col, n, _ = oracle.coloring(dims, 1, 2, 0)
+    colg = cuda(col)
+    opts = dp.Context.opts(tol=1e-13)
+    m2 = torch.tensor(0.3, dtype=torch.float64, device="cuda", requires_grad=True)
+    U = cuda(U0).requires_grad_(True)
+
+    def loss(m2_, U_):
+        T = dp.probed_trace(m2_, U_, dims, 3, 1, colg, n, seed=4, nsamples=1, noise="z2_complex",
+                            dilute=True, opts=opts)
+        return (T * (0.7 - 0.4j)).real + T.abs() ** 2 * 0.1
+
+    L = loss(m2, U)
+    L.backward()
+    h = 1e-5
+    with torch.no_grad():
+        fd = (loss(m2 + h, U) - loss(m2 - h, U)) / (2 * h)
+    assert abs(fd.item() - m2.grad.item()) < 1e-6 * max(1.0, abs(fd.item()))
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((4, N, 3, 3)) + 1j * rng.standard_normal((4, N, 3, 3))
+    X = 0.5 * (G + np.conj(np.swapaxes(G, -1, -2)))
+    w_, Q = np.linalg.eigh(X)
+
+    def rot(t):
+        E = (Q * np.exp(1j * t * w_)[..., None, :]) @ np.conj(np.swapaxes(Q, -1, -2))
+        return cuda(E @ U0)
+
+    with torch.no_grad():
+        fdU = (loss(m2, rot(h)) - loss(m2, rot(-h))).item() / (2 * h)
+    dUdt = cuda(1j * X @ U0)
+    an = torch.sum((U.grad.conj() * dUdt).real).item()  # PyTorch: dL = Re<grad, dU>
+    assert abs(fdU - an) < 1e-6 * max(1.0, abs(fdU)), (fdU, an)
