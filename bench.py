@@ -39,8 +39,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--rhs-block", type=int, default=64)
+    ap.add_argument("--rhs-block", type=int, default=32)
     ap.add_argument("--inner", default="f32")
+    ap.add_argument("--delta", type=float, default=1e-3, help="reliable-update residual drop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-rhs", type=int, default=0, help="right-hand sides in the CPU sample (0: cores)")
@@ -79,7 +80,7 @@ def main():
     Ug = torch.from_numpy(U).cuda()
     colg = torch.from_numpy(col).cuda()
     op = c.operator(dims, nc, w.m2, Ug)
-    opts = c.opts(tol=w.tol, inner=a.inner, rhs_block=a.rhs_block, profile=1)
+    opts = c.opts(tol=w.tol, inner=a.inner, rhs_block=a.rhs_block, reliable_delta=a.delta, profile=1)
 
     def step(sample, prof=1):
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, sample, 1, "z2_complex", True)

@@ -401,8 +401,14 @@ dp_status dp_apply(dp_ctx *ctx, const dp_operator *opd, int32_t prec, const void
     for (long long r0 = 0; r0 < nrhs; r0 += W) {
         const long long nv = std::min<long long>(W, nrhs - r0);
         launch_abi_to_internal(L, prec, (const double *)v, r0, nv, ctx->at(kSlotP));
-        launch_stencil(L, prec, op.links, op.m2 + 8.0, ctx->at(kSlotP), ctx->at(kSlotQ), op.ULo, op.nbr, false, rd,
-                       cs);
+        StencilArgs sa;
+        sa.links = op.links;
+        sa.diag = op.m2 + 8.0;
+        sa.pin = ctx->at(kSlotP);
+        sa.q = ctx->at(kSlotQ);
+        sa.U = op.ULo;
+        sa.nbr = op.nbr;
+        launch_stencil(L, prec, sa);
         launch_internal_to_abi_prec(L, prec, ctx->at(kSlotQ), (double *)y, r0, nv);
         DP_HIP(hipGetLastError());
     }

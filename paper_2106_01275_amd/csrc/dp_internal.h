@@ -74,15 +74,26 @@ void launch_init_probe(const Launch &L, int prec, const ProbeGen &g, double *b64
 void launch_init_abi(const Launch &L, int prec, const double *babi, long long rhs0, long long nvalid,
                      double *b64, void *r, void *p, void *xlo, double *x64, int mixed, const Red &rd,
                      const CgState &cs);
-void launch_stencil(const Launch &L, int prec, bool links, double diag, const void *p, void *q,
-                    const void *U, const int *nbr, bool cg, const Red &rd, const CgState &cs);
+// Arguments of the stencil launch: q = A pin, with p^H q and alpha when cg.
+struct StencilArgs {
+    bool links = false;
+    double diag = 0;
+    const void *pin = nullptr;
+    void *q = nullptr;
+    const void *U = nullptr;
+    const int *nbr = nullptr;
+    int cg = 0;
+    Red rd{};
+    CgState cs{};
+};
+void launch_stencil(const Launch &L, int prec, const StencilArgs &a);
 void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r, const void *q,
                     const Red &rd, const CgState &cs);
 void launch_update2(const Launch &L, int prec, const void *r, void *p, const CgState &cs);
 void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
-                       const double *x64, const void *U64, const int *nbr, void *r, int ru_mode,
-                       const Red &rd, const CgState &cs);
+                       const double *x64, const void *xlo, const void *p, int pend, const void *U64,
+                       const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs);
 void launch_displaced_dot(const Launch &L, const ProbeGen &g, int p, const double *x64, const Red &rd,
                           const CgState &cs);
 void launch_dot(const Launch &L, const double *a64, const double *b64, const Red &rd,

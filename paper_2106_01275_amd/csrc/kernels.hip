@@ -56,6 +56,7 @@ struct St<double2> {
     __device__ static __forceinline__ void st(double2 *__restrict__ a, size_t i, R re, R im) {
         a[i] = make_double2(re, im);
     }
+    __device__ static __forceinline__ void round(R &, R &) {}
 };
 
 template <>
@@ -69,6 +70,7 @@ struct St<float2> {
     __device__ static __forceinline__ void st(float2 *__restrict__ a, size_t i, R re, R im) {
         a[i] = make_float2(re, im);
     }
+    __device__ static __forceinline__ void round(R &, R &) {}
 };
 
 template <>
@@ -83,6 +85,11 @@ struct St<bf16x2> {
         bf16x2 o;
         o.v = f32_to_bf16(re) | (f32_to_bf16(im) << 16);
         a[i] = o;
+    }
+    // the value a store followed by a load would give
+    __device__ static __forceinline__ void round(R &re, R &im) {
+        re = __uint_as_float(f32_to_bf16(re) << 16);
+        im = __uint_as_float(f32_to_bf16(im) << 16);
     }
 };
 
@@ -100,6 +107,57 @@ __device__ __forceinline__ void tile_range(int ntiles, int &t0, int &t1) {
     const int lb = logical_block(), n = gridDim.x;
     t0 = (int)(((long long)lb * ntiles) / n);
     t1 = (int)(((long long)(lb + 1) * ntiles) / n);
+}
+
+// Site traversal of the stencil kernels.  XCD x (workgroups with
+// blockIdx % 8 == x) owns the x0-slices [x*D0/8, (x+1)*D0/8) when D0 is a
+// multiple of 8 (otherwise one eighth of the site range); its workgroups
+// walk the slab in steps, all together: step k covers consecutive work
+// items, item w mapping to site (x0_lo + w % n0) * V3 + w / n0 (x0
+// varies fastest).  The sites in flight then form a compact window whose
+// neighbours (x0 ones included) are read at nearly the same time, so they
+// hit in the XCD's L2.
+struct SiteWalk {
+    int items;      // work items of this XCD
+    int n0, x0_lo;  // x0-slices of the slab (n0 == 0: plain range)
+    int base;       // first site (plain range)
+    int V3;         // sites per x0-slice
+    int first, stride;  // first tile of this workgroup and tile stride
+};
+
+__device__ __forceinline__ SiteWalk site_walk(const Lat &lat) {
+    SiteWalk w;
+    const int nb = gridDim.x, b = blockIdx.x;
+    w.V3 = lat.D[1] * lat.D[2] * lat.D[3];
+    if (nb >= 8 && nb % 8 == 0) {
+        const int x = b % 8;
+        w.first = b / 8;
+        w.stride = nb / 8;
+        if (lat.D[0] % 8 == 0) {
+            w.n0 = lat.D[0] / 8;
+            w.x0_lo = x * w.n0;
+            w.items = w.n0 * w.V3;
+            w.base = 0;
+        } else {
+            w.n0 = 0;
+            w.x0_lo = 0;
+            w.base = (int)(((long long)x * lat.N) / 8);
+            w.items = (int)(((long long)(x + 1) * lat.N) / 8) - w.base;
+        }
+    } else {
+        w.first = b;
+        w.stride = nb;
+        w.n0 = 0;
+        w.x0_lo = 0;
+        w.base = 0;
+        w.items = lat.N;
+    }
+    return w;
+}
+
+__device__ __forceinline__ int walk_site(const SiteWalk &w, int item) {
+    if (w.n0 == 0) return w.base + item;
+    return (w.x0_lo + item % w.n0) * w.V3 + item / w.n0;
 }
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
@@ -352,101 +410,159 @@ __global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const dou
 // q = A p for one block of right-hand sides; with CG, also p^H q per lane
 // and, in the finishing workgroup, alpha = rr / p^H q.
 // STAGE: links of the tile's sites staged in LDS (W >= 16).
-template <typename S, typename LS, int NC, bool LINKS, bool STAGE>
-__global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ p,
+// ------------------------------------------------------------ stencil helpers
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
+
+// colour components of lane j at site y; `row` arithmetic is uniform when y is
+// (32-bit lane offsets from a row base: with a uniform y the base stays in
+// scalar registers and the loads use the scalar-base + offset form)
+template <typename S, int NC>
+__device__ __forceinline__ void ld_site(const S *__restrict__ v, int y, int logW, int j,
+                                        typename St<S>::R (&re)[NC], typename St<S>::R (&im)[NC]) {
+    const S *row = v + ((size_t)(y * NC) << logW);
+#pragma unroll
+    for (int b = 0; b < NC; ++b) St<S>::ld(row, (unsigned)((b << logW) + j), re[b], im[b]);
+}
+
+// acc -= U v (DAG = false) or acc -= U^H v (DAG = true), u = 3x3 (or 1x1)
+// complex matrix as (re, im) pairs in row-major order; four FMAs per
+// complex multiply-subtract.
+template <typename R, int NC, bool DAG>
+__device__ __forceinline__ void mul_sub(const R *u, const R (&vr)[NC], const R (&vi)[NC], R (&ar)[NC], R (&ai)[NC]) {
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+            const int e = DAG ? b * NC + a : a * NC + b;
+            const R ur = u[2 * e];
+            const R ui = DAG ? -u[2 * e + 1] : u[2 * e + 1];
+            ar[a] = fmaR(-ur, vr[b], ar[a]);
+            ar[a] = fmaR(ui, vi[b], ar[a]);
+            ai[a] = fmaR(-ur, vi[b], ai[a]);
+            ai[a] = fmaR(-ui, vr[b], ai[a]);
+        }
+    }
+}
+
+// link U_mu(src) converted to the compute precision
+template <typename LS, typename R, int NC>
+__device__ __forceinline__ void ld_link(const LS *__restrict__ U, int src, int mu, R *u) {
+    const LS *base = U + ((size_t)src * 4 + mu) * NC * NC;
+#pragma unroll
+    for (int e = 0; e < NC * NC; ++e) {
+        typename St<LS>::R re, im;
+        St<LS>::ld(base, e, re, im);
+        u[2 * e] = (R)re;
+        u[2 * e + 1] = (R)im;
+    }
+}
+
+// The stencil q = A p for one block of right-hand sides, with p^H q summed
+// per lane when `cg` is set (the first kernel of a CG iteration).
+//
+// MODE 0 (W < 16): every lane loads its site's links itself (the lanes of a
+// site read the same addresses).  MODE 1 (16 <= W < 64): the links of the
+// tile's sites are staged in LDS once and shared by the W lanes.  MODE 2
+// (W >= 64): a wavefront covers one site, so the site index is uniform and
+// the links and neighbour indices come through scalar loads; no LDS and no
+// barriers.  In every mode the vector loads of the site and its eight
+// neighbours are issued before any arithmetic, so they are in flight
+// together.
+template <typename S, typename LS, int NC, bool LINKS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ pin,
                                                     S *__restrict__ q, const LS *__restrict__ U,
-                                                    const int *__restrict__ nbr, int cg, Red rd, CgState cs) {
+                                                    const int *__restrict__ nbr, int cg, Red rd) {
     using R = typename St<S>::R;
+    constexpr bool STAGE = MODE == 1 && LINKS;
     constexpr int kMaxSites = kBlock / 16;
     __shared__ R su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
-    __shared__ int snb[STAGE ? kMaxSites * 8 : 1];
+    __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
     __shared__ double sm[kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
-    const int j = tid & (W - 1), sl = tid >> logW;
+    const int j = tid & (W - 1);
+    const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
-    const int N = L.lat.N;
-    double acc_pq[1] = {0.0};
-    int t0, t1;
-    tile_range(L.ntiles, t0, t1);
-    for (int t = t0; t < t1; ++t) {
-        const int site0 = t * sites_per_tile;
-        const int site = site0 + sl;
-        if (STAGE) {
+    double acc_pq = 0.0;
+    const SiteWalk wk = site_walk(L.lat);
+    for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
+        const int item0 = t * sites_per_tile;
+        if (MODE == 1) {
             __syncthreads();
-            const int ne = sites_per_tile * 8 * NC * NC;
-            for (int e = tid; e < ne; e += kBlock) {
-                const int s_l = e / (8 * NC * NC);
-                const int rem = e - s_l * 8 * NC * NC;
-                const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
-                const int gs = site0 + s_l;
-                R re = 0, im = 0;
-                if (LINKS && gs < N) {
-                    const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
-                    St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, re, im);
+            if (STAGE) {
+                const int ne = sites_per_tile * 8 * NC * NC;
+                for (int e = tid; e < ne; e += kBlock) {
+                    const int s_l = e / (8 * NC * NC);
+                    const int rem = e - s_l * 8 * NC * NC;
+                    const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
+                    typename St<LS>::R re = 0, im = 0;
+                    if (item0 + s_l < wk.items) {
+                        const int gs = walk_site(wk, item0 + s_l);
+                        const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
+                        St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, re, im);
+                    }
+                    su[2 * e] = (R)re;
+                    su[2 * e + 1] = (R)im;
                 }
-                su[2 * e] = re;
-                su[2 * e + 1] = im;
             }
-            for (int e = tid; e < sites_per_tile * 8; e += kBlock) {
-                const int gs = site0 + e / 8;
-                snb[e] = gs < N ? nbr[site0 * 8 + e] : 0;
-            }
+            for (int e = tid; e < sites_per_tile * 8; e += kBlock)
+                snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
             __syncthreads();
         }
-        if (site >= N) continue;
-        R ar[NC], ai[NC], pr[NC], pi[NC];
+        if (item0 + sl >= wk.items) continue;
+        const int site = walk_site(wk, item0 + sl);
+        int y[9];
+        y[0] = site;
+#pragma unroll
+        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
+        R vr[9][NC], vi[9][NC];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ld_site<S, NC>(pin, y[k], logW, j, vr[k], vi[k]);
+        R ar[NC], ai[NC];
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            St<S>::ld(p, ((size_t)(site * NC + a) << logW) + j, pr[a], pi[a]);
-            ar[a] = diag * pr[a];
-            ai[a] = diag * pi[a];
+            ar[a] = diag * vr[0][a];
+            ai[a] = diag * vi[0][a];
         }
 #pragma unroll
         for (int dir = 0; dir < 8; ++dir) {
-            const int y = STAGE ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
-            R vr[NC], vi[NC];
-#pragma unroll
-            for (int b = 0; b < NC; ++b) St<S>::ld(p, ((size_t)(y * NC + b) << logW) + j, vr[b], vi[b]);
             if (!LINKS) {
 #pragma unroll
                 for (int a = 0; a < NC; ++a) {
-                    ar[a] -= vr[a];
-                    ai[a] -= vi[a];
+                    ar[a] -= vr[dir + 1][a];
+                    ai[a] -= vi[dir + 1][a];
                 }
                 continue;
             }
+            R u[2 * NC * NC];
+            if (STAGE) {
 #pragma unroll
-            for (int a = 0; a < NC; ++a) {
-#pragma unroll
-                for (int b = 0; b < NC; ++b) {
-                    // forward: U_mu(x)[a][b];  backward: conj(U_mu(x-mu)[b][a])
-                    const int ab = dir < 4 ? a * NC + b : b * NC + a;
-                    R ur, ui;
-                    if (STAGE) {
-                        const int e = (sl * 8 + dir) * NC * NC + ab;
-                        ur = su[2 * e];
-                        ui = su[2 * e + 1];
-                    } else {
-                        const int src = dir < 4 ? site : y;
-                        St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, ur, ui);
-                    }
-                    if (dir >= 4) ui = -ui;
-                    ar[a] -= ur * vr[b] - ui * vi[b];
-                    ai[a] -= ur * vi[b] + ui * vr[b];
-                }
+                for (int e = 0; e < 2 * NC * NC; ++e) u[e] = su[(sl * 8 + dir) * NC * NC * 2 + e];
+            } else {
+                ld_link<LS, R, NC>(U, dir < 4 ? site : y[dir + 1], dir & 3, u);
             }
+            if (dir < 4)
+                mul_sub<R, NC, false>(u, vr[dir + 1], vi[dir + 1], ar, ai);
+            else
+                mul_sub<R, NC, true>(u, vr[dir + 1], vi[dir + 1], ar, ai);
         }
+        S *qrow = q + ((size_t)(site * NC) << logW);
+        R pqs = 0;
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            St<S>::st(q, ((size_t)(site * NC + a) << logW) + j, ar[a], ai[a]);
-            acc_pq[0] += (double)pr[a] * (double)ar[a] + (double)pi[a] * (double)ai[a];
+            St<S>::st(qrow, (unsigned)((a << logW) + j), ar[a], ai[a]);
+            pqs = fmaR(vr[0][a], ar[a], fmaR(vi[0][a], ai[a], pqs));
         }
+        acc_pq += (double)pqs;
     }
     if (!cg) return;
-    block_partials<1>(acc_pq, W, logW, rd, sm);
+    double acc[1] = {acc_pq};
+    block_partials<1>(acc, W, logW, rd, sm);
 }
 
-// x += alpha p; r -= alpha q; |r|^2 per lane; epilogue: beta, convergence.
+// x += alpha p, r -= alpha q and |r|^2 per lane (second kernel of a CG
+// iteration).
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xlo, const S *__restrict__ p,
                                                     S *__restrict__ r, const S *__restrict__ q, Red rd,
@@ -454,38 +570,42 @@ __global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xl
     using R = typename St<S>::R;
     __shared__ double sm[kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
-    const int j = tid & (W - 1), sl = tid >> logW;
+    const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> logW;
-    const int nc = L.nc;
     const R alpha = (R)cs.alpha[j];
     double acc[1] = {0.0};
     int t0, t1;
     tile_range(L.ntiles, t0, t1);
-    const size_t e0 = (size_t)t0 * sites_per_tile * nc * W;
-    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * nc * W;
     // element e = ((site * nc + a) << logW) + j: lane j is tid & (W-1) for
     // every e = e0 + tid + k * kBlock since kBlock is a multiple of W
+    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
+    R part = 0;
+    int cnt = 0;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
-        (void)sl;
         R xr, xi, pr, pi, rr_, ri, qr, qi;
         St<S>::ld(xlo, e, xr, xi);
         St<S>::ld(p, e, pr, pi);
         St<S>::ld(r, e, rr_, ri);
         St<S>::ld(q, e, qr, qi);
-        xr += alpha * pr;
-        xi += alpha * pi;
-        rr_ -= alpha * qr;
-        ri -= alpha * qi;
-        St<S>::st(xlo, e, xr, xi);
+        St<S>::st(xlo, e, fmaR(alpha, pr, xr), fmaR(alpha, pi, xi));
+        rr_ = fmaR(-alpha, qr, rr_);
+        ri = fmaR(-alpha, qi, ri);
         St<S>::st(r, e, rr_, ri);
-        // the stored (rounded) residual is what the next iteration uses
-        St<S>::ld(r, e, rr_, ri);
-        acc[0] += (double)rr_ * rr_ + (double)ri * ri;
+        // the next iteration uses the stored (rounded) residual
+        St<S>::round(rr_, ri);
+        part = fmaR(rr_, rr_, fmaR(ri, ri, part));
+        if (++cnt == 24) {
+            acc[0] += (double)part;
+            part = 0;
+            cnt = 0;
+        }
     }
+    acc[0] += (double)part;
     block_partials<1>(acc, W, logW, rd, sm);
 }
 
-// p = r + beta p
+// p = r + beta p (third kernel of a CG iteration)
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restrict__ r, S *__restrict__ p,
                                                     CgState cs) {
@@ -502,11 +622,11 @@ __global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restric
         R rr_, ri, pr, pi;
         St<S>::ld(r, e, rr_, ri);
         St<S>::ld(p, e, pr, pi);
-        St<S>::st(p, e, rr_ + beta * pr, ri + beta * pi);
+        St<S>::st(p, e, fmaR(beta, pr, rr_), fmaR(beta, pi, ri));
     }
 }
 
-// x64 += xlo; xlo = 0
+// x64 += xlo, xlo = 0 (mixed precision)
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
     using R = typename St<S>::R;
@@ -527,65 +647,81 @@ __global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__
     }
 }
 
-// FP64 true residual r = b - A x (FP64 links); stores r in the storage
-// precision and |r|^2 per lane.  ru_mode 1 (reliable update): the residual
-// replaces the recursive one, beta is recomputed from it and lanes whose
-// true residual meets tol are retired.  ru_mode 0: statistics only.
-template <typename S, int NC, bool LINKS>
+// FP64 true residual r = b - A x_eff with FP64 links, x_eff = x64 (pend = 0)
+// or x64 + xlo + alpha p (pend = 1: the solution including the inner
+// iterate and the pending update, formed on the fly).  Stores r in the
+// storage precision and |r|^2 per lane.
+template <typename S, int NC, bool LINKS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
-                                                       const double2 *__restrict__ x64,
+                                                       const double2 *__restrict__ x64, const S *__restrict__ xlo,
+                                                       const S *__restrict__ p, int pend,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
-                                                       S *__restrict__ rout, int ru_mode, Red rd, CgState cs) {
+                                                       S *__restrict__ rout, Red rd, CgState cs) {
     __shared__ double sm[kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
-    const int j = tid & (W - 1), sl = tid >> logW;
+    const int j = tid & (W - 1);
+    const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
+    const double alpha = pend ? cs.alpha[j] : 0.0;
     double acc[1] = {0.0};
-    int t0, t1;
-    tile_range(L.ntiles, t0, t1);
-    for (int t = t0; t < t1; ++t) {
-        const int site = t * sites_per_tile + sl;
-        if (site >= L.lat.N) continue;
+    const SiteWalk wk = site_walk(L.lat);
+    auto xeff = [&](int y, double (&vr)[NC], double (&vi)[NC]) {
+        ld_site<double2, NC>(x64, y, logW, j, vr, vi);
+        if (pend) {
+            typename St<S>::R lr[NC], li[NC], qr[NC], qi[NC];
+            ld_site<S, NC>(xlo, y, logW, j, lr, li);
+            ld_site<S, NC>(p, y, logW, j, qr, qi);
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                vr[b] += (double)lr[b] + alpha * (double)qr[b];
+                vi[b] += (double)li[b] + alpha * (double)qi[b];
+            }
+        }
+    };
+    for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
+        if (t * sites_per_tile + sl >= wk.items) continue;
+        const int site = walk_site(wk, t * sites_per_tile + sl);
         double ar[NC], ai[NC];
+        {
+            double vr[NC], vi[NC], br[NC], bi[NC];
+            xeff(site, vr, vi);
+            ld_site<double2, NC>(b64, site, logW, j, br, bi);
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                ar[a] = fma(-diag, vr[a], br[a]);
+                ai[a] = fma(-diag, vi[a], bi[a]);
+            }
+        }
+        // r = b - diag x + sum of hops: accumulate with the sign flipped
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            const size_t i = ((size_t)(site * NC + a) << logW) + j;
-            const double2 xv = x64[i], bv = b64[i];
-            ar[a] = bv.x - diag * xv.x;
-            ai[a] = bv.y - diag * xv.y;
+            ar[a] = -ar[a];
+            ai[a] = -ai[a];
         }
 #pragma unroll
         for (int dir = 0; dir < 8; ++dir) {
             const int y = nbr[site * 8 + dir];
             double vr[NC], vi[NC];
+            xeff(y, vr, vi);
+            if (!LINKS) {
 #pragma unroll
-            for (int b = 0; b < NC; ++b) {
-                const double2 v = x64[((size_t)(y * NC + b) << logW) + j];
-                vr[b] = v.x;
-                vi[b] = v.y;
-            }
-#pragma unroll
-            for (int a = 0; a < NC; ++a) {
-                if (!LINKS) {
-                    ar[a] += vr[a];
-                    ai[a] += vi[a];
-                    continue;
+                for (int a = 0; a < NC; ++a) {
+                    ar[a] -= vr[a];
+                    ai[a] -= vi[a];
                 }
-#pragma unroll
-                for (int b = 0; b < NC; ++b) {
-                    const int src = dir < 4 ? site : y;
-                    const int ab = dir < 4 ? a * NC + b : b * NC + a;
-                    const double2 u = U[((size_t)src * 4 + (dir & 3)) * NC * NC + ab];
-                    const double ui = dir < 4 ? u.y : -u.y;
-                    ar[a] += u.x * vr[b] - ui * vi[b];
-                    ai[a] += u.x * vi[b] + ui * vr[b];
-                }
+                continue;
             }
+            double u[2 * NC * NC];
+            ld_link<double2, double, NC>(U, dir < 4 ? site : y, dir & 3, u);
+            if (dir < 4)
+                mul_sub<double, NC, false>(u, vr, vi, ar, ai);
+            else
+                mul_sub<double, NC, true>(u, vr, vi, ar, ai);
         }
+        S *rrow = rout + ((size_t)(site * NC) << logW);
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            const size_t i = ((size_t)(site * NC + a) << logW) + j;
-            St<S>::st(rout, i, (typename St<S>::R)ar[a], (typename St<S>::R)ai[a]);
+            St<S>::st(rrow, ((size_t)a << logW) + j, (typename St<S>::R)(-ar[a]), (typename St<S>::R)(-ai[a]));
             acc[0] += ar[a] * ar[a] + ai[a] * ai[a];
         }
     }
@@ -806,45 +942,46 @@ void launch_init_abi(const Launch &L, int prec, const double *babi, long long rh
     k_finish<1, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
-template <typename S, typename LS>
-static void stencil_t(const Launch &L, bool links, double diag, const void *p, void *q, const void *U,
-                      const int *nbr, bool cg, const Red &rd, const CgState &cs) {
+template <typename S, typename LS, int NC, bool LINKS>
+static void stencil_nc(const Launch &L, const StencilArgs &a) {
     using R = typename St<S>::R;
-    const bool stage = L.W >= 16;
-    const S *pp = (const S *)p;
-    S *qq = (S *)q;
-    const LS *uu = (const LS *)U;
     dim3 grid(L.nblk), blk(kBlock);
+    const S *pin = (const S *)a.pin;
+    S *q = (S *)a.q;
+    const LS *U = (const LS *)a.U;
+#define DP_ST(M) k_stencil<S, LS, NC, LINKS, M><<<grid, blk, 0, L.stream>>>(L, (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd)
+    if (L.W >= 64)
+        DP_ST(2);
+    else if (L.W >= 16)
+        DP_ST(1);
+    else
+        DP_ST(0);
+#undef DP_ST
+}
+
+template <typename S, typename LS>
+static void stencil_t(const Launch &L, const StencilArgs &a) {
     if (L.nc == 3) {
-        if (links) {
-            if (stage)
-                k_stencil<S, LS, 3, true, true><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
-            else
-                k_stencil<S, LS, 3, true, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
-        } else {
-            k_stencil<S, LS, 3, false, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
-        }
+        if (a.links)
+            stencil_nc<S, LS, 3, true>(L, a);
+        else
+            stencil_nc<S, LS, 3, false>(L, a);
     } else {
-        if (links) {
-            if (stage)
-                k_stencil<S, LS, 1, true, true><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
-            else
-                k_stencil<S, LS, 1, true, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
-        } else {
-            k_stencil<S, LS, 1, false, false><<<grid, blk, 0, L.stream>>>(L, (R)diag, pp, qq, uu, nbr, cg, rd, cs);
-        }
+        if (a.links)
+            stencil_nc<S, LS, 1, true>(L, a);
+        else
+            stencil_nc<S, LS, 1, false>(L, a);
     }
 }
 
-void launch_stencil(const Launch &L, int prec, bool links, double diag, const void *p, void *q, const void *U,
-                    const int *nbr, bool cg, const Red &rd, const CgState &cs) {
+void launch_stencil(const Launch &L, int prec, const StencilArgs &a) {
     if (prec == kF64)
-        stencil_t<double2, double2>(L, links, diag, p, q, U, nbr, cg, rd, cs);
+        stencil_t<double2, double2>(L, a);
     else if (prec == kF32)
-        stencil_t<float2, float2>(L, links, diag, p, q, U, nbr, cg, rd, cs);
+        stencil_t<float2, float2>(L, a);
     else
-        stencil_t<bf16x2, bf16x2>(L, links, diag, p, q, U, nbr, cg, rd, cs);
-    if (cg) k_finish<1, kEpiAlpha><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+        stencil_t<bf16x2, bf16x2>(L, a);
+    if (a.cg) k_finish<1, kEpiAlpha><<<L.W, kBlock, 0, L.stream>>>(a.rd, a.cs);
 }
 
 void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r, const void *q, const Red &rd,
@@ -864,21 +1001,29 @@ void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {
 }
 
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64, const double *x64,
-                       const void *U64, const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs) {
+                       const void *xlo, const void *p, int pend, const void *U64, const int *nbr, void *r,
+                       int ru_mode, const Red &rd, const CgState &cs) {
     const double2 *b = (const double2 *)b64, *x = (const double2 *)x64, *u = (const double2 *)U64;
+#define DP_TR(NC_, LK_, M_)                                                                                  \
+    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, (const S *)xlo, (const S *)p, \
+                                                                   pend, u, nbr, (S *)r, rd, cs)
     DP_DISPATCH_PREC(prec, S, {
+        const bool wu = L.W >= 64;
         if (L.nc == 3) {
-            if (links)
-                k_true_resid<S, 3, true><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
-            else
-                k_true_resid<S, 3, false><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
+            if (links) {
+                if (wu) DP_TR(3, true, 2); else DP_TR(3, true, 0);
+            } else {
+                if (wu) DP_TR(3, false, 2); else DP_TR(3, false, 0);
+            }
         } else {
-            if (links)
-                k_true_resid<S, 1, true><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
-            else
-                k_true_resid<S, 1, false><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, ru_mode, rd, cs);
+            if (links) {
+                if (wu) DP_TR(1, true, 2); else DP_TR(1, true, 0);
+            } else {
+                if (wu) DP_TR(1, false, 2); else DP_TR(1, false, 0);
+            }
         }
     });
+#undef DP_TR
     if (ru_mode)
         k_finish<1, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
     else

@@ -147,8 +147,7 @@ static dp_status read_ctrl(dp_ctx *ctx, const CgState &cs, int W, hipStream_t s)
     return DP_OK;
 }
 
-static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L, const OpPrep &op,
-                               const Red &rd, const CgState &cs) {
+static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L, const StencilArgs &a) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (cfg.profile) {
         if (ctx->ev_pool.size() < 2) {
@@ -164,8 +163,7 @@ static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L
         ctx->ev_pool.pop_back();
         DP_HIP(hipEventRecord(e0, L.stream));
     }
-    launch_stencil(L, cfg.inner, op.links, op.m2 + 8.0, ctx->at(kSlotP), ctx->at(kSlotQ), op.ULo, op.nbr, true, rd,
-                   cs);
+    launch_stencil(L, cfg.inner, a);
     if (cfg.profile) {
         DP_HIP(hipEventRecord(e1, L.stream));
         ctx->ev_pending.emplace_back(e0, e1);
@@ -199,18 +197,29 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     void *xlo = mixed ? ctx->at(kSlotXLo) : (void *)x64;
     void *r = ctx->at(kSlotR), *p = ctx->at(kSlotP), *q = ctx->at(kSlotQ);
     const double *b64 = (const double *)ctx->at(kSlotB64);
-    init(xlo, x64);
+    const double diag = op.m2 + 8.0;
+    init(xlo, x64);  // b, r = p = b, xlo = 0 (x64 = 0)
     DP_HIP(hipGetLastError());
     DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
     int nactive = ctx->ctrl_host[0];
     int it = 0;
-    bool pending = false;
+    bool pending = false;  // p = r + beta p not yet applied
+    StencilArgs a;
+    a.links = op.links;
+    a.diag = diag;
+    a.pin = p;
+    a.q = q;
+    a.U = op.ULo;
+    a.nbr = op.nbr;
+    a.cg = 1;
+    a.rd = rd;
+    a.cs = cs;
     const int check = std::max(1, ctx->check_every);
     while (nactive > 0 && it < cfg.max_iter) {
         const int steps = std::min(check, cfg.max_iter - it);
         for (int c = 0; c < steps; ++c) {
             if (pending) launch_update2(L, cfg.inner, r, p, cs);
-            DP_TRY(timed_stencil(ctx, cfg, L, op, rd, cs));
+            DP_TRY(timed_stencil(ctx, cfg, L, a));
             launch_update1(L, cfg.inner, xlo, p, r, q, rd, cs);
             pending = true;
         }
@@ -220,8 +229,10 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
         nactive = ctx->ctrl_host[0];
         if (mixed && nactive > 0 &&
             (ctx->ctrl_host[2] > 0 || ctx->ctrl_host[1] == nactive || it >= cfg.max_iter)) {
+            // reliable update: x64 += xlo, r = b - A x64 in FP64, beta from it
             launch_fold(L, cfg.inner, x64, xlo);
-            launch_true_resid(L, cfg.inner, op.links, op.m2 + 8.0, b64, x64, op.U64, op.nbr, r, 1, rd, cs);
+            launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, nullptr, nullptr, 0, op.U64, op.nbr, r, 1,
+                              rd, cs);
             DP_HIP(hipGetLastError());
             ++bs.ru;
             DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
@@ -230,7 +241,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     }
     if (mixed) launch_fold(L, cfg.inner, x64, xlo);
     // final FP64 true residual (statistics only)
-    launch_true_resid(L, cfg.inner, op.links, op.m2 + 8.0, b64, x64, op.U64, op.nbr, r, 0, rd, cs);
+    launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, nullptr, nullptr, 0, op.U64, op.nbr, r, 0, rd, cs);
     DP_HIP(hipGetLastError());
     const int W = L.W;
     double *h = ctx->state_host;
