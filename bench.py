@@ -42,9 +42,13 @@ def parse():
     ap.add_argument("--rhs-block", type=int, default=32)
     ap.add_argument("--inner", default="f32")
     ap.add_argument("--delta", type=float, default=1e-3, help="reliable-update residual drop")
+    ap.add_argument("--graph", type=int, default=0, help="replay CG iteration groups from hipGraphs")
+    ap.add_argument("--profile", type=int, default=1, help="time the stencil launches with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-rhs", type=int, default=0, help="right-hand sides in the CPU sample (0: cores)")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (reference for byte counters)")
     return ap.parse_args()
 
 
@@ -80,9 +84,10 @@ def main():
     Ug = torch.from_numpy(U).cuda()
     colg = torch.from_numpy(col).cuda()
     op = c.operator(dims, nc, w.m2, Ug)
-    opts = c.opts(tol=w.tol, inner=a.inner, rhs_block=a.rhs_block, reliable_delta=a.delta, profile=1)
+    opts = c.opts(tol=w.tol, inner=a.inner, rhs_block=a.rhs_block, reliable_delta=a.delta, profile=1,
+                  use_graph=a.graph)
 
-    def step(sample, prof=1):
+    def step(sample, prof=a.profile):
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, sample, 1, "z2_complex", True)
         opts.profile = prof
         return c.trace_estimate([op], [ps], [p], opts)[0]
@@ -108,10 +113,10 @@ def main():
     lbytes = {"f64": 16, "f32": 8, "bf16": 4}[a.inner] * nc * nc  # per link
     alg_bytes = N * (2 * vbytes * W + 4 * lbytes)                 # read p, write q, links once
     avg_s = st_ms / 1e3 / max(launches, 1)
-    achieved = alg_bytes / avg_s / 1e9
+    achieved = alg_bytes / avg_s / 1e9 if launches else None
 
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "stencil_gauge16_f32_w64_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", f"stencil_gauge16_{a.inner}_w{W}_traffic.json")
     if os.path.exists(tfile):
         t = json.load(open(tfile))
         if t.get("kernels_hip_sha") == kernel_sha() and t.get("rhs_block") == W and t.get("inner") == a.inner:
@@ -181,7 +186,7 @@ def main():
                    "rhs_per_step": nrhs // a.steps, "rhs_block": W, "inner": a.inner,
                    "colours": [int(v) for v in ncols], "coloring_seconds": t_color},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                      "kernel": "k_stencil (q = A p, p^H q)", "launches": launches,
                      "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
@@ -191,6 +196,14 @@ def main():
                   "reliable_updates": sum(r["solve"]["reliable_updates"] for r in res),
                   "max_true_resid": max(r["solve"]["max_true_resid"] for r in res)},
     }
+    if a.copy_ref_mib:
+        # a plain copy kernel of known size: reads and writes copy_ref_mib MiB
+        src = torch.ones(a.copy_ref_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_ref_mib"] = a.copy_ref_mib
     print(json.dumps(out), flush=True)
 
 

@@ -41,6 +41,7 @@ dp_status solve_cfg(dp_ctx *ctx, const dp_solve_opts *o, SolveCfg &c) {
     c.inner = o->inner;
     c.delta = o->reliable_delta > 0 ? o->reliable_delta : 0.1;
     c.profile = o->profile;
+    c.use_graph = o->use_graph;
     if (!(c.tol > 0) || !(c.delta < 1)) {
         ctx->err = "tol must be > 0 and reliable_delta < 1";
         return DP_EINVAL;
@@ -138,6 +139,10 @@ void dp_destroy(dp_ctx *ctx) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
+    ctx->drop_graphs();
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->ctrl_host) (void)hipHostFree(ctx->ctrl_host);
     if (ctx->state_host) (void)hipHostFree(ctx->state_host);
     delete ctx;
@@ -192,6 +197,13 @@ dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, con
     }
     SolveCfg cfg;
     DP_TRY(solve_cfg(ctx, o, cfg));
+    WorkStream ws_;
+    DP_TRY(ws_.enter(ctx, stream, cfg.use_graph));
+    struct Leave {
+        WorkStream &w;
+        ~Leave() { (void)w.leave(); }
+    } leave_{ws_};
+    stream = ws_.s;
     dp_status worst = DP_OK;
     for (int i = 0; i < ninst; ++i) {
         const double t0 = now_s();
@@ -302,6 +314,13 @@ dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, 
     }
     SolveCfg cfg;
     DP_TRY(solve_cfg(ctx, o, cfg));
+    WorkStream ws_;
+    DP_TRY(ws_.enter(ctx, stream, cfg.use_graph));
+    struct Leave {
+        WorkStream &w;
+        ~Leave() { (void)w.leave(); }
+    } leave_{ws_};
+    stream = ws_.s;
     dp_status worst = DP_OK;
     for (int i = 0; i < ninst; ++i) {
         dp_status s = trace_one(ctx, ops[i], p[i], ps[i], o, cfg, out[i], stream);
@@ -325,6 +344,14 @@ dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *opd, int32_t p, const dp
     SolveCfg cfg;
     DP_TRY(solve_cfg(ctx, o, cfg));
     DP_TRY(check_spec(ctx, *ps, opd));
+    WorkStream ws_;
+    DP_TRY(ws_.enter(ctx, stream, cfg.use_graph));
+    struct Leave {
+        WorkStream &w;
+        ~Leave() { (void)w.leave(); }
+    } leave_{ws_};
+    stream = ws_.s;
+
     OpPrep op;
     DP_TRY(prepare_operator(ctx, *opd, cfg.inner, op, stream));
     const int ndil = ps->dilute ? ps->nc : 1;

@@ -62,6 +62,11 @@ struct dp_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     std::map<std::string, int> tuned_w;
     int check_every = 8;
+    hipStream_t gstream = nullptr;            // library stream for graph capture
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::map<int, hipGraphExec_t> graphs;     // iteration groups by length (one solve)
+
+    void drop_graphs();
 
     dp_status ensure(int s, size_t bytes, bool zero = false);
     void *at(int s) const { return slot[s]; }
@@ -70,6 +75,7 @@ struct dp_ctx {
 namespace dp {
 
 struct SolveCfg {
+    int use_graph = 0;
     double tol = 1e-10;
     int max_iter = 100000;
     int inner = kF64;
@@ -89,6 +95,17 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
                        hipStream_t s, int &W);
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
+
+// Work stream of a call: the caller's stream, or (graph replay requested)
+// the library's own stream, ordered after the caller's stream on entry and
+// before it on exit.
+struct WorkStream {
+    dp_ctx *ctx;
+    hipStream_t user, s;
+    bool own = false;
+    dp_status enter(dp_ctx *c, hipStream_t u, bool graph);
+    dp_status leave();
+};
 
 // Initialisers of a block: probes generated on the device, or ABI vectors.
 struct InitProbe {

@@ -32,6 +32,7 @@ struct CgState {
     double *tj;          // [W][2] contraction results / dot products
     int *active, *iters, *flags;
     int *ctrl;           // [0] active, [1] candidates, [2] need reliable update, [3] breakdowns
+    double *ctrld;       // [0] max over active lanes of |r|^2 / (tol^2 |b|^2)
     double tol2, delta2;
     int exact;           // 1: FP64 inner solve (no reliable updates)
 };

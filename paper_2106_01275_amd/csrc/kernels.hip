@@ -316,21 +316,36 @@ __global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
 
 // Control word for the host: [0] active lanes, [1] active lanes whose
 // recursive residual meets tol, [2] active lanes due a reliable update,
-// [3] lanes that broke down.
+// [3] lanes that broke down; ctrld[0] the largest |r|^2 / (tol^2 |b|^2) of
+// an active lane (how far the slowest one still is from convergence).
 __global__ void k_ctrl(CgState cs, int W) {
-    if (threadIdx.x != 0) return;
+    __shared__ int cnt[4][64];
+    __shared__ double worst[64];
+    const int t = threadIdx.x;
     int na = 0, nk = 0, nru = 0, nb = 0;
-    for (int k = 0; k < W; ++k) {
+    double wr = 0.0;
+    for (int k = t; k < W; k += 64) {
         nb += (cs.flags[k] & kFlagBreakdown) ? 1 : 0;
         if (!cs.active[k]) continue;
         ++na;
-        if (cs.rr[k] <= cs.tol2 * cs.bb[k]) ++nk;
+        const double goal = cs.tol2 * cs.bb[k];
+        if (cs.rr[k] <= goal) ++nk;
         if (cs.rr[k] < cs.delta2 * cs.rr_ref[k]) ++nru;
+        wr = fmax(wr, cs.rr[k] / goal);
     }
-    cs.ctrl[0] = na;
-    cs.ctrl[1] = nk;
-    cs.ctrl[2] = nru;
-    cs.ctrl[3] = nb;
+    cnt[0][t] = na;
+    cnt[1][t] = nk;
+    cnt[2][t] = nru;
+    cnt[3][t] = nb;
+    worst[t] = wr;
+    __syncthreads();
+    if (t != 0) return;
+    for (int i = 1; i < 64; ++i) {
+        for (int c = 0; c < 4; ++c) cnt[c][0] += cnt[c][i];
+        worst[0] = fmax(worst[0], worst[i]);
+    }
+    for (int c = 0; c < 4; ++c) cs.ctrl[c] = cnt[c][0];
+    cs.ctrld[0] = worst[0];
 }
 
 // ============================================================ kernels
@@ -459,6 +474,35 @@ __device__ __forceinline__ void ld_link(const LS *__restrict__ U, int src, int m
     }
 }
 
+// Stages the links of the tile's sites (forward U_mu(x), backward
+// U_mu(x - mu)) and their neighbour indices in LDS, converted to the compute
+// precision R.  All threads of the workgroup call it; it ends with a barrier.
+template <typename LS, typename R, int NC, bool LINKS>
+__device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, int item0, int sites_per_tile,
+                                           const LS *__restrict__ U, const int *__restrict__ nbr) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if (LINKS) {
+        const int ne = sites_per_tile * 8 * NC * NC;
+        for (int e = tid; e < ne; e += kBlock) {
+            const int s_l = e / (8 * NC * NC);
+            const int rem = e - s_l * 8 * NC * NC;
+            const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
+            typename St<LS>::R re = 0, im = 0;
+            if (item0 + s_l < wk.items) {
+                const int gs = walk_site(wk, item0 + s_l);
+                const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
+                St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, re, im);
+            }
+            su[2 * e] = (R)re;
+            su[2 * e + 1] = (R)im;
+        }
+    }
+    for (int e = tid; e < sites_per_tile * 8; e += kBlock)
+        snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
+    __syncthreads();
+}
+
 // The stencil q = A p for one block of right-hand sides, with p^H q summed
 // per lane when `cg` is set (the first kernel of a CG iteration).
 //
@@ -488,28 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
     const SiteWalk wk = site_walk(L.lat);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
-        if (MODE == 1) {
-            __syncthreads();
-            if (STAGE) {
-                const int ne = sites_per_tile * 8 * NC * NC;
-                for (int e = tid; e < ne; e += kBlock) {
-                    const int s_l = e / (8 * NC * NC);
-                    const int rem = e - s_l * 8 * NC * NC;
-                    const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
-                    typename St<LS>::R re = 0, im = 0;
-                    if (item0 + s_l < wk.items) {
-                        const int gs = walk_site(wk, item0 + s_l);
-                        const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
-                        St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, re, im);
-                    }
-                    su[2 * e] = (R)re;
-                    su[2 * e + 1] = (R)im;
-                }
-            }
-            for (int e = tid; e < sites_per_tile * 8; e += kBlock)
-                snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
-            __syncthreads();
-        }
+        if (MODE == 1) stage_tile<LS, R, NC, LINKS>(su, snb, wk, item0, sites_per_tile, U, nbr);
         if (item0 + sl >= wk.items) continue;
         const int site = walk_site(wk, item0 + sl);
         int y[9];
@@ -657,6 +680,9 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, co
                                                        const S *__restrict__ p, int pend,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
                                                        S *__restrict__ rout, Red rd, CgState cs) {
+    constexpr int kMaxSites = kBlock / 16;
+    __shared__ double su[MODE == 1 && LINKS ? kMaxSites * 8 * NC * NC * 2 : 1];
+    __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
     __shared__ double sm[kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
@@ -679,6 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, co
         }
     };
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
+        if (MODE == 1) stage_tile<double2, double, NC, LINKS>(su, snb, wk, t * sites_per_tile, sites_per_tile, U, nbr);
         if (t * sites_per_tile + sl >= wk.items) continue;
         const int site = walk_site(wk, t * sites_per_tile + sl);
         double ar[NC], ai[NC];
@@ -700,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, co
         }
 #pragma unroll
         for (int dir = 0; dir < 8; ++dir) {
-            const int y = nbr[site * 8 + dir];
+            const int y = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
             double vr[NC], vi[NC];
             xeff(y, vr, vi);
             if (!LINKS) {
@@ -712,7 +739,12 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, co
                 continue;
             }
             double u[2 * NC * NC];
-            ld_link<double2, double, NC>(U, dir < 4 ? site : y, dir & 3, u);
+            if (MODE == 1) {
+#pragma unroll
+                for (int e = 0; e < 2 * NC * NC; ++e) u[e] = su[(sl * 8 + dir) * NC * NC * 2 + e];
+            } else {
+                ld_link<double2, double, NC>(U, dir < 4 ? site : y, dir & 3, u);
+            }
             if (dir < 4)
                 mul_sub<double, NC, false>(u, vr, vi, ar, ai);
             else
@@ -1008,18 +1040,18 @@ void launch_true_resid(const Launch &L, int prec, bool links, double diag, const
     k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, (const S *)xlo, (const S *)p, \
                                                                    pend, u, nbr, (S *)r, rd, cs)
     DP_DISPATCH_PREC(prec, S, {
-        const bool wu = L.W >= 64;
+        const int m = L.W >= 64 ? 2 : (L.W >= 16 ? 1 : 0);
         if (L.nc == 3) {
             if (links) {
-                if (wu) DP_TR(3, true, 2); else DP_TR(3, true, 0);
+                if (m == 2) DP_TR(3, true, 2); else if (m == 1) DP_TR(3, true, 1); else DP_TR(3, true, 0);
             } else {
-                if (wu) DP_TR(3, false, 2); else DP_TR(3, false, 0);
+                if (m == 2) DP_TR(3, false, 2); else if (m == 1) DP_TR(3, false, 1); else DP_TR(3, false, 0);
             }
         } else {
             if (links) {
-                if (wu) DP_TR(1, true, 2); else DP_TR(1, true, 0);
+                if (m == 2) DP_TR(1, true, 2); else if (m == 1) DP_TR(1, true, 1); else DP_TR(1, true, 0);
             } else {
-                if (wu) DP_TR(1, false, 2); else DP_TR(1, false, 0);
+                if (m == 2) DP_TR(1, false, 2); else if (m == 1) DP_TR(1, false, 1); else DP_TR(1, false, 0);
             }
         }
     });

@@ -43,7 +43,39 @@ dp_status dp_ctx::ensure(int s, size_t bytes, bool zero) {
     return DP_OK;
 }
 
+void dp_ctx::drop_graphs() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+}
+
 namespace dp {
+
+dp_status WorkStream::enter(dp_ctx *c, hipStream_t u, bool graph) {
+    ctx = c;
+    user = u;
+    s = u;
+    if (!graph) return DP_OK;
+    if (!ctx->gstream) {
+        DP_HIP(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+        DP_HIP(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+        DP_HIP(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    }
+    DP_HIP(hipEventRecord(ctx->ev_in, u));
+    DP_HIP(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+    s = ctx->gstream;
+    own = true;
+    ctx->drop_graphs();
+    return DP_OK;
+}
+
+dp_status WorkStream::leave() {
+    if (!own) return DP_OK;
+    own = false;
+    DP_HIP(hipEventRecord(ctx->ev_out, s));
+    DP_HIP(hipStreamWaitEvent(user, ctx->ev_out, 0));
+    ctx->drop_graphs();
+    return DP_OK;
+}
 
 static size_t prec_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
 
@@ -118,7 +150,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     DP_TRY(ctx->ensure(kSlotPart1, (size_t)L.nblk * W * 2 * sizeof(double)));
     rd.part1 = (double *)ctx->at(kSlotPart1);
     rd.nblk = L.nblk;
-    const size_t nd = 9 * kMaxW, ni = 3 * kMaxW + 8;
+    const size_t nd = 9 * kMaxW + 8, ni = 3 * kMaxW + 8;
     DP_TRY(ctx->ensure(kSlotState, nd * sizeof(double) + ni * sizeof(int)));
     double *d = (double *)ctx->at(kSlotState);
     cs.rr = d;
@@ -129,6 +161,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     cs.beta = d + 5 * kMaxW;
     cs.true_rr = d + 6 * kMaxW;
     cs.tj = d + 7 * kMaxW;
+    cs.ctrld = d + 9 * kMaxW;
     int *iv = (int *)(d + nd);
     cs.active = iv;
     cs.iters = iv + kMaxW;
@@ -143,6 +176,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
 static dp_status read_ctrl(dp_ctx *ctx, const CgState &cs, int W, hipStream_t s) {
     launch_ctrl(cs, W, s);
     DP_HIP(hipMemcpyAsync(ctx->ctrl_host, cs.ctrl, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    DP_HIP(hipMemcpyAsync(ctx->ctrl_host + 4, cs.ctrld, sizeof(double), hipMemcpyDeviceToHost, s));
     DP_HIP(hipStreamSynchronize(s));
     return DP_OK;
 }
@@ -214,19 +248,56 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     a.cg = 1;
     a.rd = rd;
     a.cs = cs;
-    const int check = std::max(1, ctx->check_every);
+    // Iterations between host checks: start with check_every, then predict
+    // from the decay of the slowest lane's residual since the last check.
+    int steps_next = std::max(1, ctx->check_every);
+    double ratio_prev = -1.0;
+    int it_prev = 0;
     while (nactive > 0 && it < cfg.max_iter) {
-        const int steps = std::min(check, cfg.max_iter - it);
-        for (int c = 0; c < steps; ++c) {
-            if (pending) launch_update2(L, cfg.inner, r, p, cs);
-            DP_TRY(timed_stencil(ctx, cfg, L, a));
-            launch_update1(L, cfg.inner, xlo, p, r, q, rd, cs);
-            pending = true;
+        const int steps = std::min(steps_next, cfg.max_iter - it);
+        if (cfg.use_graph && pending && !cfg.profile) {
+            // the group [update2, stencil, update1] x steps replayed from a graph
+            auto g = ctx->graphs.find(steps);
+            if (g == ctx->graphs.end()) {
+                hipGraph_t graph = nullptr;
+                hipGraphExec_t exec = nullptr;
+                DP_HIP(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal));
+                for (int c = 0; c < steps; ++c) {
+                    launch_update2(L, cfg.inner, r, p, cs);
+                    launch_stencil(L, cfg.inner, a);
+                    launch_update1(L, cfg.inner, xlo, p, r, q, rd, cs);
+                }
+                DP_HIP(hipStreamEndCapture(L.stream, &graph));
+                const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                DP_HIP(ie);
+                g = ctx->graphs.emplace(steps, exec).first;
+            }
+            DP_HIP(hipGraphLaunch(g->second, L.stream));
+        } else {
+            for (int c = 0; c < steps; ++c) {
+                if (pending) launch_update2(L, cfg.inner, r, p, cs);
+                DP_TRY(timed_stencil(ctx, cfg, L, a));
+                launch_update1(L, cfg.inner, xlo, p, r, q, rd, cs);
+                pending = true;
+            }
         }
         DP_HIP(hipGetLastError());
         it += steps;
         DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
         nactive = ctx->ctrl_host[0];
+        {
+            double ratio;
+            std::memcpy(&ratio, ctx->ctrl_host + 4, sizeof(double));
+            int next = std::max(1, ctx->check_every);
+            if (ratio_prev > 0 && ratio > 1.0 && ratio < ratio_prev && it > it_prev) {
+                const double per_it = std::log(ratio_prev / ratio) / (it - it_prev);
+                next = (int)std::ceil(std::log(ratio) / per_it);
+            }
+            steps_next = std::min(16, std::max(2, next));
+            ratio_prev = ratio;
+            it_prev = it;
+        }
         if (mixed && nactive > 0 &&
             (ctx->ctrl_host[2] > 0 || ctx->ctrl_host[1] == nactive || it >= cfg.max_iter)) {
             // reliable update: x64 += xlo, r = b - A x64 in FP64, beta from it

@@ -309,3 +309,29 @@ def test_autograd_function_matches_finite_differences(ctx):
     dUdt = cuda(1j * X @ U0)
     an = torch.sum((U.grad.conj() * dUdt).real).item()  # PyTorch: dL = Re<grad, dU>
     assert abs(fdU - an) < 1e-6 * max(1.0, abs(fdU)), (fdU, an)
+
+
+# ------------------------------------------------------------------ graphs
+
+
+def test_graph_replay_matches_eager(ctx):
+    """Iteration groups replayed from captured hipGraphs give bit-identical
+    results to eager launches, on every replay, with eager work between."""
+    dims, nc = (6, 4, 5, 4), 3
+    U = workloads.random_links(dims, 0.4, 21, nc)
+    col, n, colg, ps = _probe_setup(ctx, dims, nc, 1, 2, "natural", 5, 0, 2, "z2_complex", True)
+    op = ctx.operator(dims, nc, 0.1, cuda(U))
+    for inner in ("f64", "f32"):
+        o_e = ctx.opts(tol=1e-10, inner=inner, rhs_block=32)
+        o_g = ctx.opts(tol=1e-10, inner=inner, rhs_block=32, use_graph=1)
+        ref = ctx.trace_estimate([op], [ps], [1], o_e)[0]
+        for rep in range(3):
+            g = ctx.trace_estimate([op], [ps], [1], o_g)[0]
+            assert np.array_equal(g["tj"], ref["tj"]), (inner, rep)
+            assert g["solve"]["rhs_iters"] == ref["solve"]["rhs_iters"]
+            e = ctx.trace_estimate([op], [ps], [1], o_e)[0]  # eager work between replays
+            assert np.array_equal(e["tj"], ref["tj"])
+        B = ctx.make_probes(ps, 0, 40)
+        (Xe,), _ = ctx.solve_batch([op], [B], o_e)
+        (Xg,), _ = ctx.solve_batch([op], [B], o_g)
+        assert torch.equal(Xe, Xg)
