@@ -1,0 +1,133 @@
+"""Full-size checks at the 16^4 and 32^4 workloads, through the C ABI.
+
+The oracle cannot solve 10^5-10^6-unknown systems in test time, so these
+tests check properties that hold at any size: the oracle's FP64 operator
+applied to GPU solutions (the true residual), the oracle's independent
+colouring code on the same lattice, sampled contractions solved one by one
+by the oracle (16^4), and central finite differences of the GPU estimate
+against the GPU adjoint gradient (32^4).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2106_01275_amd as dp  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return dp.context(0)
+
+
+def test_gauge16_nested_sampled_parity(ctx):
+    """16^4 x 3 nested workload in the configuration the benchmark times
+    (finest level, FP32 + FP64 reliable updates, W = 32, tol 1e-8): a few
+    contractions t_j recomputed by the oracle one right-hand side at a time
+    (FP64 CG to 1e-10) agree to 1e-6 relative to max |t|."""
+    w = workloads.GAUGE_16
+    _say("16^4 nested sampled parity")
+    cols, ncols, _ = dp.build_coloring(w.dims, w.p, list(w.ks), "natural")
+    assert list(ncols) == [3, 5, 16, 960]
+    col = np.ascontiguousarray(cols[-1])
+    U = w.links()
+    op = ctx.operator(w.dims, 3, w.m2, torch.from_numpy(U).cuda())
+    colg = torch.from_numpy(col).cuda()
+    ps = ctx.probe_spec(w.dims, 3, colg, 960, 0, 0, 1, "z2_complex", True)
+    r = ctx.trace_estimate([op], [ps], [w.p], ctx.opts(tol=1e-8, inner="f32", rhs_block=32,
+                                                       reliable_delta=1e-3))[0]
+    assert r["solve"]["nconverged"] == 2880 and r["solve"]["max_true_resid"] <= 1e-8
+    js = [0, 1, 2, 1441, 2879]
+    B = np.stack([oracle.probe(w.dims, 3, col, 0, 0, j // 3, j % 3, True, oracle.Z2_COMPLEX) for j in js])
+    X, its, rel = oracle.cg_many(w.dims, 3, w.m2, U, B, tol=1e-10)
+    N = w.volume
+    for k, j in enumerate(js):
+        xs = X[k].reshape(N, 3)
+        idx = np.arange(N).reshape(w.dims)
+        shifted = np.roll(idx, -w.p, axis=0).ravel()  # site x -> x + p e0
+        t_or = np.sum(np.conj(B[k]) * xs[shifted])
+        scale = np.abs(r["tj"]).max()
+        assert abs(r["tj"][j] - t_or) < 1e-6 * scale, (j, r["tj"][j], t_or)
+
+
+def test_gauge32_solution_residual_by_oracle_operator(ctx):
+    """32^4 x 3 (3.1M unknowns): GPU solutions of two probes have FP64
+    residual <= 1e-9 when the oracle's own operator is applied to them."""
+    w = workloads.GAUGE_32
+    _say("32^4 residual")
+    col, n, _ = dp.build_coloring(w.dims, w.p, 8, "natural")
+    U = w.links()
+    Ug = torch.from_numpy(U).cuda()
+    op = ctx.operator(w.dims, 3, w.m2, Ug)
+    ps = ctx.probe_spec(w.dims, 3, torch.from_numpy(col).cuda(), n, 0, 0, 1, "z2_complex", True)
+    B = ctx.make_probes(ps, 0, 2)
+    (X,), (st,) = ctx.solve_batch([op], [B], ctx.opts(tol=1e-10, inner="f32", rhs_block=2,
+                                                      reliable_delta=1e-3))
+    assert st["nconverged"] == 2
+    Xh, Bh = X.cpu().numpy(), B.cpu().numpy()
+    for k in range(2):
+        res = Bh[k] - oracle.apply(w.dims, 3, w.m2, U, Xh[k])
+        assert np.linalg.norm(res) <= 1e-9 * np.linalg.norm(Bh[k])
+
+
+def test_gauge32_gradient_finite_differences(ctx):
+    """32^4 x 3, m2 = 0.01, eps = 0.5, p = 8, distance-8 colouring (32
+    colours), 96 diluted probes: the adjoint dT/dm2 and dT/dU (recomputed
+    solves, no Krylov history) against central differences of the GPU
+    estimate in m2 and along a random su(3) link direction.  At m2 = 0.01 the
+    O(h^2) truncation error of a central difference is not negligible; it is
+    estimated from the same difference at 2h (D(2h) - D(h) = 3 c h^2 for
+    D(h) = g + c h^2), so the check is |D(h) - g| <= 1e-6 |g| + |D(2h) - D(h)|."""
+    w = workloads.GAUGE_32
+    _say("32^4 gradient")
+    col, n, _ = dp.build_coloring(w.dims, w.p, 8, "best")
+    assert n == 32
+    U = w.links()
+    colg = torch.from_numpy(col).cuda()
+    opts = ctx.opts(tol=1e-11, inner="f32", rhs_block=32, reliable_delta=1e-3)
+    ps = ctx.probe_spec(w.dims, 3, colg, n, 0, 0, 1, "z2_complex", True)
+    Ug = torch.from_numpy(U).cuda()
+    op = ctx.operator(w.dims, 3, w.m2, Ug)
+    T, g, dU, dUb, st = ctx.trace_grad(op, ps, w.p, opts)
+    assert st["nconverged"] == st["nrhs"] == 2 * 96
+    h = 1e-4
+
+    def T_at(m2, Uc):
+        o = ctx.operator(w.dims, 3, m2, Uc)
+        return ctx.trace_estimate([o], [ps], [w.p], opts)[0]["T"]
+
+    T0 = T_at(w.m2, Ug)
+    assert abs(T0 - T) < 1e-9 * abs(T)
+    fd = (T_at(w.m2 + h, Ug) - T_at(w.m2 - h, Ug)) / (2 * h)
+    fd2 = (T_at(w.m2 + 2 * h, Ug) - T_at(w.m2 - 2 * h, Ug)) / (4 * h)
+    assert abs(fd - g) <= 1e-6 * abs(g) + abs(fd2 - fd), (fd, fd2, g)
+    assert abs(fd - g) < 1e-4 * abs(g)
+    rng = np.random.default_rng(1)
+    N = w.volume
+    G = rng.standard_normal((4, N, 3, 3)) + 1j * rng.standard_normal((4, N, 3, 3))
+    X = 0.5 * (G + np.conj(np.swapaxes(G, -1, -2)))
+    wv, Q = np.linalg.eigh(X)
+
+    def rot(t):
+        E = (Q * np.exp(1j * t * wv)[..., None, :]) @ np.conj(np.swapaxes(Q, -1, -2))
+        return torch.from_numpy(E @ U).cuda()
+
+    fdU = (T_at(w.m2, rot(h)) - T_at(w.m2, rot(-h))) / (2 * h)
+    fdU2 = (T_at(w.m2, rot(2 * h)) - T_at(w.m2, rot(-2 * h))) / (4 * h)
+    dUdt = torch.from_numpy(1j * X @ U).cuda()
+    an = (torch.sum(dU * dUdt) + torch.sum(dUb * torch.conj(dUdt))).item()
+    assert abs(fdU - an) <= 1e-6 * abs(an) + abs(fdU2 - fdU), (fdU, fdU2, an)
+    assert abs(fdU - an) < 1e-4 * abs(an)
