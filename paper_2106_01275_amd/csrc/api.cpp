@@ -42,6 +42,7 @@ dp_status solve_cfg(dp_ctx *ctx, const dp_solve_opts *o, SolveCfg &c) {
     c.delta = o->reliable_delta > 0 ? o->reliable_delta : 0.1;
     c.profile = o->profile;
     c.use_graph = o->use_graph;
+    c.ru_gap = c.inner == kBF16 ? 24 : 100;
     if (!(c.tol > 0) || !(c.delta < 1)) {
         ctx->err = "tol must be > 0 and reliable_delta < 1";
         return DP_EINVAL;
@@ -86,6 +87,38 @@ ProbeGen make_gen(const dp_probe_spec &ps, long long rhs0, long long nvalid, int
 }
 
 double noise_norm(int kind) { return kind == DP_NOISE_Z2_COMPLEX ? 0.5 : 1.0; }
+
+dp_status batch_inst(dp_ctx *ctx, const dp_operator &op, BatchInst &I) {
+    for (int d = 0; d < 4; ++d)
+        if (op.dims[d] < 1) {
+            ctx->err = "operator dims must be >= 1";
+            return DP_EINVAL;
+        }
+    if (op.nc != 1 && op.nc != 3) {
+        ctx->err = "operator nc must be 1 or 3";
+        return DP_EINVAL;
+    }
+    const long long N = (long long)op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3];
+    if (N > (1LL << 30) / 8) {
+        ctx->err = "lattice too large";
+        return DP_EUNSUPPORTED;
+    }
+    for (int d = 0; d < 4; ++d) I.lat.D[d] = op.dims[d];
+    I.lat.N = (int)N;
+    I.nc = op.nc;
+    I.m2 = op.m2;
+    I.links = op.links != nullptr;
+    I.links_abi = op.links;
+    return DP_OK;
+}
+
+// The multi-instance engine needs one nc and either links everywhere or nowhere.
+bool batchable(int ninst, const dp_operator *ops) {
+    if (ninst < 2) return false;
+    for (int i = 1; i < ninst; ++i)
+        if (ops[i].nc != ops[0].nc || (ops[i].links == nullptr) != (ops[0].links == nullptr)) return false;
+    return true;
+}
 
 dp_status final_status(const dp_solve_stats &st) {
     if (st.nbreakdown > 0) return DP_EBREAKDOWN;
@@ -205,6 +238,41 @@ dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, con
     } leave_{ws_};
     stream = ws_.s;
     dp_status worst = DP_OK;
+    if (batchable(ninst, ops)) {
+        const double t0 = now_s();
+        std::vector<BatchInst> in(ninst);
+        long long maxr = 0;
+        for (int i = 0; i < ninst; ++i) {
+            if (nrhs[i] < 0 || (nrhs[i] > 0 && (!b[i] || !x[i]))) {
+                ctx->err = "solve_batch: bad right-hand sides";
+                return DP_EINVAL;
+            }
+            DP_TRY(batch_inst(ctx, ops[i], in[i]));
+            in[i].nrhs = nrhs[i];
+            in[i].babi = (const double *)b[i];
+            in[i].xabi = (double *)x[i];
+            maxr = std::max<long long>(maxr, nrhs[i]);
+        }
+        int W = o->rhs_block;
+        if (W <= 0) {
+            W = 1;
+            while (W < maxr && W < 32) W *= 2;
+        } else if (W > kMaxW || (W & (W - 1))) {
+            ctx->err = "rhs_block must be a power of two <= 256";
+            return DP_EINVAL;
+        }
+        DP_TRY(run_batch(ctx, in, cfg, W, false, stream));
+        for (int i = 0; i < ninst; ++i) {
+            in[i].st.rhs_block = W;
+            in[i].st.seconds = now_s() - t0;
+            if (st) st[i] = in[i].st;
+            dp_status fs = final_status(in[i].st);
+            if (fs != DP_OK && worst == DP_OK) worst = fs;
+        }
+        if (worst == DP_ENOCONV) ctx->err = "solve_batch: some right-hand sides did not converge";
+        if (worst == DP_EBREAKDOWN) ctx->err = "solve_batch: CG breakdown (operator not positive definite?)";
+        return worst;
+    }
     for (int i = 0; i < ninst; ++i) {
         const double t0 = now_s();
         dp_solve_stats s{};
@@ -242,6 +310,36 @@ dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, con
     return worst;
 }
 
+// T_s, T and stderr from the per-right-hand-side contractions
+static void combine(const dp_probe_spec &ps, const std::vector<double> &tj, dp_trace_result &out) {
+    const int ndil = ps.dilute ? ps.nc : 1;
+    const long long nrhs = (long long)ps.nsamples * ps.ncolors * ndil;
+    const double norm = noise_norm(ps.noise);
+    const long long per = (long long)ps.ncolors * ndil;
+    std::vector<double> Ts(2 * ps.nsamples, 0.0);
+    for (long long j = 0; j < nrhs; ++j) {
+        Ts[2 * (j / per)] += norm * tj[2 * j];
+        Ts[2 * (j / per) + 1] += norm * tj[2 * j + 1];
+    }
+    double Tr = 0, Ti = 0;
+    for (int s_ = 0; s_ < ps.nsamples; ++s_) {
+        Tr += Ts[2 * s_];
+        Ti += Ts[2 * s_ + 1];
+    }
+    Tr /= ps.nsamples;
+    Ti /= ps.nsamples;
+    double var = 0;
+    for (int s_ = 0; s_ < ps.nsamples; ++s_) {
+        const double dr = Ts[2 * s_] - Tr, di = Ts[2 * s_ + 1] - Ti;
+        var += dr * dr + di * di;
+    }
+    out.tr[0] = Tr;
+    out.tr[1] = Ti;
+    out.stderr_ = ps.nsamples > 1 ? std::sqrt(var / (ps.nsamples - 1) / ps.nsamples) : NAN;
+    if (out.per_sample) std::memcpy(out.per_sample, Ts.data(), Ts.size() * sizeof(double));
+    if (out.per_rhs) std::memcpy(out.per_rhs, tj.data(), tj.size() * sizeof(double));
+}
+
 static dp_status trace_one(dp_ctx *ctx, const dp_operator &opd, int32_t p, const dp_probe_spec &ps,
                            const dp_solve_opts *o, const SolveCfg &cfg, dp_trace_result &out, hipStream_t stream) {
     const double t0 = now_s();
@@ -275,30 +373,7 @@ static dp_status trace_one(dp_ctx *ctx, const dp_operator &opd, int32_t p, const
         DP_HIP(hipMemcpyAsync(tj.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
     }
     DP_HIP(hipStreamSynchronize(stream));
-    const double norm = noise_norm(ps.noise);
-    const long long per = (long long)ps.ncolors * ndil;
-    std::vector<double> Ts(2 * ps.nsamples, 0.0);
-    for (long long j = 0; j < nrhs; ++j) {
-        Ts[2 * (j / per)] += norm * tj[2 * j];
-        Ts[2 * (j / per) + 1] += norm * tj[2 * j + 1];
-    }
-    double Tr = 0, Ti = 0;
-    for (int s_ = 0; s_ < ps.nsamples; ++s_) {
-        Tr += Ts[2 * s_];
-        Ti += Ts[2 * s_ + 1];
-    }
-    Tr /= ps.nsamples;
-    Ti /= ps.nsamples;
-    double var = 0;
-    for (int s_ = 0; s_ < ps.nsamples; ++s_) {
-        const double dr = Ts[2 * s_] - Tr, di = Ts[2 * s_ + 1] - Ti;
-        var += dr * dr + di * di;
-    }
-    out.tr[0] = Tr;
-    out.tr[1] = Ti;
-    out.stderr_ = ps.nsamples > 1 ? std::sqrt(var / (ps.nsamples - 1) / ps.nsamples) : NAN;
-    if (out.per_sample) std::memcpy(out.per_sample, Ts.data(), Ts.size() * sizeof(double));
-    if (out.per_rhs) std::memcpy(out.per_rhs, tj.data(), tj.size() * sizeof(double));
+    combine(ps, tj, out);
     s.seconds = now_s() - t0;
     out.solve = s;
     return final_status(s);
@@ -322,6 +397,45 @@ dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, 
     } leave_{ws_};
     stream = ws_.s;
     dp_status worst = DP_OK;
+    if (batchable(ninst, ops)) {
+        const double t0 = now_s();
+        std::vector<BatchInst> in(ninst);
+        long long maxr = 0;
+        for (int i = 0; i < ninst; ++i) {
+            DP_TRY(check_spec(ctx, ps[i], &ops[i]));
+            if (p[i] < 0) {
+                ctx->err = "trace_estimate: p must be >= 0";
+                return DP_EINVAL;
+            }
+            DP_TRY(batch_inst(ctx, ops[i], in[i]));
+            const int ndil = ps[i].dilute ? ps[i].nc : 1;
+            in[i].nrhs = (long long)ps[i].nsamples * ps[i].ncolors * ndil;
+            in[i].ps = ps[i];
+            in[i].disp = p[i];
+            in[i].tj.assign(2 * in[i].nrhs, 0.0);
+            maxr = std::max<long long>(maxr, in[i].nrhs);
+        }
+        int W = o->rhs_block;
+        if (W <= 0) {
+            W = 1;
+            while (W < maxr && W < 32) W *= 2;
+        } else if (W > kMaxW || (W & (W - 1))) {
+            ctx->err = "rhs_block must be a power of two <= 256";
+            return DP_EINVAL;
+        }
+        DP_TRY(run_batch(ctx, in, cfg, W, true, stream));
+        for (int i = 0; i < ninst; ++i) {
+            combine(ps[i], in[i].tj, out[i]);
+            in[i].st.rhs_block = W;
+            in[i].st.seconds = now_s() - t0;
+            out[i].solve = in[i].st;
+            dp_status fs = final_status(in[i].st);
+            if (fs != DP_OK && worst == DP_OK) worst = fs;
+        }
+        if (worst == DP_ENOCONV) ctx->err = "trace_estimate: some right-hand sides did not converge";
+        if (worst == DP_EBREAKDOWN) ctx->err = "trace_estimate: CG breakdown";
+        return worst;
+    }
     for (int i = 0; i < ninst; ++i) {
         dp_status s = trace_one(ctx, ops[i], p[i], ps[i], o, cfg, out[i], stream);
         if (s == DP_EINVAL || s == DP_ENOMEM || s == DP_EHIP || s == DP_EUNSUPPORTED) return s;

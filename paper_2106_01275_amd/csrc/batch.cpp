@@ -1,0 +1,375 @@
+// Multi-instance engine: many independent lattice instances (each with its
+// own operator, displacement and probes) solved together.  The work is a
+// list of jobs, one per block of W right-hand sides of an instance, ordered
+// longest first.  Up to kMaxSlots jobs are resident at once, each in a slot
+// with its own buffers and CG state; every kernel of a CG iteration is ONE
+// launch over all slots (a device-side slot table maps workgroups to slots),
+// so small lattices share the GPU instead of each underfilling it.  At each
+// host check the finished slots are contracted and refilled with the next
+// jobs; the slot table is rewritten in device memory, so the captured graph
+// of an iteration group stays valid for the whole batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "context.h"
+
+namespace dp {
+
+namespace {
+
+constexpr int kMaxSlots = 64;
+
+struct DevBuf {
+    std::vector<void *> ptrs;
+    ~DevBuf() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    dp_status alloc(dp_ctx *ctx, void **out, size_t bytes, bool zero = false) {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes ? bytes : 256) != hipSuccess) {
+            ctx->err = "batch: out of device memory";
+            return DP_ENOMEM;
+        }
+        ptrs.push_back(p);
+        if (zero) DP_HIP(hipMemset(p, 0, bytes ? bytes : 256));
+        *out = p;
+        return DP_OK;
+    }
+};
+
+size_t prec_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
+
+struct Job {
+    int inst;
+    long long r0;
+    int nv;
+    double cost;
+};
+
+}  // namespace
+
+dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg, int W, bool trace_mode,
+                    hipStream_t s) {
+    const int ninst = (int)in.size();
+    const bool mixed = cfg.inner != kF64;
+    const int nc = in[0].nc;
+    const bool links = in[0].links;
+    int logW = 0;
+    while ((1 << logW) < W) ++logW;
+    DevBuf mem;
+
+    // per-instance operator data: neighbour table and converted links
+    int maxN = 0;
+    for (auto &I : in) {
+        maxN = std::max(maxN, I.lat.N);
+        DP_TRY(mem.alloc(ctx, (void **)&I.nbr, (size_t)I.lat.N * 8 * sizeof(int)));
+        build_neighbours(I.lat, I.nbr, s);
+        if (I.links) {
+            const size_t nl = (size_t)I.lat.N * 4 * nc * nc;
+            DP_TRY(mem.alloc(ctx, &I.U64, nl * 16));
+            convert_links(kF64, I.lat, nc, I.links_abi, I.U64, s);
+            if (mixed) {
+                DP_TRY(mem.alloc(ctx, &I.ULo, nl * prec_bytes(cfg.inner)));
+                convert_links(cfg.inner, I.lat, nc, I.links_abi, I.ULo, s);
+            } else {
+                I.ULo = I.U64;
+            }
+        }
+    }
+    DP_HIP(hipGetLastError());
+
+    // jobs, longest first
+    std::vector<Job> jobs;
+    for (int i = 0; i < ninst; ++i)
+        for (long long r0 = 0; r0 < in[i].nrhs; r0 += W) {
+            const int nv = (int)std::min<long long>(W, in[i].nrhs - r0);
+            jobs.push_back({i, r0, nv, (double)in[i].lat.N * nv * std::sqrt(9.0 / std::max(in[i].m2, 1e-6))});
+        }
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.cost > b.cost; });
+    const int nslots = std::max(1, std::min<int>((int)jobs.size(), kMaxSlots));
+
+    // workgroups per slot: enough for the largest lattice, a multiple of 8
+    const int spt = kBlock >> logW;
+    int nblk = std::min(grid_blocks((maxN + spt - 1) / spt), 2048 * 8 / nslots);
+    nblk = std::max(8, nblk - nblk % 8);
+
+    // slot buffers
+    const size_t vec = (size_t)maxN * nc * W;
+    const size_t lo = vec * prec_bytes(cfg.inner);
+    std::vector<SlotDesc> hsd(nslots);
+    int *ctrl_all = nullptr;
+    DP_TRY(mem.alloc(ctx, (void **)&ctrl_all, (size_t)nslots * 8 * sizeof(double), true));
+    for (int k = 0; k < nslots; ++k) {
+        SlotDesc &d = hsd[k];
+        std::memset(&d, 0, sizeof d);
+        DP_TRY(mem.alloc(ctx, (void **)&d.b64, vec * 16));
+        DP_TRY(mem.alloc(ctx, (void **)&d.x64, vec * 16));
+        DP_TRY(mem.alloc(ctx, &d.r, lo));
+        DP_TRY(mem.alloc(ctx, &d.p, lo));
+        DP_TRY(mem.alloc(ctx, &d.q, lo));
+        if (mixed)
+            DP_TRY(mem.alloc(ctx, &d.xlo, lo));
+        else
+            d.xlo = d.x64;
+        DP_TRY(mem.alloc(ctx, (void **)&d.rd.part1, (size_t)W * nblk * 2 * sizeof(double)));
+        d.rd.nblk = nblk;
+        double *st = nullptr;
+        DP_TRY(mem.alloc(ctx, (void **)&st, (9 * kMaxW + 8) * sizeof(double) + (3 * kMaxW + 8) * sizeof(int)));
+        CgState &cs = d.cs;
+        cs.rr = st;
+        cs.rr_prev = st + kMaxW;
+        cs.rr_ref = st + 2 * kMaxW;
+        cs.bb = st + 3 * kMaxW;
+        cs.alpha = st + 4 * kMaxW;
+        cs.beta = st + 5 * kMaxW;
+        cs.true_rr = st + 6 * kMaxW;
+        cs.tj = st + 7 * kMaxW;
+        int *iv = (int *)(st + 9 * kMaxW + 8);
+        cs.active = iv;
+        cs.iters = iv + kMaxW;
+        cs.flags = iv + 2 * kMaxW;
+        cs.ctrl = ctrl_all + 16 * k;
+        cs.ctrld = (double *)(ctrl_all + 16 * k + 8);
+        cs.tol2 = cfg.tol * cfg.tol;
+        cs.delta2 = cfg.delta * cfg.delta;
+        cs.exact = !mixed;
+        d.blk0 = k * nblk;
+    }
+    std::vector<int> slot_of((size_t)nslots * nblk);
+    for (size_t w = 0; w < slot_of.size(); ++w) slot_of[w] = (int)(w / nblk);
+    SlotDesc *d_sd = nullptr;
+    int *d_slot_of = nullptr;
+    DP_TRY(mem.alloc(ctx, (void **)&d_sd, sizeof(SlotDesc) * nslots));
+    DP_TRY(mem.alloc(ctx, (void **)&d_slot_of, sizeof(int) * slot_of.size()));
+    DP_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int) * slot_of.size(), hipMemcpyHostToDevice, s));
+
+    BatchLaunch B;
+    B.sd = d_sd;
+    B.slot_of = d_slot_of;
+    B.nslots = nslots;
+    B.nblocks = nslots * nblk;
+    B.W = W;
+    B.nc = nc;
+    B.prec = cfg.inner;
+    B.links = links;
+    B.mode = W >= 64 ? 2 : (W >= 16 ? 1 : 0);
+    B.stream = s;
+
+    std::vector<int> slot_job(nslots, -1), slot_it(nslots, 0), slot_ru(nslots, 0);
+    size_t next_job = 0;
+    auto assign = [&](int k, int jidx) {
+        const Job &jb = jobs[jidx];
+        BatchInst &I = in[jb.inst];
+        SlotDesc &d = hsd[k];
+        d.L.lat = I.lat;
+        d.L.nc = nc;
+        d.L.W = W;
+        d.L.logW = logW;
+        d.L.nblk = nblk;
+        d.L.ntiles = (I.lat.N + spt - 1) / spt;
+        d.L.stream = s;
+        d.diag = I.m2 + 8.0;
+        d.U = I.ULo;
+        d.U64 = I.U64;
+        d.nbr = I.nbr;
+        ProbeGen g{};
+        if (trace_mode) {
+            g.colors = I.ps.colors_dev;
+            g.seed = I.ps.seed;
+            g.ncolors = I.ps.ncolors;
+            g.sample0 = I.ps.sample0;
+            g.noise = I.ps.noise;
+            g.dilute = I.ps.dilute ? 1 : 0;
+        }
+        g.rhs0 = jb.r0;
+        g.nvalid = jb.nv;
+        d.g = g;
+        d.disp = I.disp;
+        d.flags = kSlotInit;
+        slot_job[k] = jidx;
+        slot_it[k] = 0;
+        slot_ru[k] = 0;
+    };
+    auto upload = [&]() -> dp_status {
+        DP_HIP(hipMemcpyAsync(d_sd, hsd.data(), sizeof(SlotDesc) * nslots, hipMemcpyHostToDevice, s));
+        return DP_OK;
+    };
+    // initialise the slots flagged kSlotInit, then make them iterate
+    auto init_slots = [&]() -> dp_status {
+        DP_TRY(upload());
+        if (trace_mode) {
+            launch_b_init(B, mixed ? 1 : 0);
+        } else {
+            for (int k = 0; k < nslots; ++k) {
+                if (!(hsd[k].flags & kSlotInit)) continue;
+                const Job &jb = jobs[slot_job[k]];
+                launch_init_abi(hsd[k].L, cfg.inner, in[jb.inst].babi, jb.r0, jb.nv, hsd[k].b64, hsd[k].r,
+                                hsd[k].p, hsd[k].xlo, hsd[k].x64, mixed ? 1 : 0, hsd[k].rd, hsd[k].cs);
+            }
+        }
+        DP_HIP(hipGetLastError());
+        for (auto &d : hsd)
+            if (d.flags & kSlotInit) d.flags = kSlotIter;
+        return upload();
+    };
+    std::vector<int> hctrl((size_t)nslots * 16);
+    auto read_ctrl_all = [&]() -> dp_status {
+        launch_b_ctrl(B);
+        DP_HIP(hipMemcpyAsync(hctrl.data(), ctrl_all, sizeof(int) * 16 * nslots, hipMemcpyDeviceToHost, s));
+        DP_HIP(hipStreamSynchronize(s));
+        return DP_OK;
+    };
+    // contract / copy out the slots flagged kSlotFinal and record statistics
+    std::vector<double> hres(6 * kMaxW);
+    auto finish_slots = [&]() -> dp_status {
+        DP_TRY(upload());
+        launch_b_ru(B, 1);
+        if (trace_mode) launch_b_dot(B);
+        DP_HIP(hipGetLastError());
+        for (int k = 0; k < nslots; ++k) {
+            if (!(hsd[k].flags & kSlotFinal)) continue;
+            const Job &jb = jobs[slot_job[k]];
+            BatchInst &I = in[jb.inst];
+            const CgState &cs = hsd[k].cs;
+            if (!trace_mode) launch_to_abi(hsd[k].L, hsd[k].x64, I.xabi, jb.r0, jb.nv);
+            double *h = hres.data();
+            int *hi = (int *)(h + 4 * kMaxW);
+            DP_HIP(hipMemcpyAsync(h, cs.true_rr, W * sizeof(double), hipMemcpyDeviceToHost, s));
+            DP_HIP(hipMemcpyAsync(h + kMaxW, cs.bb, W * sizeof(double), hipMemcpyDeviceToHost, s));
+            DP_HIP(hipMemcpyAsync(h + 2 * kMaxW, cs.tj, 2 * W * sizeof(double), hipMemcpyDeviceToHost, s));
+            DP_HIP(hipMemcpyAsync(hi, cs.iters, W * sizeof(int), hipMemcpyDeviceToHost, s));
+            DP_HIP(hipMemcpyAsync(hi + kMaxW, cs.flags, W * sizeof(int), hipMemcpyDeviceToHost, s));
+            DP_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j < jb.nv; ++j) {
+                const double bb = h[kMaxW + j];
+                I.st.max_true_resid = std::max(I.st.max_true_resid, bb > 0 ? std::sqrt(h[j] / bb) : 0.0);
+                I.st.rhs_iters += hi[j];
+                I.st.max_iters = std::max(I.st.max_iters, hi[j]);
+                if (hi[kMaxW + j] & kFlagBreakdown) ++I.st.nbreakdown;
+                else if (hi[kMaxW + j] & kFlagConverged) ++I.st.nconverged;
+                if (trace_mode) {
+                    I.tj[2 * (jb.r0 + j)] = h[2 * kMaxW + 2 * j];
+                    I.tj[2 * (jb.r0 + j) + 1] = h[2 * kMaxW + 2 * j + 1];
+                }
+            }
+            I.st.nrhs += jb.nv;
+            hsd[k].flags = 0;
+            slot_job[k] = -1;
+        }
+        return DP_OK;
+    };
+
+    for (int k = 0; k < nslots && next_job < jobs.size(); ++k) assign(k, (int)next_job++);
+    DP_TRY(init_slots());
+
+    int steps_next = std::max(1, ctx->check_every);
+    std::vector<double> ratio_prev(nslots, -1.0);
+    std::vector<int> it_prev(nslots, 0);
+    ctx->drop_graphs();
+    for (;;) {
+        bool any = false;
+        for (auto &d : hsd) any |= (d.flags & kSlotIter) != 0;
+        if (!any) break;
+        int steps = steps_next;
+        for (int k = 0; k < nslots; ++k)
+            if (hsd[k].flags & kSlotIter) steps = std::min(steps, std::max(1, cfg.max_iter - slot_it[k]));
+        if (cfg.use_graph && !cfg.profile) {
+            auto g = ctx->graphs.find(steps);
+            if (g == ctx->graphs.end()) {
+                hipGraph_t graph = nullptr;
+                hipGraphExec_t exec = nullptr;
+                DP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                for (int c = 0; c < steps; ++c) launch_b_iteration(B, true);
+                DP_HIP(hipStreamEndCapture(s, &graph));
+                const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                DP_HIP(ie);
+                g = ctx->graphs.emplace(steps, exec).first;
+            }
+            DP_HIP(hipGraphLaunch(g->second, s));
+        } else {
+            // update2 on a freshly initialised slot is harmless: beta = 0 and p = r = b
+            for (int c = 0; c < steps; ++c) launch_b_iteration(B, true);
+        }
+        DP_HIP(hipGetLastError());
+        for (int k = 0; k < nslots; ++k)
+            if (hsd[k].flags & kSlotIter) slot_it[k] += steps;
+        DP_TRY(read_ctrl_all());
+        bool any_ru = false, any_fin = false;
+        int next_steps = 16;
+        for (int k = 0; k < nslots; ++k) {
+            SlotDesc &d = hsd[k];
+            if (!(d.flags & kSlotIter)) continue;
+            const int *c = hctrl.data() + 16 * k;
+            double ratio;
+            std::memcpy(&ratio, c + 8, sizeof(double));
+            const int nactive = c[0];
+            if (nactive == 0) {
+                d.flags = kSlotFinal;
+                any_fin = true;
+                continue;
+            }
+            if (mixed && (c[2] > 0 || c[1] == nactive || slot_it[k] >= cfg.max_iter ||
+                          slot_it[k] - slot_ru[k] >= cfg.ru_gap)) {
+                d.flags = kSlotIter | kSlotRU;
+                slot_ru[k] = slot_it[k];
+                any_ru = true;
+            } else if (slot_it[k] >= cfg.max_iter) {
+                d.flags = kSlotFinal;
+                any_fin = true;
+                continue;
+            }
+            int nx = std::max(1, ctx->check_every);
+            if (ratio_prev[k] > 0 && ratio > 1.0 && ratio < ratio_prev[k] && slot_it[k] > it_prev[k]) {
+                const double per_it = std::log(ratio_prev[k] / ratio) / (slot_it[k] - it_prev[k]);
+                nx = (int)std::ceil(std::log(ratio) / per_it);
+            }
+            next_steps = std::min(next_steps, std::max(2, nx));
+            ratio_prev[k] = ratio;
+            it_prev[k] = slot_it[k];
+        }
+        steps_next = next_steps;
+        if (any_ru) {
+            DP_TRY(upload());
+            launch_b_ru(B, 0);
+            DP_HIP(hipGetLastError());
+            DP_TRY(read_ctrl_all());
+            for (int k = 0; k < nslots; ++k) {
+                SlotDesc &d = hsd[k];
+                if (!(d.flags & kSlotRU)) continue;
+                ++in[jobs[slot_job[k]].inst].st.reliable_updates;
+                d.flags = kSlotIter;
+                if (hctrl[16 * k] == 0 || slot_it[k] >= cfg.max_iter) {
+                    d.flags = kSlotFinal;
+                    any_fin = true;
+                }
+            }
+        }
+        if (any_fin) {
+            DP_TRY(finish_slots());
+            bool any_init = false;
+            for (int k = 0; k < nslots; ++k) {
+                if (hsd[k].flags == 0 && next_job < jobs.size()) {
+                    assign(k, (int)next_job++);
+                    ratio_prev[k] = -1.0;
+                    it_prev[k] = 0;
+                    any_init = true;
+                }
+            }
+            if (any_init) DP_TRY(init_slots());
+            else DP_TRY(upload());
+        } else if (any_ru) {
+            DP_TRY(upload());
+        }
+    }
+    DP_HIP(hipStreamSynchronize(s));
+    ctx->drop_graphs();
+    return DP_OK;
+}
+
+}  // namespace dp

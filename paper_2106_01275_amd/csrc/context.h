@@ -80,6 +80,7 @@ struct SolveCfg {
     int max_iter = 100000;
     int inner = kF64;
     double delta = 0.1;
+    int ru_gap = 100;     // a reliable update at least every ru_gap iterations (mixed)
     int profile = 0;
     int W = 0, logW = 0;
 };
@@ -106,6 +107,26 @@ struct WorkStream {
     dp_status enter(dp_ctx *c, hipStream_t u, bool graph);
     dp_status leave();
 };
+
+// One instance of a multi-instance batch (batch.cpp).
+struct BatchInst {
+    Lat lat{};
+    int nc = 3;
+    double m2 = 0;
+    bool links = false;
+    const void *links_abi = nullptr;   // caller's complex128 [4][N][nc][nc]
+    void *U64 = nullptr, *ULo = nullptr;
+    int *nbr = nullptr;
+    long long nrhs = 0;
+    dp_probe_spec ps{};                // trace mode
+    int disp = 0;
+    const double *babi = nullptr;      // solve mode
+    double *xabi = nullptr;
+    std::vector<double> tj;            // [2 * nrhs] contractions (trace mode)
+    dp_solve_stats st{};
+};
+dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg, int W, bool trace_mode,
+                    hipStream_t s);
 
 // Initialisers of a block: probes generated on the device, or ABI vectors.
 struct InitProbe {

@@ -37,7 +37,9 @@ struct CgState {
     int exact;           // 1: FP64 inner solve (no reliable updates)
 };
 
-enum { kFlagBreakdown = 1, kFlagConverged = 2 };
+// kFlagRestart (mixed precision): p^H A p <= 0 in low precision; the next
+// reliable update restarts the search direction from the true residual.
+enum { kFlagBreakdown = 1, kFlagConverged = 2, kFlagRestart = 4 };
 
 // Geometry of a lattice on the device.
 struct Lat {
@@ -65,6 +67,39 @@ struct Launch {
     int nblk, ntiles;   // grid size and number of site tiles
     hipStream_t stream;
 };
+
+// One job of a multi-instance launch: a block of W right-hand sides of one
+// lattice instance, with its own buffers and CG state.  All slots of a
+// launch share the precision, nc, W and whether links are present.
+struct SlotDesc {
+    Launch L;            // geometry; L.nblk workgroups starting at blk0
+    int blk0;
+    int flags;           // kSlot* phases this slot takes part in
+    double diag;         // m2 + 8
+    const void *U;       // inner-precision links
+    const void *U64;     // FP64 links
+    const int *nbr;
+    void *r, *p, *q, *xlo;
+    double *x64, *b64;
+    Red rd;
+    CgState cs;
+    ProbeGen g;          // probes of the slot's right-hand sides
+    int disp;            // displacement of the contraction
+};
+enum { kSlotIter = 1, kSlotInit = 2, kSlotRU = 4, kSlotFinal = 8 };
+
+// Multi-instance launches: slot_of[workgroup] = slot; W lanes per slot.
+struct BatchLaunch {
+    const SlotDesc *sd;  // device array [nslots]
+    const int *slot_of;  // device array [total workgroups]
+    int nslots, nblocks, W, nc, prec, links, mode;
+    hipStream_t stream;
+};
+void launch_b_init(const BatchLaunch &B, int mixed);
+void launch_b_iteration(const BatchLaunch &B, bool update2);
+void launch_b_ru(const BatchLaunch &B, int final_stats);
+void launch_b_dot(const BatchLaunch &B);
+void launch_b_ctrl(const BatchLaunch &B);
 
 int grid_blocks(int ntiles);
 void build_neighbours(const Lat &lat, int *nbr, hipStream_t s);

@@ -95,16 +95,26 @@ struct St<bf16x2> {
 
 // ============================================================ helpers
 
-__device__ __forceinline__ int logical_block() {
+// The workgroups working on one lattice: this workgroup's index b among
+// them and their number nb.  A standalone launch uses (blockIdx, gridDim);
+// in a multi-instance launch each slot owns a range of workgroups (starting
+// at a multiple of 8, so b % 8 is still the XCD).
+struct Blk {
+    int b, nb;
+};
+
+__device__ __forceinline__ Blk own_blk() { return Blk{(int)blockIdx.x, (int)gridDim.x}; }
+
+__device__ __forceinline__ int logical_block(const Blk &bk) {
     // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
     // that XCD x runs the contiguous range of logical blocks [x*n/8, (x+1)*n/8).
-    const int n = gridDim.x, b = blockIdx.x;
+    const int n = bk.nb, b = bk.b;
     if (n % 8) return b;
     return (b % 8) * (n / 8) + b / 8;
 }
 
-__device__ __forceinline__ void tile_range(int ntiles, int &t0, int &t1) {
-    const int lb = logical_block(), n = gridDim.x;
+__device__ __forceinline__ void tile_range(const Blk &bk, int ntiles, int &t0, int &t1) {
+    const int lb = logical_block(bk), n = bk.nb;
     t0 = (int)(((long long)lb * ntiles) / n);
     t1 = (int)(((long long)(lb + 1) * ntiles) / n);
 }
@@ -125,9 +135,9 @@ struct SiteWalk {
     int first, stride;  // first tile of this workgroup and tile stride
 };
 
-__device__ __forceinline__ SiteWalk site_walk(const Lat &lat) {
+__device__ __forceinline__ SiteWalk site_walk(const Lat &lat, const Blk &bk) {
     SiteWalk w;
-    const int nb = gridDim.x, b = blockIdx.x;
+    const int nb = bk.nb, b = bk.b;
     w.V3 = lat.D[1] * lat.D[2] * lat.D[3];
     if (nb >= 8 && nb % 8 == 0) {
         const int x = b % 8;
@@ -215,9 +225,9 @@ __device__ __forceinline__ void probe_value(const ProbeGen &g, unsigned long lon
 // ------------------------------------------------------------ reductions
 
 // Writes this workgroup's sums of NV values per lane to
-// part[(lane * nblk + blockIdx.x) * NV + v] (all threads call it once).
+// part[(lane * nblk + b) * NV + v] (all threads call it once).
 template <int NV>
-__device__ void block_partials(const double (&val)[NV], int W, int logW, const Red &rd, double *sm) {
+__device__ void block_partials(const Blk &bk, const double (&val)[NV], int W, int logW, const Red &rd, double *sm) {
     const int tid = threadIdx.x;
     const int spl = kBlock >> logW;  // threads per lane
 #pragma unroll
@@ -228,7 +238,7 @@ __device__ void block_partials(const double (&val)[NV], int W, int logW, const R
         for (int v = 0; v < NV; ++v) {
             double s = 0.0;
             for (int k = 0; k < spl; ++k) s += sm[v * kBlock + k * W + tid];
-            rd.part1[((size_t)tid * rd.nblk + blockIdx.x) * NV + v] = s;
+            rd.part1[((size_t)tid * rd.nblk + bk.b) * NV + v] = s;
         }
     }
 }
@@ -238,9 +248,9 @@ enum Epi { kEpiInit, kEpiAlpha, kEpiBeta, kEpiRU, kEpiStats, kEpiTj };
 // One workgroup per lane: total of the lane's partials (fixed order), then
 // the scalar epilogue of that lane.
 template <int NV, int EPI>
-__global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
+__device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgState &cs) {
     __shared__ double sm[NV * kBlock];
-    const int lane = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     double s[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) s[v] = 0.0;
@@ -275,9 +285,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
     } else if (EPI == kEpiAlpha) {
         if (cs.active[j]) {
             if (!(t > 0.0) || !isfinite(t)) {
-                cs.flags[j] |= kFlagBreakdown;
-                cs.active[j] = 0;
                 cs.alpha[j] = 0.0;
+                if (cs.exact) {
+                    cs.flags[j] |= kFlagBreakdown;
+                    cs.active[j] = 0;
+                } else {
+                    cs.flags[j] |= kFlagRestart;
+                }
             } else {
                 cs.alpha[j] = cs.rr[j] / t;
             }
@@ -300,7 +314,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
     } else if (EPI == kEpiRU || EPI == kEpiStats) {
         cs.true_rr[j] = t;
         if (EPI == kEpiRU && cs.active[j]) {
-            cs.beta[j] = t / cs.rr_prev[j];
+            // restart the direction (beta = 0) after a low-precision
+            // breakdown or when the true residual grew since the last update
+            const bool restart = (cs.flags[j] & kFlagRestart) || !(t <= cs.rr_ref[j]);
+            cs.beta[j] = restart ? 0.0 : t / cs.rr_prev[j];
+            cs.flags[j] &= ~kFlagRestart;
             cs.rr[j] = t;
             cs.rr_ref[j] = t;
             if (t <= cs.tol2 * cs.bb[j]) {
@@ -314,11 +332,16 @@ __global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
     }
 }
 
+template <int NV, int EPI>
+__global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
+    k_finish_body<NV, EPI>(blockIdx.x, rd, cs);
+}
+
 // Control word for the host: [0] active lanes, [1] active lanes whose
 // recursive residual meets tol, [2] active lanes due a reliable update,
 // [3] lanes that broke down; ctrld[0] the largest |r|^2 / (tol^2 |b|^2) of
 // an active lane (how far the slowest one still is from convergence).
-__global__ void k_ctrl(CgState cs, int W) {
+__device__ __forceinline__ void k_ctrl_body(const CgState &cs, int W) {
     __shared__ int cnt[4][64];
     __shared__ double worst[64];
     const int t = threadIdx.x;
@@ -330,7 +353,7 @@ __global__ void k_ctrl(CgState cs, int W) {
         ++na;
         const double goal = cs.tol2 * cs.bb[k];
         if (cs.rr[k] <= goal) ++nk;
-        if (cs.rr[k] < cs.delta2 * cs.rr_ref[k]) ++nru;
+        if (cs.rr[k] < cs.delta2 * cs.rr_ref[k] || (cs.flags[k] & kFlagRestart) || !isfinite(cs.rr[k])) ++nru;
         wr = fmax(wr, cs.rr[k] / goal);
     }
     cnt[0][t] = na;
@@ -347,6 +370,8 @@ __global__ void k_ctrl(CgState cs, int W) {
     for (int c = 0; c < 4; ++c) cs.ctrl[c] = cnt[c][0];
     cs.ctrld[0] = worst[0];
 }
+
+__global__ void k_ctrl(CgState cs, int W) { k_ctrl_body(cs, W); }
 
 // ============================================================ kernels
 
@@ -386,7 +411,7 @@ __global__ void k_convert_links(Lat L, int nc, const double2 *__restrict__ in, L
 // precision), x = 0, and |b|^2 per lane; the finishing workgroup sets up
 // the CG scalars.  SRC 0: probes generated from ProbeGen; 1: from ABI b.
 template <typename S, int SRC>
-__global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const double2 *__restrict__ babi,
+__device__ __forceinline__ void k_init_body(const Blk &bk, Launch L, ProbeGen g, const double2 *__restrict__ babi,
                                                  long long rhs0, long long nvalid, double2 *__restrict__ b64,
                                                  S *__restrict__ r, S *__restrict__ p, S *__restrict__ xlo,
                                                  double2 *__restrict__ x64, int mixed, Red rd, CgState cs) {
@@ -397,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const dou
     const unsigned long long seedmix = SRC == 0 ? mix64(g.seed) : 0ull;
     double acc[1] = {0.0};
     int t0, t1;
-    tile_range(L.ntiles, t0, t1);
+    tile_range(bk, L.ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
         const int site = t * (kBlock >> logW) + (tid >> logW);
         if (site >= L.lat.N) continue;
@@ -419,7 +444,15 @@ __global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const dou
             acc[0] += re * re + im * im;
         }
     }
-    block_partials<1>(acc, W, logW, rd, sm);
+    block_partials<1>(bk, acc, W, logW, rd, sm);
+}
+
+template <typename S, int SRC>
+__global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const double2 *__restrict__ babi,
+                                                 long long rhs0, long long nvalid, double2 *__restrict__ b64,
+                                                 S *__restrict__ r, S *__restrict__ p, S *__restrict__ xlo,
+                                                 double2 *__restrict__ x64, int mixed, Red rd, CgState cs) {
+    k_init_body<S, SRC>(own_blk(), L, g, babi, rhs0, nvalid, b64, r, p, xlo, x64, mixed, rd, cs);
 }
 
 // q = A p for one block of right-hand sides; with CG, also p^H q per lane
@@ -515,7 +548,7 @@ __device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, 
 // neighbours are issued before any arithmetic, so they are in flight
 // together.
 template <typename S, typename LS, int NC, bool LINKS, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ pin,
+__device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename St<S>::R diag, const S *__restrict__ pin,
                                                     S *__restrict__ q, const LS *__restrict__ U,
                                                     const int *__restrict__ nbr, int cg, Red rd) {
     using R = typename St<S>::R;
@@ -529,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
     double acc_pq = 0.0;
-    const SiteWalk wk = site_walk(L.lat);
+    const SiteWalk wk = site_walk(L.lat, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
         if (MODE == 1) stage_tile<LS, R, NC, LINKS>(su, snb, wk, item0, sites_per_tile, U, nbr);
@@ -581,13 +614,20 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
     }
     if (!cg) return;
     double acc[1] = {acc_pq};
-    block_partials<1>(acc, W, logW, rd, sm);
+    block_partials<1>(bk, acc, W, logW, rd, sm);
+}
+
+template <typename S, typename LS, int NC, bool LINKS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ pin,
+                                                    S *__restrict__ q, const LS *__restrict__ U,
+                                                    const int *__restrict__ nbr, int cg, Red rd) {
+    k_stencil_body<S, LS, NC, LINKS, MODE>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
 }
 
 // x += alpha p, r -= alpha q and |r|^2 per lane (second kernel of a CG
 // iteration).
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xlo, const S *__restrict__ p,
+__device__ __forceinline__ void k_update1_body(const Blk &bk, Launch L, S *__restrict__ xlo, const S *__restrict__ p,
                                                     S *__restrict__ r, const S *__restrict__ q, Red rd,
                                                     CgState cs) {
     using R = typename St<S>::R;
@@ -598,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xl
     const R alpha = (R)cs.alpha[j];
     double acc[1] = {0.0};
     int t0, t1;
-    tile_range(L.ntiles, t0, t1);
+    tile_range(bk, L.ntiles, t0, t1);
     // element e = ((site * nc + a) << logW) + j: lane j is tid & (W-1) for
     // every e = e0 + tid + k * kBlock since kBlock is a multiple of W
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
@@ -625,12 +665,19 @@ __global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xl
         }
     }
     acc[0] += (double)part;
-    block_partials<1>(acc, W, logW, rd, sm);
+    block_partials<1>(bk, acc, W, logW, rd, sm);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xlo, const S *__restrict__ p,
+                                                    S *__restrict__ r, const S *__restrict__ q, Red rd,
+                                                    CgState cs) {
+    k_update1_body<S>(own_blk(), L, xlo, p, r, q, rd, cs);
 }
 
 // p = r + beta p (third kernel of a CG iteration)
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restrict__ r, S *__restrict__ p,
+__device__ __forceinline__ void k_update2_body(const Blk &bk, Launch L, const S *__restrict__ r, S *__restrict__ p,
                                                     CgState cs) {
     using R = typename St<S>::R;
     const int tid = threadIdx.x, W = L.W;
@@ -638,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restric
     const int sites_per_tile = kBlock >> L.logW;
     const R beta = (R)cs.beta[j];
     int t0, t1;
-    tile_range(L.ntiles, t0, t1);
+    tile_range(bk, L.ntiles, t0, t1);
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
     const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
@@ -649,14 +696,20 @@ __global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restric
     }
 }
 
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restrict__ r, S *__restrict__ p,
+                                                    CgState cs) {
+    k_update2_body<S>(own_blk(), L, r, p, cs);
+}
+
 // x64 += xlo, xlo = 0 (mixed precision)
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
+__device__ __forceinline__ void k_fold_body(const Blk &bk, Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
     using R = typename St<S>::R;
     const int tid = threadIdx.x;
     const int sites_per_tile = kBlock >> L.logW;
     int t0, t1;
-    tile_range(L.ntiles, t0, t1);
+    tile_range(bk, L.ntiles, t0, t1);
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * L.W;
     const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * L.W;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
@@ -670,12 +723,17 @@ __global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__
     }
 }
 
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
+    k_fold_body<S>(own_blk(), L, x64, xlo);
+}
+
 // FP64 true residual r = b - A x_eff with FP64 links, x_eff = x64 (pend = 0)
 // or x64 + xlo + alpha p (pend = 1: the solution including the inner
 // iterate and the pending update, formed on the fly).  Stores r in the
 // storage precision and |r|^2 per lane.
 template <typename S, int NC, bool LINKS, int MODE>
-__global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
+__device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, double diag, const double2 *__restrict__ b64,
                                                        const double2 *__restrict__ x64, const S *__restrict__ xlo,
                                                        const S *__restrict__ p, int pend,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
@@ -690,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, co
     const int sites_per_tile = kBlock >> logW;
     const double alpha = pend ? cs.alpha[j] : 0.0;
     double acc[1] = {0.0};
-    const SiteWalk wk = site_walk(L.lat);
+    const SiteWalk wk = site_walk(L.lat, bk);
     auto xeff = [&](int y, double (&vr)[NC], double (&vi)[NC]) {
         ld_site<double2, NC>(x64, y, logW, j, vr, vi);
         if (pend) {
@@ -757,11 +815,20 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, co
             acc[0] += ar[a] * ar[a] + ai[a] * ai[a];
         }
     }
-    block_partials<1>(acc, W, logW, rd, sm);
+    block_partials<1>(bk, acc, W, logW, rd, sm);
+}
+
+template <typename S, int NC, bool LINKS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
+                                                       const double2 *__restrict__ x64, const S *__restrict__ xlo,
+                                                       const S *__restrict__ p, int pend,
+                                                       const double2 *__restrict__ U, const int *__restrict__ nbr,
+                                                       S *__restrict__ rout, Red rd, CgState cs) {
+    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, xlo, p, pend, U, nbr, rout, rd, cs);
 }
 
 // t_j = sum_x sum_b conj(v_j(x,b)) x_j(x + p e0, b), probes regenerated.
-__global__ __launch_bounds__(kBlock) void k_displaced_dot(Launch L, ProbeGen g, int p,
+__device__ __forceinline__ void k_displaced_dot_body(const Blk &bk, Launch L, ProbeGen g, int p,
                                                          const double2 *__restrict__ x64, Red rd, CgState cs) {
     __shared__ double sm[2 * kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
@@ -770,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_displaced_dot(Launch L, ProbeGen g, 
     const unsigned long long seedmix = mix64(g.seed);
     double acc[2] = {0.0, 0.0};
     int t0, t1;
-    tile_range(L.ntiles, t0, t1);
+    tile_range(bk, L.ntiles, t0, t1);
     if (j < g.nvalid) {
         const long long J = g.rhs0 + j;
         const int ndil = g.dilute ? nc : 1;
@@ -789,18 +856,23 @@ __global__ __launch_bounds__(kBlock) void k_displaced_dot(Launch L, ProbeGen g, 
             }
         }
     }
-    block_partials<2>(acc, W, logW, rd, sm);
+    block_partials<2>(bk, acc, W, logW, rd, sm);
+}
+
+__global__ __launch_bounds__(kBlock) void k_displaced_dot(Launch L, ProbeGen g, int p,
+                                                         const double2 *__restrict__ x64, Red rd, CgState cs) {
+    k_displaced_dot_body(own_blk(), L, g, p, x64, rd, cs);
 }
 
 // t_j = a_j^H b_j (FP64 vectors)
-__global__ __launch_bounds__(kBlock) void k_dot(Launch L, const double2 *__restrict__ a64,
+__device__ __forceinline__ void k_dot_body(const Blk &bk, Launch L, const double2 *__restrict__ a64,
                                                const double2 *__restrict__ b64, Red rd, CgState cs) {
     __shared__ double sm[2 * kBlock];
     const int tid = threadIdx.x, W = L.W;
     const int sites_per_tile = kBlock >> L.logW;
     double acc[2] = {0.0, 0.0};
     int t0, t1;
-    tile_range(L.ntiles, t0, t1);
+    tile_range(bk, L.ntiles, t0, t1);
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
     const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
@@ -808,7 +880,12 @@ __global__ __launch_bounds__(kBlock) void k_dot(Launch L, const double2 *__restr
         acc[0] += u.x * v.x + u.y * v.y;
         acc[1] += u.x * v.y - u.y * v.x;
     }
-    block_partials<2>(acc, W, L.logW, rd, sm);
+    block_partials<2>(bk, acc, W, L.logW, rd, sm);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(Launch L, const double2 *__restrict__ a64,
+                                               const double2 *__restrict__ b64, Red rd, CgState cs) {
+    k_dot_body(own_blk(), L, a64, b64, rd, cs);
 }
 
 // Adjoint force of one block of right-hand sides, one thread per output
@@ -911,6 +988,97 @@ __global__ void k_probes_abi(Lat lat, int nc, ProbeGen g, long long nrhs, double
     double re, im;
     probe_value(g, mix64(g.seed), lat, nc, g.rhs0 + jj, site, b, re, im);
     out[e] = make_double2(re, im);
+}
+
+// ============================================================ multi-instance launches
+//
+// One launch covers every slot (job) of a batch: workgroup w belongs to slot
+// slot_of[w] and runs the same body as a standalone launch on that slot's
+// lattice, with the slot's own buffers.  Slots whose flags do not include
+// the kernel's phase return at once.  The descriptors live in device memory
+// and are rewritten by the host between launches, so a captured graph of
+// these launches stays valid while finished slots are refilled.
+
+__device__ __forceinline__ const SlotDesc *slot_of_block(const BatchLaunch &B, Blk &bk, int phase) {
+    const int s = B.slot_of[blockIdx.x];
+    const SlotDesc *d = B.sd + s;
+    if (!(d->flags & phase)) return nullptr;
+    bk.b = (int)blockIdx.x - d->blk0;
+    bk.nb = d->L.nblk;
+    return d;
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_b_init(BatchLaunch B, int mixed) {
+    Blk bk;
+    const SlotDesc *d = slot_of_block(B, bk, kSlotInit);
+    if (!d) return;
+    k_init_body<S, 0>(bk, d->L, d->g, nullptr, 0, 0, (double2 *)d->b64, (S *)d->r, (S *)d->p, (S *)d->xlo,
+                      (double2 *)d->x64, mixed, d->rd, d->cs);
+}
+
+template <typename S, typename LS, int NC, bool LINKS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_b_stencil(BatchLaunch B) {
+    Blk bk;
+    const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
+    if (!d) return;
+    k_stencil_body<S, LS, NC, LINKS, MODE>(bk, d->L, (typename St<S>::R)d->diag, (const S *)d->p, (S *)d->q,
+                                           (const LS *)d->U, d->nbr, 1, d->rd);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_b_update1(BatchLaunch B) {
+    Blk bk;
+    const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
+    if (!d) return;
+    k_update1_body<S>(bk, d->L, (S *)d->xlo, (const S *)d->p, (S *)d->r, (const S *)d->q, d->rd, d->cs);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_b_update2(BatchLaunch B) {
+    Blk bk;
+    const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
+    if (!d) return;
+    k_update2_body<S>(bk, d->L, (const S *)d->r, (S *)d->p, d->cs);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_b_fold(BatchLaunch B, int phase) {
+    Blk bk;
+    const SlotDesc *d = slot_of_block(B, bk, phase);
+    if (!d) return;
+    k_fold_body<S>(bk, d->L, d->x64 ? (double2 *)d->x64 : nullptr, (S *)d->xlo);
+}
+
+template <typename S, int NC, bool LINKS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_b_true_resid(BatchLaunch B, int phase) {
+    Blk bk;
+    const SlotDesc *d = slot_of_block(B, bk, phase);
+    if (!d) return;
+    k_true_resid_body<S, NC, LINKS, MODE>(bk, d->L, d->diag, (const double2 *)d->b64, (const double2 *)d->x64,
+                                          nullptr, nullptr, 0, (const double2 *)d->U64, d->nbr, (S *)d->r,
+                                          d->rd, d->cs);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_dot(BatchLaunch B) {
+    Blk bk;
+    const SlotDesc *d = slot_of_block(B, bk, kSlotFinal);
+    if (!d) return;
+    k_displaced_dot_body(bk, d->L, d->g, d->disp, (const double2 *)d->x64, d->rd, d->cs);
+}
+
+// one workgroup per (slot, lane)
+template <int NV, int EPI>
+__global__ __launch_bounds__(kBlock) void k_b_finish(BatchLaunch B, int phase) {
+    const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
+    const SlotDesc *d = B.sd + s;
+    if (!(d->flags & phase)) return;
+    k_finish_body<NV, EPI>(lane, d->rd, d->cs);
+}
+
+__global__ void k_b_ctrl(BatchLaunch B) {
+    const SlotDesc *d = B.sd + blockIdx.x;
+    k_ctrl_body(d->cs, B.W);
 }
 
 // ============================================================ launchers
@@ -1107,5 +1275,74 @@ void launch_make_probes_abi(const Lat &lat, int nc, const ProbeGen &g, long long
     const long long n = nrhs * lat.N * nc;
     k_probes_abi<<<blocks_for(n), kBlock, 0, s>>>(lat, nc, g, nrhs, (double2 *)out);
 }
+
+// ------------------------------------------------------------ multi-instance launchers
+
+void launch_b_init(const BatchLaunch &B, int mixed) {
+    DP_DISPATCH_PREC(B.prec, S, k_b_init<S><<<B.nblocks, kBlock, 0, B.stream>>>(B, mixed));
+    k_b_finish<1, kEpiInit><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotInit);
+}
+
+template <typename S, typename LS, int NC, bool LINKS>
+static void b_stencil_t(const BatchLaunch &B) {
+    if (B.mode == 2)
+        k_b_stencil<S, LS, NC, LINKS, 2><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+    else if (B.mode == 1)
+        k_b_stencil<S, LS, NC, LINKS, 1><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+    else
+        k_b_stencil<S, LS, NC, LINKS, 0><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+}
+
+template <typename S>
+static void b_stencil(const BatchLaunch &B) {
+    if (B.nc == 3)
+        B.links ? b_stencil_t<S, S, 3, true>(B) : b_stencil_t<S, S, 3, false>(B);
+    else
+        B.links ? b_stencil_t<S, S, 1, true>(B) : b_stencil_t<S, S, 1, false>(B);
+}
+
+void launch_b_iteration(const BatchLaunch &B, bool update2) {
+    DP_DISPATCH_PREC(B.prec, S, {
+        if (update2) k_b_update2<S><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+        b_stencil<S>(B);
+        k_b_finish<1, kEpiAlpha><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
+        k_b_update1<S><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+        k_b_finish<1, kEpiBeta><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
+    });
+}
+
+template <typename S, int NC, bool LINKS>
+static void b_tr_t(const BatchLaunch &B, int phase) {
+    if (B.mode == 2)
+        k_b_true_resid<S, NC, LINKS, 2><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+    else if (B.mode == 1)
+        k_b_true_resid<S, NC, LINKS, 1><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+    else
+        k_b_true_resid<S, NC, LINKS, 0><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+}
+
+// Reliable update (final_stats = 0: slots flagged kSlotRU) or the final
+// fold and statistics (final_stats = 1: slots flagged kSlotFinal).
+void launch_b_ru(const BatchLaunch &B, int final_stats) {
+    const int phase = final_stats ? kSlotFinal : kSlotRU;
+    DP_DISPATCH_PREC(B.prec, S, {
+        if (B.prec != kF64) k_b_fold<S><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+        if (B.nc == 3)
+            B.links ? b_tr_t<S, 3, true>(B, phase) : b_tr_t<S, 3, false>(B, phase);
+        else
+            B.links ? b_tr_t<S, 1, true>(B, phase) : b_tr_t<S, 1, false>(B, phase);
+    });
+    if (final_stats)
+        k_b_finish<1, kEpiStats><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, phase);
+    else
+        k_b_finish<1, kEpiRU><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, phase);
+}
+
+void launch_b_dot(const BatchLaunch &B) {
+    k_b_dot<<<B.nblocks, kBlock, 0, B.stream>>>(B);
+    k_b_finish<2, kEpiTj><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotFinal);
+}
+
+void launch_b_ctrl(const BatchLaunch &B) { k_b_ctrl<<<B.nslots, 64, 0, B.stream>>>(B); }
 
 }  // namespace dp

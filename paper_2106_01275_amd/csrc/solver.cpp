@@ -252,7 +252,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     // from the decay of the slowest lane's residual since the last check.
     int steps_next = std::max(1, ctx->check_every);
     double ratio_prev = -1.0;
-    int it_prev = 0;
+    int it_prev = 0, it_ru = 0;
     while (nactive > 0 && it < cfg.max_iter) {
         const int steps = std::min(steps_next, cfg.max_iter - it);
         if (cfg.use_graph && pending && !cfg.profile) {
@@ -299,7 +299,9 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             it_prev = it;
         }
         if (mixed && nactive > 0 &&
-            (ctx->ctrl_host[2] > 0 || ctx->ctrl_host[1] == nactive || it >= cfg.max_iter)) {
+            (ctx->ctrl_host[2] > 0 || ctx->ctrl_host[1] == nactive || it >= cfg.max_iter ||
+             it - it_ru >= cfg.ru_gap)) {
+            it_ru = it;
             // reliable update: x64 += xlo, r = b - A x64 in FP64, beta from it
             launch_fold(L, cfg.inner, x64, xlo);
             launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, nullptr, nullptr, 0, op.U64, op.nbr, r, 1,

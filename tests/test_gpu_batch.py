@@ -1,0 +1,133 @@
+"""The multi-instance path (dp_trace_estimate / dp_solve_batch with several
+instances): every CG kernel is one launch over all resident jobs.  Each
+instance is compared with the oracle run on that instance alone."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2106_01275_amd as dp  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return dp.context(0)
+
+
+# small uneven instances: (dims, m2, eps, p, k, seed)
+SMALL = [((4, 4, 4, 4), 0.3, 0.3, 1, 2, 101), ((6, 4, 4, 6), 0.1, 0.4, 2, 2, 102),
+         ((4, 6, 4, 4), 0.45, 0.2, 1, 1, 103), ((6, 6, 4, 6), 0.2, 0.5, 3, 2, 104),
+         ((4, 4, 6, 4), 0.05, 0.3, 2, 3, 105), ((8, 4, 4, 4), 0.25, 0.35, 1, 2, 106)]
+
+
+def _instances(ctx, inst, nsamples=1, noise="z2_complex"):
+    ops, pss, ps_, Us, cols = [], [], [], [], []
+    for i, (dims, m2, eps, p, k, seed) in enumerate(inst):
+        U = workloads.random_links(dims, eps, seed)
+        col, n, _ = oracle.coloring(dims, p, k, oracle.NATURAL)
+        colg = torch.from_numpy(col).cuda()
+        ops.append(ctx.operator(dims, 3, m2, torch.from_numpy(U).cuda()))
+        pss.append(ctx.probe_spec(dims, 3, colg, n, i, 0, nsamples, noise, True))
+        ps_.append(p)
+        Us.append(U)
+        cols.append((col, n, colg))
+    return ops, pss, ps_, Us, cols
+
+
+@pytest.mark.parametrize("inner,block,tol,rtol", [("f64", 16, 1e-12, 1e-10), ("f32", 32, 1e-10, 1e-6),
+                                                  ("bf16", 32, 1e-10, 1e-6), ("f64", 8, 1e-12, 1e-10)])
+def test_batched_trace_matches_oracle(ctx, inner, block, tol, rtol):
+    _say("batched trace", inner, block)
+    ops, pss, ps_, Us, cols = _instances(ctx, SMALL)
+    res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=tol, inner=inner, rhs_block=block,
+                                                     reliable_delta=1e-2))
+    for i, (dims, m2, eps, p, k, seed) in enumerate(SMALL):
+        col, n, _ = cols[i]
+        o = oracle.trace(dims, 3, m2, Us[i], p, col, n, i, 0, 1, oracle.Z2_COMPLEX, True, tol=1e-13)
+        assert abs(res[i]["T"] - o["T"]) < rtol * abs(o["T"]), (i, res[i]["T"], o["T"])
+        assert np.abs(res[i]["tj"] - o["tj"]).max() < rtol * np.abs(o["tj"]).max()
+        assert res[i]["solve"]["nconverged"] == res[i]["solve"]["nrhs"] == n * 3
+        assert res[i]["solve"]["max_true_resid"] <= tol * (1 if inner != "f64" else 10)
+
+
+def test_batched_equals_single_instance(ctx):
+    """The batch engine and the single-instance path run the same kernels on
+    the same data: FP64 contractions agree to rounding."""
+    ops, pss, ps_, Us, cols = _instances(ctx, SMALL[:3])
+    o = ctx.opts(tol=1e-12, rhs_block=16)
+    batch = ctx.trace_estimate(ops, pss, ps_, o)
+    for i in range(3):
+        one = ctx.trace_estimate([ops[i]], [pss[i]], [ps_[i]], o)[0]
+        assert np.abs(batch[i]["tj"] - one["tj"]).max() < 1e-12 * np.abs(one["tj"]).max()
+
+
+def test_batched_graph_replay_matches_eager(ctx):
+    ops, pss, ps_, Us, cols = _instances(ctx, SMALL)
+    e = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-9, inner="f32", rhs_block=32))
+    for rep in range(2):
+        g = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-9, inner="f32", rhs_block=32, use_graph=1))
+        for i in range(len(SMALL)):
+            assert np.array_equal(g[i]["tj"], e[i]["tj"]), (rep, i)
+
+
+def test_batched_solve_matches_oracle(ctx):
+    _say("batched solve")
+    inst = SMALL[:4]
+    ops, bs, Bs, Us = [], [], [], []
+    rng = np.random.default_rng(5)
+    for i, (dims, m2, eps, p, k, seed) in enumerate(inst):
+        N = int(np.prod(dims))
+        U = workloads.random_links(dims, eps, seed)
+        nr = [3, 17, 40, 1][i]
+        B = rng.standard_normal((nr, N, 3)) + 1j * rng.standard_normal((nr, N, 3))
+        ops.append(ctx.operator(dims, 3, m2, torch.from_numpy(U).cuda()))
+        bs.append(torch.from_numpy(B).cuda())
+        Bs.append(B)
+        Us.append(U)
+    xs, stats = ctx.solve_batch(ops, bs, ctx.opts(tol=1e-11, inner="f32", rhs_block=16, reliable_delta=1e-2))
+    for i, (dims, m2, eps, p, k, seed) in enumerate(inst):
+        Xo, it, rel = oracle.cg_many(dims, 3, m2, Us[i], Bs[i], tol=1e-13)
+        X = xs[i].cpu().numpy()
+        assert stats[i]["nconverged"] == Bs[i].shape[0]
+        assert np.abs(X - Xo).max() < 1e-9 * np.abs(Xo).max()
+
+
+def test_uneven_batch_workload_64(ctx):
+    """The 64-instance uneven batch (extents from {4,6,8,10,12}^4, BF16
+    storage, FP64 refinement, distance-4 colourings): every instance
+    converges to tol 1e-8 in FP64 true residual; three sampled instances are
+    recomputed by the oracle."""
+    _say("uneven batch 64")
+    batch = workloads.uneven_batch()
+    ops, pss, ps_, Us, cols = [], [], [], [], []
+    for i, w in enumerate(batch):
+        col, n, _ = dp.build_coloring(w.dims, w.p, 4, "best")
+        colg = torch.from_numpy(col).cuda()
+        U = w.links()
+        ops.append(ctx.operator(w.dims, 3, w.m2, torch.from_numpy(U).cuda()))
+        pss.append(ctx.probe_spec(w.dims, 3, colg, n, i, 0, 1, "z2_complex", True))
+        ps_.append(w.p)
+        Us.append(U)
+        cols.append((col, n))
+    res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-8, inner="bf16", rhs_block=32, reliable_delta=0.1))
+    for r in res:
+        assert r["solve"]["nconverged"] == r["solve"]["nrhs"] and r["solve"]["max_true_resid"] <= 1e-8
+    order = np.argsort([w.volume for w in batch])
+    for i in (order[0], order[len(order) // 2], order[-1]):
+        w = batch[i]
+        col, n = cols[i]
+        o = oracle.trace(w.dims, 3, w.m2, Us[i], w.p, col, n, i, 0, 1, oracle.Z2_COMPLEX, True, tol=1e-11)
+        assert abs(res[i]["T"] - o["T"]) < 1e-5 * abs(o["T"]), (i, res[i]["T"], o["T"])
