@@ -253,13 +253,17 @@ dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, con
             in[i].xabi = (double *)x[i];
             maxr = std::max<long long>(maxr, nrhs[i]);
         }
-        int W = o->rhs_block;
-        if (W <= 0) {
-            W = 1;
-            while (W < maxr && W < 32) W *= 2;
-        } else if (W > kMaxW || (W & (W - 1))) {
-            ctx->err = "rhs_block must be a power of two <= 256";
-            return DP_EINVAL;
+        int W = 1;
+        {
+            // the width is tuned on the largest instance
+            int imax = 0;
+            for (int i = 1; i < ninst; ++i)
+                if ((long long)ops[i].dims[0] * ops[i].dims[1] * ops[i].dims[2] * ops[i].dims[3] >
+                    (long long)ops[imax].dims[0] * ops[imax].dims[1] * ops[imax].dims[2] * ops[imax].dims[3])
+                    imax = i;
+            OpPrep opm;
+            DP_TRY(prepare_operator(ctx, ops[imax], cfg.inner, opm, stream));
+            DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W));
         }
         DP_TRY(run_batch(ctx, in, cfg, W, false, stream));
         for (int i = 0; i < ninst; ++i) {
@@ -415,13 +419,17 @@ dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, 
             in[i].tj.assign(2 * in[i].nrhs, 0.0);
             maxr = std::max<long long>(maxr, in[i].nrhs);
         }
-        int W = o->rhs_block;
-        if (W <= 0) {
-            W = 1;
-            while (W < maxr && W < 32) W *= 2;
-        } else if (W > kMaxW || (W & (W - 1))) {
-            ctx->err = "rhs_block must be a power of two <= 256";
-            return DP_EINVAL;
+        int W = 1;
+        {
+            // the width is tuned on the largest instance
+            int imax = 0;
+            for (int i = 1; i < ninst; ++i)
+                if ((long long)ops[i].dims[0] * ops[i].dims[1] * ops[i].dims[2] * ops[i].dims[3] >
+                    (long long)ops[imax].dims[0] * ops[imax].dims[1] * ops[imax].dims[2] * ops[imax].dims[3])
+                    imax = i;
+            OpPrep opm;
+            DP_TRY(prepare_operator(ctx, ops[imax], cfg.inner, opm, stream));
+            DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W));
         }
         DP_TRY(run_batch(ctx, in, cfg, W, true, stream));
         for (int i = 0; i < ninst; ++i) {

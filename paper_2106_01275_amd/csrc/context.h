@@ -60,7 +60,8 @@ struct dp_ctx {
     double *state_host = nullptr;    // pinned staging of per-lane results
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-    std::map<std::string, int> tuned_w;
+    std::map<std::string, int> tuned_w;       // autotuned block widths
+    bool tune_loaded = false;
     int check_every = 8;
     hipStream_t gstream = nullptr;            // library stream for graph capture
     hipEvent_t ev_in = nullptr, ev_out = nullptr;

@@ -21,7 +21,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "context.h"
 
@@ -346,9 +349,105 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     return DP_OK;
 }
 
+// Autotuner of the right-hand-side block width W: for each candidate W
+// (powers of two from 8 to 128, not above the next power of two of nrhs,
+// within a memory budget) a block of dense random right-hand sides runs
+// 2 + 6 CG iterations of the real kernels; the 6 are timed with HIP events
+// and the cost per useful right-hand side and iteration,
+// time / min(W, nrhs), decides.  Results are cached per (N, nc, precision,
+// links, next power of two of nrhs) in the context, and in the JSON file
+// named by DP_TUNE_CACHE when that variable is set.
+static std::string tune_key(const OpPrep &op, const SolveCfg &cfg, long long nrhs) {
+    long long b = 1;
+    while (b < nrhs && b < kMaxW) b *= 2;
+    char k[160];
+    std::snprintf(k, sizeof k, "gfx950 N=%d dims=%dx%dx%dx%d nc=%d prec=%d links=%d rhs=%lld", op.lat.N,
+                  op.lat.D[0], op.lat.D[1], op.lat.D[2], op.lat.D[3], op.nc, cfg.inner, op.links ? 1 : 0, b);
+    return k;
+}
+
+static void load_tune_file(dp_ctx *ctx) {
+    const char *path = std::getenv("DP_TUNE_CACHE");
+    if (!path || ctx->tune_loaded) return;
+    ctx->tune_loaded = true;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        // lines of the form   "<key>": <W>,
+        char *a = std::strchr(line, '"');
+        char *b = a ? std::strchr(a + 1, '"') : nullptr;
+        char *c = b ? std::strchr(b, ':') : nullptr;
+        if (!c) continue;
+        ctx->tuned_w[std::string(a + 1, b)] = std::atoi(c + 1);
+    }
+    std::fclose(f);
+}
+
+static void save_tune_file(dp_ctx *ctx) {
+    const char *path = std::getenv("DP_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto &kv : ctx->tuned_w)
+        std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < ctx->tuned_w.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+}
+
+static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, int W, hipStream_t s,
+                            float &ms) {
+    Launch L;
+    Red rd;
+    CgState cs;
+    DP_TRY(make_launch(ctx, op, W, s, L, rd, cs, cfg));
+    DP_TRY(ctx->ensure(kSlotColors, (size_t)op.lat.N * sizeof(int), true));
+    ProbeGen g{};
+    g.colors = (const int *)ctx->at(kSlotColors);  // one colour: dense noise
+    g.seed = 12345;
+    g.ncolors = 1;
+    g.noise = DP_NOISE_Z2_COMPLEX;
+    g.rhs0 = 0;
+    g.nvalid = W;
+    const bool mixed = cfg.inner != kF64;
+    void *xlo = mixed ? ctx->at(kSlotXLo) : ctx->at(kSlotX64);
+    launch_init_probe(L, cfg.inner, g, (double *)ctx->at(kSlotB64), ctx->at(kSlotR), ctx->at(kSlotP), xlo,
+                      (double *)ctx->at(kSlotX64), mixed ? 1 : 0, rd, cs);
+    StencilArgs a;
+    a.links = op.links;
+    a.diag = op.m2 + 8.0;
+    a.pin = ctx->at(kSlotP);
+    a.q = ctx->at(kSlotQ);
+    a.U = op.ULo;
+    a.nbr = op.nbr;
+    a.cg = 1;
+    a.rd = rd;
+    a.cs = cs;
+    auto iter = [&]() {
+        launch_update2(L, cfg.inner, ctx->at(kSlotR), ctx->at(kSlotP), cs);
+        launch_stencil(L, cfg.inner, a);
+        launch_update1(L, cfg.inner, xlo, ctx->at(kSlotP), ctx->at(kSlotR), ctx->at(kSlotQ), rd, cs);
+    };
+    iter();
+    iter();
+    hipEvent_t e0, e1;
+    DP_HIP(hipEventCreate(&e0));
+    DP_HIP(hipEventCreate(&e1));
+    DP_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < 6; ++i) iter();
+    DP_HIP(hipEventRecord(e1, s));
+    DP_HIP(hipEventSynchronize(e1));
+    DP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    DP_HIP(hipGetLastError());
+    return DP_OK;
+}
+
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
                        hipStream_t s, int &W) {
-    (void)s;
     if (requested > 0) {
         if (requested > kMaxW || (requested & (requested - 1))) {
             ctx->err = "rhs_block must be a power of two <= 256";
@@ -357,12 +456,34 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
         W = requested;
         return DP_OK;
     }
-    // default: the smallest power of two covering nrhs, capped at 64
-    int w = 1;
-    while (w < nrhs && w < 64) w *= 2;
-    (void)op;
-    (void)cfg;
-    W = w;
+    if (nrhs <= 1) {
+        W = 1;
+        return DP_OK;
+    }
+    load_tune_file(ctx);
+    const std::string key = tune_key(op, cfg, nrhs);
+    auto it = ctx->tuned_w.find(key);
+    if (it != ctx->tuned_w.end()) {
+        W = it->second;
+        return DP_OK;
+    }
+    const size_t bytes_per_w = (size_t)op.lat.N * op.nc * (2 * 16 + 4 * (cfg.inner == kF64 ? 16 : 8));
+    double best = 1e300;
+    int best_w = 1;
+    for (int w = 8; w <= 128; w *= 2) {
+        if (w > 8 && w / 2 >= nrhs) break;
+        if (bytes_per_w * w > ((size_t)32 << 30)) break;
+        float ms = 0;
+        DP_TRY(time_width(ctx, op, cfg, w, s, ms));
+        const double cost = ms / (double)std::min<long long>(w, nrhs);
+        if (cost < best) {
+            best = cost;
+            best_w = w;
+        }
+    }
+    W = best_w;
+    ctx->tuned_w[key] = W;
+    save_tune_file(ctx);
     return DP_OK;
 }
 

@@ -335,3 +335,30 @@ def test_graph_replay_matches_eager(ctx):
         (Xe,), _ = ctx.solve_batch([op], [B], o_e)
         (Xg,), _ = ctx.solve_batch([op], [B], o_g)
         assert torch.equal(Xe, Xg)
+
+
+# ------------------------------------------------------------------ autotuner
+
+
+def test_autotuned_width(ctx, tmp_path, monkeypatch):
+    """rhs_block = 0 times candidate widths on the real kernels, caches the
+    choice (also in the DP_TUNE_CACHE file) and gives the same estimate as an
+    explicit run at the chosen width."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("DP_TUNE_CACHE", str(cache))
+    dims, nc = (8, 8, 8, 8), 3
+    U = workloads.random_links(dims, 0.3, 1)
+    col, n, colg, ps = _probe_setup(ctx, dims, nc, 2, 4, "best", 0, 0, 1, "z2_complex", True)
+    op = ctx.operator(dims, nc, 0.1, cuda(U))
+    c2 = dp.Context(0)  # fresh context: empty tuning cache
+    r = c2.trace_estimate([op], [ps], [2], c2.opts(tol=1e-10, inner="f32", rhs_block=0))[0]
+    W = r["solve"]["rhs_block"]
+    assert W in (8, 16, 32, 64, 128)
+    assert str(W) in cache.read_text()
+    r2 = c2.trace_estimate([op], [ps], [2], c2.opts(tol=1e-10, inner="f32", rhs_block=W))[0]
+    assert np.array_equal(r["tj"], r2["tj"])
+    c3 = dp.Context(0)  # a new context reads the cache file
+    r3 = c3.trace_estimate([op], [ps], [2], c3.opts(tol=1e-10, inner="f32", rhs_block=0))[0]
+    assert r3["solve"]["rhs_block"] == W
+    c2.close()
+    c3.close()
