@@ -140,7 +140,11 @@ typedef struct {
                                FP64 reliable updates */
     int32_t rhs_block;      /* right-hand sides solved together (W); 0 = autotune */
     double reliable_delta;  /* mixed precision: replace the residual by the FP64
-                               true residual once it dropped by this factor (0: 0.1) */
+                               true residual once it dropped by this factor; a lane
+                               that reaches it waits for that update before it moves
+                               on (0: 0.1 for BF16, 1e-3 for F32).  BF16 storage
+                               resolves about 3 digits: values well below 0.1 stall
+                               it */
     int32_t use_graph;      /* 1: replay the iteration loop from a captured hipGraph */
     int32_t profile;        /* 1: time the stencil kernel launches with HIP events */
 } dp_solve_opts;
@@ -156,6 +160,13 @@ typedef struct {
     int32_t rhs_block;       /* W used */
     int32_t stencil_launches;/* profile = 1: stencil kernel launches timed */
     double stencil_ms;       /* profile = 1: summed duration of those launches */
+    double stencil_bytes;    /* profile = 1: their algorithmic bytes, per lattice site of a
+                                launch 2*W*V + 4*L (read p and write q for the W right-hand
+                                sides, read each of the 4 links once), V = bytes of one site
+                                vector, L = bytes of one link matrix (0 without links).
+                                A multi-instance launch (solve_batch / trace_estimate with
+                                ninst > 1) covers every instance: its totals are reported
+                                in the stats of instance 0 only */
     double seconds;          /* wall time of the call */
 } dp_solve_stats;
 

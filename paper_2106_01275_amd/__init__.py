@@ -61,7 +61,8 @@ class SolveStats(ctypes.Structure):
                 ("nconverged", ctypes.c_int32), ("nbreakdown", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("max_true_resid", ctypes.c_double),
                 ("rhs_block", ctypes.c_int32), ("stencil_launches", ctypes.c_int32),
-                ("stencil_ms", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("stencil_ms", ctypes.c_double), ("stencil_bytes", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -200,7 +201,7 @@ class Context:
         return ps
 
     @staticmethod
-    def opts(tol=1e-10, max_iter=0, inner="f64", rhs_block=0, reliable_delta=0.1, use_graph=0, profile=0):
+    def opts(tol=1e-10, max_iter=0, inner="f64", rhs_block=0, reliable_delta=0.0, use_graph=0, profile=0):
         o = SolveOpts()
         o.tol = tol
         o.max_iter = max_iter

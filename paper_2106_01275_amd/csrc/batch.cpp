@@ -137,6 +137,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         cs.ctrld = (double *)(ctrl_all + 16 * k + 8);
         cs.tol2 = cfg.tol * cfg.tol;
         cs.delta2 = cfg.delta * cfg.delta;
+        cs.hold = cfg.inner == kBF16;
         cs.exact = !mixed;
         d.blk0 = k * nblk;
     }
@@ -222,6 +223,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         launch_b_ctrl(B);
         DP_HIP(hipMemcpyAsync(hctrl.data(), ctrl_all, sizeof(int) * 16 * nslots, hipMemcpyDeviceToHost, s));
         DP_HIP(hipStreamSynchronize(s));
+        if (cfg.profile) DP_TRY(finish_profile(ctx, &in[0].st));
         return DP_OK;
     };
     // contract / copy out the slots flagged kSlotFinal and record statistics
@@ -294,7 +296,14 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             DP_HIP(hipGraphLaunch(g->second, s));
         } else {
             // update2 on a freshly initialised slot is harmless: beta = 0 and p = r = b
-            for (int c = 0; c < steps; ++c) launch_b_iteration(B, true);
+            double bytes = 0;
+            for (int k = 0; k < nslots; ++k)
+                if (hsd[k].flags & kSlotIter) bytes += stencil_alg_bytes(hsd[k].L.lat, nc, W, cfg.inner, B.links);
+            for (int c = 0; c < steps; ++c) {
+                launch_b_update2(B);
+                DP_TRY(timed_launch(ctx, cfg.profile != 0, s, bytes, [&] { launch_b_stencil(B); }));
+                launch_b_update1(B);
+            }
         }
         DP_HIP(hipGetLastError());
         for (int k = 0; k < nslots; ++k)
@@ -306,8 +315,9 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             SlotDesc &d = hsd[k];
             if (!(d.flags & kSlotIter)) continue;
             const int *c = hctrl.data() + 16 * k;
-            double ratio;
+            double ratio, ru_ratio;
             std::memcpy(&ratio, c + 8, sizeof(double));
+            std::memcpy(&ru_ratio, c + 10, sizeof(double));
             const int nactive = c[0];
             if (nactive == 0) {
                 d.flags = kSlotFinal;
@@ -324,12 +334,8 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
                 any_fin = true;
                 continue;
             }
-            int nx = std::max(1, ctx->check_every);
-            if (ratio_prev[k] > 0 && ratio > 1.0 && ratio < ratio_prev[k] && slot_it[k] > it_prev[k]) {
-                const double per_it = std::log(ratio_prev[k] / ratio) / (slot_it[k] - it_prev[k]);
-                nx = (int)std::ceil(std::log(ratio) / per_it);
-            }
-            next_steps = std::min(next_steps, std::max(2, nx));
+            next_steps = std::min(next_steps, next_check(std::max(1, ctx->check_every), ratio, ratio_prev[k],
+                                                         slot_it[k] - it_prev[k], cfg.inner == kBF16 ? ru_ratio : 0.0));
             ratio_prev[k] = ratio;
             it_prev[k] = slot_it[k];
         }
@@ -368,6 +374,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         }
     }
     DP_HIP(hipStreamSynchronize(s));
+    if (cfg.profile) DP_TRY(finish_profile(ctx, &in[0].st));
     ctx->drop_graphs();
     return DP_OK;
 }

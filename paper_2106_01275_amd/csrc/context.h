@@ -56,10 +56,11 @@ struct dp_ctx {
     std::string err;
     void *slot[dp::kNumSlots] = {};
     size_t slot_bytes[dp::kNumSlots] = {};
-    int *ctrl_host = nullptr;        // pinned [8]
+    int *ctrl_host = nullptr;        // pinned [16]: 4 counts, then 2 doubles at [4] and [6]
     double *state_host = nullptr;    // pinned staging of per-lane results
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    double ev_bytes = 0;                      // algorithmic bytes of the pending timed launches
     std::map<std::string, int> tuned_w;       // autotuned block widths
     bool tune_loaded = false;
     int check_every = 8;
@@ -97,6 +98,38 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
                        hipStream_t s, int &W);
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
+// runs `launch`; when profiling, between two events on stream s whose pair (and the
+// launch's algorithmic bytes) finish_profile() later adds to the stats
+template <typename F>
+dp_status timed_launch(dp_ctx *ctx, bool profile, hipStream_t s, double bytes, F launch) {
+    if (!profile) {
+        launch();
+        return DP_OK;
+    }
+    if (ctx->ev_pool.size() < 2) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            DP_HIP(hipEventCreate(&e));
+            ctx->ev_pool.push_back(e);
+        }
+    }
+    hipEvent_t e0 = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    hipEvent_t e1 = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    DP_HIP(hipEventRecord(e0, s));
+    launch();
+    DP_HIP(hipEventRecord(e1, s));
+    ctx->ev_pending.emplace_back(e0, e1);
+    ctx->ev_bytes += bytes;
+    return DP_OK;
+}
+double stencil_alg_bytes(const Lat &lat, int nc, int W, int prec, bool links);
+// Iterations until the next host check (2..16): what the slowest lane needs
+// to reach tol and, with ru_ratio > 1 (mixed precision), what the first lane
+// needs to be due a reliable update, both from the slowest lane's decay of
+// |r|^2 over the last dit iterations (ratio_prev -> ratio); dflt without one.
+int next_check(int dflt, double ratio, double ratio_prev, int dit, double ru_ratio);
 
 // Work stream of a call: the caller's stream, or (graph replay requested)
 // the library's own stream, ordered after the caller's stream on entry and

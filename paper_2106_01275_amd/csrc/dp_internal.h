@@ -35,11 +35,17 @@ struct CgState {
     double *ctrld;       // [0] max over active lanes of |r|^2 / (tol^2 |b|^2)
     double tol2, delta2;
     int exact;           // 1: FP64 inner solve (no reliable updates)
+    int hold;            // 1: lanes due a reliable update wait for it (BF16 storage)
 };
 
 // kFlagRestart (mixed precision): p^H A p <= 0 in low precision; the next
 // reliable update restarts the search direction from the true residual.
-enum { kFlagBreakdown = 1, kFlagConverged = 2, kFlagRestart = 4 };
+// kFlagHold (BF16 storage): the lane is due a reliable update (its residual
+// fell by the factor delta, or it must restart); it does not move (alpha = 0,
+// p kept, iteration count unchanged) until the update is done, so it never
+// iterates past what the low precision resolves.  (FP32 lanes go on: a few
+// iterations beyond delta cost them nothing.)
+enum { kFlagBreakdown = 1, kFlagConverged = 2, kFlagRestart = 4, kFlagHold = 8 };
 
 // Geometry of a lattice on the device.
 struct Lat {
@@ -97,6 +103,9 @@ struct BatchLaunch {
 };
 void launch_b_init(const BatchLaunch &B, int mixed);
 void launch_b_iteration(const BatchLaunch &B, bool update2);
+void launch_b_update2(const BatchLaunch &B);
+void launch_b_stencil(const BatchLaunch &B);
+void launch_b_update1(const BatchLaunch &B);  // with the alpha and beta epilogues
 void launch_b_ru(const BatchLaunch &B, int final_stats);
 void launch_b_dot(const BatchLaunch &B);
 void launch_b_ctrl(const BatchLaunch &B);

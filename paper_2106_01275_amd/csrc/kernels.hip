@@ -283,14 +283,14 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
         cs.active[j] = t > 0.0;
         cs.flags[j] = t > 0.0 ? 0 : kFlagConverged;
     } else if (EPI == kEpiAlpha) {
-        if (cs.active[j]) {
+        if (cs.active[j] && !(cs.flags[j] & kFlagHold)) {
             if (!(t > 0.0) || !isfinite(t)) {
                 cs.alpha[j] = 0.0;
                 if (cs.exact) {
                     cs.flags[j] |= kFlagBreakdown;
                     cs.active[j] = 0;
                 } else {
-                    cs.flags[j] |= kFlagRestart;
+                    cs.flags[j] |= kFlagRestart | (cs.hold ? kFlagHold : 0);
                 }
             } else {
                 cs.alpha[j] = cs.rr[j] / t;
@@ -299,16 +299,20 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
             cs.alpha[j] = 0.0;
         }
     } else if (EPI == kEpiBeta) {
-        if (cs.active[j]) {
+        if (cs.active[j] && !(cs.flags[j] & kFlagHold)) {
             cs.iters[j] += 1;
             cs.rr_prev[j] = cs.rr[j];
             cs.beta[j] = t / cs.rr[j];
             cs.rr[j] = t;
-            if (cs.exact && t <= cs.tol2 * cs.bb[j]) {
-                cs.active[j] = 0;
-                cs.flags[j] |= kFlagConverged;
+            if (cs.exact) {
+                if (t <= cs.tol2 * cs.bb[j]) {
+                    cs.active[j] = 0;
+                    cs.flags[j] |= kFlagConverged;
+                }
+            } else if (cs.hold && !(t >= cs.delta2 * cs.rr_ref[j])) {
+                cs.flags[j] |= kFlagHold;  // due a reliable update (or not finite)
             }
-        } else {
+        } else if (!cs.active[j]) {
             cs.beta[j] = 0.0;
         }
     } else if (EPI == kEpiRU || EPI == kEpiStats) {
@@ -318,7 +322,7 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
             // breakdown or when the true residual grew since the last update
             const bool restart = (cs.flags[j] & kFlagRestart) || !(t <= cs.rr_ref[j]);
             cs.beta[j] = restart ? 0.0 : t / cs.rr_prev[j];
-            cs.flags[j] &= ~kFlagRestart;
+            cs.flags[j] &= ~(kFlagRestart | kFlagHold);
             cs.rr[j] = t;
             cs.rr_ref[j] = t;
             if (t <= cs.tol2 * cs.bb[j]) {
@@ -340,20 +344,29 @@ __global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
 // Control word for the host: [0] active lanes, [1] active lanes whose
 // recursive residual meets tol, [2] active lanes due a reliable update,
 // [3] lanes that broke down; ctrld[0] the largest |r|^2 / (tol^2 |b|^2) of
-// an active lane (how far the slowest one still is from convergence).
+// an active lane (how far the slowest one still is from convergence);
+// ctrld[1] (mixed precision) the smallest |r|^2 / (delta^2 |r_ref|^2) of an
+// active lane not yet due a reliable update (how close the next one is;
+// 0 if there is none).
 __device__ __forceinline__ void k_ctrl_body(const CgState &cs, int W) {
     __shared__ int cnt[4][64];
-    __shared__ double worst[64];
+    __shared__ double worst[64], first[64];
     const int t = threadIdx.x;
     int na = 0, nk = 0, nru = 0, nb = 0;
-    double wr = 0.0;
+    double wr = 0.0, fr = 0.0;
     for (int k = t; k < W; k += 64) {
         nb += (cs.flags[k] & kFlagBreakdown) ? 1 : 0;
         if (!cs.active[k]) continue;
         ++na;
         const double goal = cs.tol2 * cs.bb[k];
         if (cs.rr[k] <= goal) ++nk;
-        if (cs.rr[k] < cs.delta2 * cs.rr_ref[k] || (cs.flags[k] & kFlagRestart) || !isfinite(cs.rr[k])) ++nru;
+        const bool due = !(cs.rr[k] >= cs.delta2 * cs.rr_ref[k]) || (cs.flags[k] & (kFlagRestart | kFlagHold));
+        if (due) {
+            ++nru;
+        } else if (!cs.exact) {
+            const double q = cs.rr[k] / (cs.delta2 * cs.rr_ref[k]);
+            fr = fr == 0.0 ? q : fmin(fr, q);
+        }
         wr = fmax(wr, cs.rr[k] / goal);
     }
     cnt[0][t] = na;
@@ -361,14 +374,17 @@ __device__ __forceinline__ void k_ctrl_body(const CgState &cs, int W) {
     cnt[2][t] = nru;
     cnt[3][t] = nb;
     worst[t] = wr;
+    first[t] = fr;
     __syncthreads();
     if (t != 0) return;
     for (int i = 1; i < 64; ++i) {
         for (int c = 0; c < 4; ++c) cnt[c][0] += cnt[c][i];
         worst[0] = fmax(worst[0], worst[i]);
+        if (first[i] > 0.0) first[0] = first[0] == 0.0 ? first[i] : fmin(first[0], first[i]);
     }
     for (int c = 0; c < 4; ++c) cs.ctrl[c] = cnt[c][0];
     cs.ctrld[0] = worst[0];
+    cs.ctrld[1] = first[0];
 }
 
 __global__ void k_ctrl(CgState cs, int W) { k_ctrl_body(cs, W); }
@@ -684,6 +700,7 @@ __device__ __forceinline__ void k_update2_body(const Blk &bk, Launch L, const S 
     const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> L.logW;
     const R beta = (R)cs.beta[j];
+    if (cs.flags[j] & kFlagHold) return;  // a held lane keeps its direction
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
@@ -1301,14 +1318,24 @@ static void b_stencil(const BatchLaunch &B) {
         B.links ? b_stencil_t<S, S, 1, true>(B) : b_stencil_t<S, S, 1, false>(B);
 }
 
+void launch_b_update2(const BatchLaunch &B) {
+    DP_DISPATCH_PREC(B.prec, S, k_b_update2<S><<<B.nblocks, kBlock, 0, B.stream>>>(B));
+}
+
+void launch_b_stencil(const BatchLaunch &B) {
+    DP_DISPATCH_PREC(B.prec, S, b_stencil<S>(B));
+}
+
+void launch_b_update1(const BatchLaunch &B) {
+    k_b_finish<1, kEpiAlpha><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
+    DP_DISPATCH_PREC(B.prec, S, k_b_update1<S><<<B.nblocks, kBlock, 0, B.stream>>>(B));
+    k_b_finish<1, kEpiBeta><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
+}
+
 void launch_b_iteration(const BatchLaunch &B, bool update2) {
-    DP_DISPATCH_PREC(B.prec, S, {
-        if (update2) k_b_update2<S><<<B.nblocks, kBlock, 0, B.stream>>>(B);
-        b_stencil<S>(B);
-        k_b_finish<1, kEpiAlpha><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
-        k_b_update1<S><<<B.nblocks, kBlock, 0, B.stream>>>(B);
-        k_b_finish<1, kEpiBeta><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
-    });
+    if (update2) launch_b_update2(B);
+    launch_b_stencil(B);
+    launch_b_update1(B);
 }
 
 template <typename S, int NC, bool LINKS>

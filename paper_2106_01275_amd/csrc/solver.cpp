@@ -172,6 +172,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     cs.ctrl = iv + 3 * kMaxW;
     cs.tol2 = cfg.tol * cfg.tol;
     cs.delta2 = cfg.delta * cfg.delta;
+    cs.hold = cfg.inner == kBF16;
     cs.exact = cfg.inner == kF64;
     return DP_OK;
 }
@@ -179,33 +180,29 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
 static dp_status read_ctrl(dp_ctx *ctx, const CgState &cs, int W, hipStream_t s) {
     launch_ctrl(cs, W, s);
     DP_HIP(hipMemcpyAsync(ctx->ctrl_host, cs.ctrl, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-    DP_HIP(hipMemcpyAsync(ctx->ctrl_host + 4, cs.ctrld, sizeof(double), hipMemcpyDeviceToHost, s));
+    DP_HIP(hipMemcpyAsync(ctx->ctrl_host + 4, cs.ctrld, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     DP_HIP(hipStreamSynchronize(s));
     return DP_OK;
 }
 
+int next_check(int dflt, double ratio, double ratio_prev, int dit, double ru_ratio) {
+    int next = dflt;
+    if (ratio_prev > 0 && ratio > 1.0 && ratio < ratio_prev && dit > 0) {
+        const double per_it = std::log(ratio_prev / ratio) / dit;
+        next = (int)std::ceil(std::log(ratio) / per_it);
+        if (ru_ratio > 1.0) next = std::min(next, (int)std::ceil(std::log(ru_ratio) / per_it));
+    }
+    return std::min(16, std::max(2, next));
+}
+
+double stencil_alg_bytes(const Lat &lat, int nc, int W, int prec, bool links) {
+    const double c = (double)prec_bytes(prec);  // one complex number
+    return (double)lat.N * (2.0 * W * nc * c + (links ? 4.0 * nc * nc * c : 0.0));
+}
+
 static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L, const StencilArgs &a) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (cfg.profile) {
-        if (ctx->ev_pool.size() < 2) {
-            for (int i = 0; i < 64; ++i) {
-                hipEvent_t e;
-                DP_HIP(hipEventCreate(&e));
-                ctx->ev_pool.push_back(e);
-            }
-        }
-        e0 = ctx->ev_pool.back();
-        ctx->ev_pool.pop_back();
-        e1 = ctx->ev_pool.back();
-        ctx->ev_pool.pop_back();
-        DP_HIP(hipEventRecord(e0, L.stream));
-    }
-    launch_stencil(L, cfg.inner, a);
-    if (cfg.profile) {
-        DP_HIP(hipEventRecord(e1, L.stream));
-        ctx->ev_pending.emplace_back(e0, e1);
-    }
-    return DP_OK;
+    return timed_launch(ctx, cfg.profile != 0, L.stream, stencil_alg_bytes(L.lat, L.nc, L.W, cfg.inner, a.links),
+                        [&] { launch_stencil(L, cfg.inner, a); });
 }
 
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
@@ -222,8 +219,10 @@ dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
     if (st) {
         st->stencil_ms += ms_sum;
         st->stencil_launches += (int)ctx->ev_pending.size();
+        st->stencil_bytes += ctx->ev_bytes;
     }
     ctx->ev_pending.clear();
+    ctx->ev_bytes = 0;
     return DP_OK;
 }
 
@@ -290,14 +289,11 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
         DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
         nactive = ctx->ctrl_host[0];
         {
-            double ratio;
+            double ratio, ru_ratio;
             std::memcpy(&ratio, ctx->ctrl_host + 4, sizeof(double));
-            int next = std::max(1, ctx->check_every);
-            if (ratio_prev > 0 && ratio > 1.0 && ratio < ratio_prev && it > it_prev) {
-                const double per_it = std::log(ratio_prev / ratio) / (it - it_prev);
-                next = (int)std::ceil(std::log(ratio) / per_it);
-            }
-            steps_next = std::min(16, std::max(2, next));
+            std::memcpy(&ru_ratio, ctx->ctrl_host + 6, sizeof(double));
+            steps_next = next_check(std::max(1, ctx->check_every), ratio, ratio_prev, it - it_prev,
+                                    cfg.inner == kBF16 ? ru_ratio : 0.0);
             ratio_prev = ratio;
             it_prev = it;
         }

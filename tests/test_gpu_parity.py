@@ -202,6 +202,24 @@ def test_trace_gauge_8(ctx, inner, block):
     assert r["solve"]["max_true_resid"] < 1e-10
 
 
+def test_bf16_iterations_near_fp64(ctx):
+    """BF16 storage with the default reliable-update drop (0.1) and held lanes
+    converges in about as many iterations as FP64 CG on the same probes (a
+    lane never iterates past what BF16 resolves)."""
+    _say("bf16 iteration count vs fp64")
+    w = workloads.GAUGE_8
+    U = w.links()
+    col, n, colg, ps = _probe_setup(ctx, w.dims, 3, 2, 4, "best", 0, 0, 1, "z2_complex", True)
+    op = ctx.operator(w.dims, 3, w.m2, cuda(U))
+    r = ctx.trace_estimate([op], [ps], [2], ctx.opts(tol=1e-8, inner="bf16", rhs_block=64))[0]
+    B = oracle.probes(w.dims, 3, col, n, 0, 0, 1, oracle.Z2_COMPLEX, True)
+    _, its, _ = oracle.cg_many(w.dims, 3, w.m2, U, B, tol=1e-8)
+    st = r["solve"]
+    assert st["nconverged"] == len(B) and st["max_true_resid"] <= 1e-8
+    assert st["rhs_iters"] <= 1.25 * its.sum() + 2 * len(B), (st["rhs_iters"], its.sum())
+    assert st["max_iters"] <= 1.5 * its.max() + 5, (st["max_iters"], its.max())
+
+
 _GAUGE8 = {}
 
 
