@@ -137,8 +137,8 @@ void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r
 void launch_update2(const Launch &L, int prec, const void *r, void *p, const CgState &cs);
 void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
-                       const double *x64, const void *xlo, const void *p, int pend, const void *U64,
-                       const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs);
+                       const double *x64, const void *U64, const int *nbr, void *r, int ru_mode,
+                       const Red &rd, const CgState &cs);
 void launch_displaced_dot(const Launch &L, const ProbeGen &g, int p, const double *x64, const Red &rd,
                           const CgState &cs);
 void launch_dot(const Launch &L, const double *a64, const double *b64, const Red &rd,

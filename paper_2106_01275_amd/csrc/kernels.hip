@@ -24,6 +24,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "dp_internal.h"
 
@@ -35,11 +36,19 @@ struct bf16x2 {
     uint32_t v;  // low half: real part, high half: imaginary part
 };
 
-__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    return u >> 16;
+typedef __bf16 bf16v2 __attribute__((ext_vector_type(2)));
+
+// two FP32 values rounded to nearest even into one bf16x2 word (low = a)
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    bf16v2 v;
+    v.x = (__bf16)a;
+    v.y = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// c + a.lo * b.lo + a.hi * b.hi for bf16x2 words a, b (FP32 accumulation)
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16v2, a), __builtin_bit_cast(bf16v2, b), c, false);
 }
 
 template <typename S>
@@ -83,13 +92,14 @@ struct St<bf16x2> {
     }
     __device__ static __forceinline__ void st(bf16x2 *__restrict__ a, size_t i, R re, R im) {
         bf16x2 o;
-        o.v = f32_to_bf16(re) | (f32_to_bf16(im) << 16);
+        o.v = pack_bf16(re, im);
         a[i] = o;
     }
     // the value a store followed by a load would give
     __device__ static __forceinline__ void round(R &re, R &im) {
-        re = __uint_as_float(f32_to_bf16(re) << 16);
-        im = __uint_as_float(f32_to_bf16(im) << 16);
+        const uint32_t v = pack_bf16(re, im);
+        re = __uint_as_float(v << 16);
+        im = __uint_as_float(v & 0xffff0000u);
     }
 };
 
@@ -552,6 +562,136 @@ __device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, 
     __syncthreads();
 }
 
+// The two bf16x2 words of link element (a, b) of one hop for the packed dot
+// products: with v = (vr, vi) and its swap vs = (vi, vr), re += dot(A, v)
+// and im += dot(B, vs).  Forward hop U, w = U[a][b] = (Ur, Ui):
+// A = (Ur, -Ui), B = (Ur, Ui).  Backward hop U^H, element (a, b) =
+// conj(U[b][a]) from w = U[b][a]: A = (Ur, Ui), B = (Ur, -Ui).
+__device__ __forceinline__ void hop_words(uint32_t w, bool dag, uint32_t &A, uint32_t &B) {
+    const uint32_t n = w ^ 0x80000000u;  // imaginary part negated
+    A = dag ? w : n;
+    B = dag ? n : w;
+}
+
+// Stages the hop words (A, B) of the tile's sites, element (a, b) of every
+// hop already transposed for the backward ones, and the neighbour indices.
+template <int NC>
+__device__ __forceinline__ void stage_tile_bf16(uint32_t *su, int *snb, const SiteWalk &wk, int item0,
+                                                int sites_per_tile, const bf16x2 *__restrict__ U,
+                                                const int *__restrict__ nbr) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    const int ne = sites_per_tile * 8 * NC * NC;
+    for (int e = tid; e < ne; e += kBlock) {
+        const int s_l = e / (8 * NC * NC);
+        const int rem = e - s_l * 8 * NC * NC;
+        const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
+        uint32_t A = 0, B = 0;
+        if (item0 + s_l < wk.items) {
+            const int gs = walk_site(wk, item0 + s_l);
+            const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
+            const int a = ab / NC, b = ab - a * NC;
+            const int el = dir < 4 ? ab : b * NC + a;
+            hop_words(U[((size_t)src * 4 + (dir & 3)) * NC * NC + el].v, dir >= 4, A, B);
+        }
+        su[2 * e] = A;
+        su[2 * e + 1] = B;
+    }
+    for (int e = tid; e < sites_per_tile * 8; e += kBlock)
+        snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
+    __syncthreads();
+}
+
+// The stencil on BF16-stored vectors and links: every complex product of a
+// hop is two packed bf16 dot products accumulated in FP32 (the loaded words
+// are used as they are, no unpacking); the modes are those of the generic
+// body below.
+template <int NC, bool LINKS, int MODE>
+__device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, float diag, const bf16x2 *__restrict__ pin,
+                                                    bf16x2 *__restrict__ q, const bf16x2 *__restrict__ U,
+                                                    const int *__restrict__ nbr, int cg, Red rd) {
+    constexpr bool STAGE = MODE == 1 && LINKS;
+    constexpr int kMaxSites = kBlock / 16;
+    __shared__ uint32_t su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
+    __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
+    __shared__ double sm[kBlock];
+    const int tid = threadIdx.x, logW = L.logW, W = L.W;
+    const int j = tid & (W - 1);
+    const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
+    const int sites_per_tile = kBlock >> logW;
+    double acc_pq = 0.0;
+    const SiteWalk wk = site_walk(L.lat, bk);
+    for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
+        const int item0 = t * sites_per_tile;
+        if (MODE == 1) {
+            if (STAGE) stage_tile_bf16<NC>(su, snb, wk, item0, sites_per_tile, U, nbr);
+            else stage_tile<bf16x2, float, NC, false>(nullptr, snb, wk, item0, sites_per_tile, U, nbr);
+        }
+        if (item0 + sl >= wk.items) continue;
+        const int site = walk_site(wk, item0 + sl);
+        int y[9];
+        y[0] = site;
+#pragma unroll
+        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
+        uint32_t v[9][NC], vs[9][NC];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const bf16x2 *row = pin + ((size_t)(y[k] * NC) << logW);
+#pragma unroll
+            for (int b = 0; b < NC; ++b) v[k][b] = row[(unsigned)((b << logW) + j)].v;
+        }
+#pragma unroll
+        for (int k = 1; k < 9; ++k)
+#pragma unroll
+            for (int b = 0; b < NC; ++b) vs[k][b] = (v[k][b] >> 16) | (v[k][b] << 16);
+        float hr[NC], hi[NC];  // sum of the hops
+#pragma unroll
+        for (int a = 0; a < NC; ++a) hr[a] = hi[a] = 0.0f;
+#pragma unroll
+        for (int dir = 0; dir < 8; ++dir) {
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+#pragma unroll
+                for (int b = 0; b < NC; ++b) {
+                    if (!LINKS) {
+                        if (a == b) {
+                            hr[a] += __uint_as_float(v[dir + 1][b] << 16);
+                            hi[a] += __uint_as_float(v[dir + 1][b] & 0xffff0000u);
+                        }
+                        continue;
+                    }
+                    uint32_t A, B;
+                    if (STAGE) {
+                        A = su[((sl * 8 + dir) * NC * NC + a * NC + b) * 2];
+                        B = su[((sl * 8 + dir) * NC * NC + a * NC + b) * 2 + 1];
+                    } else {
+                        const int src = dir < 4 ? site : y[dir + 1];
+                        const int el = dir < 4 ? a * NC + b : b * NC + a;
+                        hop_words(U[((size_t)src * 4 + (dir & 3)) * NC * NC + el].v, dir >= 4, A, B);
+                    }
+                    hr[a] = dot2_bf16(A, v[dir + 1][b], hr[a]);
+                    hi[a] = dot2_bf16(B, vs[dir + 1][b], hi[a]);
+                }
+            }
+        }
+        bf16x2 *qrow = q + ((size_t)(site * NC) << logW);
+        float pqs = 0;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            const float pr = __uint_as_float(v[0][a] << 16), pi = __uint_as_float(v[0][a] & 0xffff0000u);
+            const float ar = fmaf(diag, pr, -hr[a]), ai = fmaf(diag, pi, -hi[a]);
+            bf16x2 o;
+            o.v = pack_bf16(ar, ai);
+            qrow[(unsigned)((a << logW) + j)] = o;
+            pqs = fmaf(pr, ar, fmaf(pi, ai, pqs));
+        }
+        acc_pq += (double)pqs;
+    }
+    if (!cg) return;
+    double acc[1] = {acc_pq};
+    block_partials<1>(bk, acc, W, logW, rd, sm);
+}
+
 // The stencil q = A p for one block of right-hand sides, with p^H q summed
 // per lane when `cg` is set (the first kernel of a CG iteration).
 //
@@ -567,6 +707,10 @@ template <typename S, typename LS, int NC, bool LINKS, int MODE>
 __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename St<S>::R diag, const S *__restrict__ pin,
                                                     S *__restrict__ q, const LS *__restrict__ U,
                                                     const int *__restrict__ nbr, int cg, Red rd) {
+    if constexpr (std::is_same<S, bf16x2>::value) {
+        k_stencil_bf16_body<NC, LINKS, MODE>(bk, L, diag, pin, q, U, nbr, cg, rd);
+        return;
+    }
     using R = typename St<S>::R;
     constexpr bool STAGE = MODE == 1 && LINKS;
     constexpr int kMaxSites = kBlock / 16;
@@ -745,14 +889,11 @@ __global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__
     k_fold_body<S>(own_blk(), L, x64, xlo);
 }
 
-// FP64 true residual r = b - A x_eff with FP64 links, x_eff = x64 (pend = 0)
-// or x64 + xlo + alpha p (pend = 1: the solution including the inner
-// iterate and the pending update, formed on the fly).  Stores r in the
+// FP64 true residual r = b - A x64 with FP64 links.  Stores r in the
 // storage precision and |r|^2 per lane.
 template <typename S, int NC, bool LINKS, int MODE>
 __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, double diag, const double2 *__restrict__ b64,
-                                                       const double2 *__restrict__ x64, const S *__restrict__ xlo,
-                                                       const S *__restrict__ p, int pend,
+                                                       const double2 *__restrict__ x64,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
                                                        S *__restrict__ rout, Red rd, CgState cs) {
     constexpr int kMaxSites = kBlock / 16;
@@ -763,53 +904,35 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
     const int j = tid & (W - 1);
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
-    const double alpha = pend ? cs.alpha[j] : 0.0;
     double acc[1] = {0.0};
     const SiteWalk wk = site_walk(L.lat, bk);
-    auto xeff = [&](int y, double (&vr)[NC], double (&vi)[NC]) {
-        ld_site<double2, NC>(x64, y, logW, j, vr, vi);
-        if (pend) {
-            typename St<S>::R lr[NC], li[NC], qr[NC], qi[NC];
-            ld_site<S, NC>(xlo, y, logW, j, lr, li);
-            ld_site<S, NC>(p, y, logW, j, qr, qi);
-#pragma unroll
-            for (int b = 0; b < NC; ++b) {
-                vr[b] += (double)lr[b] + alpha * (double)qr[b];
-                vi[b] += (double)li[b] + alpha * (double)qi[b];
-            }
-        }
-    };
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         if (MODE == 1) stage_tile<double2, double, NC, LINKS>(su, snb, wk, t * sites_per_tile, sites_per_tile, U, nbr);
         if (t * sites_per_tile + sl >= wk.items) continue;
         const int site = walk_site(wk, t * sites_per_tile + sl);
-        double ar[NC], ai[NC];
-        {
-            double vr[NC], vi[NC], br[NC], bi[NC];
-            xeff(site, vr, vi);
-            ld_site<double2, NC>(b64, site, logW, j, br, bi);
+        int y[9];
+        y[0] = site;
 #pragma unroll
-            for (int a = 0; a < NC; ++a) {
-                ar[a] = fma(-diag, vr[a], br[a]);
-                ai[a] = fma(-diag, vi[a], bi[a]);
-            }
-        }
-        // r = b - diag x + sum of hops: accumulate with the sign flipped
+        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
+        // all loads of the site and its neighbours in flight before any arithmetic
+        double vr[9][NC], vi[9][NC], br[NC], bi[NC];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ld_site<double2, NC>(x64, y[k], logW, j, vr[k], vi[k]);
+        ld_site<double2, NC>(b64, site, logW, j, br, bi);
+        // r = b - diag x + sum of hops: accumulated with the sign flipped
+        double ar[NC], ai[NC];
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            ar[a] = -ar[a];
-            ai[a] = -ai[a];
+            ar[a] = -fma(-diag, vr[0][a], br[a]);
+            ai[a] = -fma(-diag, vi[0][a], bi[a]);
         }
 #pragma unroll
         for (int dir = 0; dir < 8; ++dir) {
-            const int y = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
-            double vr[NC], vi[NC];
-            xeff(y, vr, vi);
             if (!LINKS) {
 #pragma unroll
                 for (int a = 0; a < NC; ++a) {
-                    ar[a] -= vr[a];
-                    ai[a] -= vi[a];
+                    ar[a] -= vr[dir + 1][a];
+                    ai[a] -= vi[dir + 1][a];
                 }
                 continue;
             }
@@ -818,12 +941,12 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
 #pragma unroll
                 for (int e = 0; e < 2 * NC * NC; ++e) u[e] = su[(sl * 8 + dir) * NC * NC * 2 + e];
             } else {
-                ld_link<double2, double, NC>(U, dir < 4 ? site : y, dir & 3, u);
+                ld_link<double2, double, NC>(U, dir < 4 ? site : y[dir + 1], dir & 3, u);
             }
             if (dir < 4)
-                mul_sub<double, NC, false>(u, vr, vi, ar, ai);
+                mul_sub<double, NC, false>(u, vr[dir + 1], vi[dir + 1], ar, ai);
             else
-                mul_sub<double, NC, true>(u, vr, vi, ar, ai);
+                mul_sub<double, NC, true>(u, vr[dir + 1], vi[dir + 1], ar, ai);
         }
         S *rrow = rout + ((size_t)(site * NC) << logW);
 #pragma unroll
@@ -837,11 +960,10 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
 
 template <typename S, int NC, bool LINKS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
-                                                       const double2 *__restrict__ x64, const S *__restrict__ xlo,
-                                                       const S *__restrict__ p, int pend,
+                                                       const double2 *__restrict__ x64,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
                                                        S *__restrict__ rout, Red rd, CgState cs) {
-    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, xlo, p, pend, U, nbr, rout, rd, cs);
+    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, U, nbr, rout, rd, cs);
 }
 
 // t_j = sum_x sum_b conj(v_j(x,b)) x_j(x + p e0, b), probes regenerated.
@@ -1073,8 +1195,7 @@ __global__ __launch_bounds__(kBlock) void k_b_true_resid(BatchLaunch B, int phas
     const SlotDesc *d = slot_of_block(B, bk, phase);
     if (!d) return;
     k_true_resid_body<S, NC, LINKS, MODE>(bk, d->L, d->diag, (const double2 *)d->b64, (const double2 *)d->x64,
-                                          nullptr, nullptr, 0, (const double2 *)d->U64, d->nbr, (S *)d->r,
-                                          d->rd, d->cs);
+                                          (const double2 *)d->U64, d->nbr, (S *)d->r, d->rd, d->cs);
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_dot(BatchLaunch B) {
@@ -1218,12 +1339,10 @@ void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {
 }
 
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64, const double *x64,
-                       const void *xlo, const void *p, int pend, const void *U64, const int *nbr, void *r,
-                       int ru_mode, const Red &rd, const CgState &cs) {
+                       const void *U64, const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs) {
     const double2 *b = (const double2 *)b64, *x = (const double2 *)x64, *u = (const double2 *)U64;
 #define DP_TR(NC_, LK_, M_)                                                                                  \
-    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, (const S *)xlo, (const S *)p, \
-                                                                   pend, u, nbr, (S *)r, rd, cs)
+    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, rd, cs)
     DP_DISPATCH_PREC(prec, S, {
         const int m = L.W >= 64 ? 2 : (L.W >= 16 ? 1 : 0);
         if (L.nc == 3) {

@@ -303,7 +303,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             it_ru = it;
             // reliable update: x64 += xlo, r = b - A x64 in FP64, beta from it
             launch_fold(L, cfg.inner, x64, xlo);
-            launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, nullptr, nullptr, 0, op.U64, op.nbr, r, 1,
+            launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 1,
                               rd, cs);
             DP_HIP(hipGetLastError());
             ++bs.ru;
@@ -313,7 +313,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     }
     if (mixed) launch_fold(L, cfg.inner, x64, xlo);
     // final FP64 true residual (statistics only)
-    launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, nullptr, nullptr, 0, op.U64, op.nbr, r, 0, rd, cs);
+    launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs);
     DP_HIP(hipGetLastError());
     const int W = L.W;
     double *h = ctx->state_host;
