@@ -301,7 +301,8 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
                 if (hsd[k].flags & kSlotIter) bytes += stencil_alg_bytes(hsd[k].L.lat, nc, W, cfg.inner, B.links);
             for (int c = 0; c < steps; ++c) {
                 launch_b_update2(B);
-                DP_TRY(timed_launch(ctx, cfg.profile != 0, s, bytes, [&] { launch_b_stencil(B); }));
+                DP_TRY(timed_launch(ctx, cfg.profile != 0, bytes,
+                                    [&](hipEvent_t e0, hipEvent_t e1) { launch_b_stencil(B, e0, e1); }));
                 launch_b_update1(B);
             }
         }

@@ -98,18 +98,21 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
                        hipStream_t s, int &W);
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
-// runs `launch`; when profiling, between two events on stream s whose pair (and the
-// launch's algorithmic bytes) finish_profile() later adds to the stats
+// runs launch(ev0, ev1); when profiling, with two events from the pool that
+// the launch attaches to the kernel's own start and stop (finish_profile()
+// later adds their interval and the launch's algorithmic bytes to the stats),
+// otherwise with null events
 template <typename F>
-dp_status timed_launch(dp_ctx *ctx, bool profile, hipStream_t s, double bytes, F launch) {
+dp_status timed_launch(dp_ctx *ctx, bool profile, double bytes, F launch) {
     if (!profile) {
-        launch();
+        launch(hipEvent_t(nullptr), hipEvent_t(nullptr));
         return DP_OK;
     }
     if (ctx->ev_pool.size() < 2) {
         for (int i = 0; i < 64; ++i) {
+            // timing only: no system-scope fence (no L2 writeback around the timed launch)
             hipEvent_t e;
-            DP_HIP(hipEventCreate(&e));
+            DP_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             ctx->ev_pool.push_back(e);
         }
     }
@@ -117,9 +120,7 @@ dp_status timed_launch(dp_ctx *ctx, bool profile, hipStream_t s, double bytes, F
     ctx->ev_pool.pop_back();
     hipEvent_t e1 = ctx->ev_pool.back();
     ctx->ev_pool.pop_back();
-    DP_HIP(hipEventRecord(e0, s));
-    launch();
-    DP_HIP(hipEventRecord(e1, s));
+    launch(e0, e1);
     ctx->ev_pending.emplace_back(e0, e1);
     ctx->ev_bytes += bytes;
     return DP_OK;

@@ -104,7 +104,7 @@ struct BatchLaunch {
 void launch_b_init(const BatchLaunch &B, int mixed);
 void launch_b_iteration(const BatchLaunch &B, bool update2);
 void launch_b_update2(const BatchLaunch &B);
-void launch_b_stencil(const BatchLaunch &B);
+void launch_b_stencil(const BatchLaunch &B, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_b_update1(const BatchLaunch &B);  // with the alpha and beta epilogues
 void launch_b_ru(const BatchLaunch &B, int final_stats);
 void launch_b_dot(const BatchLaunch &B);
@@ -130,6 +130,7 @@ struct StencilArgs {
     int cg = 0;
     Red rd{};
     CgState cs{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // if set: the stencil kernel's own start and stop times
 };
 void launch_stencil(const Launch &L, int prec, const StencilArgs &a);
 void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r, const void *q,

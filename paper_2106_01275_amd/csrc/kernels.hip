@@ -20,6 +20,7 @@
 // device, so the host only reads a control word now and then.  The kernel
 // boundary makes the partials visible; no device-scope fence is used (on
 // this multi-XCD part such a fence writes back the whole L2 of the XCD).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1287,7 +1288,12 @@ static void stencil_nc(const Launch &L, const StencilArgs &a) {
     const S *pin = (const S *)a.pin;
     S *q = (S *)a.q;
     const LS *U = (const LS *)a.U;
-#define DP_ST(M) k_stencil<S, LS, NC, LINKS, M><<<grid, blk, 0, L.stream>>>(L, (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd)
+#define DP_ST(M)                                                                                        \
+    if (a.ev0)                                                                                          \
+        hipExtLaunchKernelGGL(k_stencil<S, LS, NC, LINKS, M>, grid, blk, 0, L.stream, a.ev0, a.ev1, 0, L, \
+                              (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd);                                 \
+    else                                                                                                \
+        k_stencil<S, LS, NC, LINKS, M><<<grid, blk, 0, L.stream>>>(L, (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd)
     if (L.W >= 64)
         DP_ST(2);
     else if (L.W >= 16)
@@ -1419,30 +1425,39 @@ void launch_b_init(const BatchLaunch &B, int mixed) {
     k_b_finish<1, kEpiInit><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotInit);
 }
 
-template <typename S, typename LS, int NC, bool LINKS>
-static void b_stencil_t(const BatchLaunch &B) {
-    if (B.mode == 2)
-        k_b_stencil<S, LS, NC, LINKS, 2><<<B.nblocks, kBlock, 0, B.stream>>>(B);
-    else if (B.mode == 1)
-        k_b_stencil<S, LS, NC, LINKS, 1><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+template <typename S, typename LS, int NC, bool LINKS, int M>
+static void b_stencil_m(const BatchLaunch &B, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0)
+        hipExtLaunchKernelGGL(k_b_stencil<S, LS, NC, LINKS, M>, dim3(B.nblocks), dim3(kBlock), 0, B.stream, ev0, ev1,
+                              0, B);
     else
-        k_b_stencil<S, LS, NC, LINKS, 0><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+        k_b_stencil<S, LS, NC, LINKS, M><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+}
+
+template <typename S, typename LS, int NC, bool LINKS>
+static void b_stencil_t(const BatchLaunch &B, hipEvent_t ev0, hipEvent_t ev1) {
+    if (B.mode == 2)
+        b_stencil_m<S, LS, NC, LINKS, 2>(B, ev0, ev1);
+    else if (B.mode == 1)
+        b_stencil_m<S, LS, NC, LINKS, 1>(B, ev0, ev1);
+    else
+        b_stencil_m<S, LS, NC, LINKS, 0>(B, ev0, ev1);
 }
 
 template <typename S>
-static void b_stencil(const BatchLaunch &B) {
+static void b_stencil(const BatchLaunch &B, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     if (B.nc == 3)
-        B.links ? b_stencil_t<S, S, 3, true>(B) : b_stencil_t<S, S, 3, false>(B);
+        B.links ? b_stencil_t<S, S, 3, true>(B, ev0, ev1) : b_stencil_t<S, S, 3, false>(B, ev0, ev1);
     else
-        B.links ? b_stencil_t<S, S, 1, true>(B) : b_stencil_t<S, S, 1, false>(B);
+        B.links ? b_stencil_t<S, S, 1, true>(B, ev0, ev1) : b_stencil_t<S, S, 1, false>(B, ev0, ev1);
 }
 
 void launch_b_update2(const BatchLaunch &B) {
     DP_DISPATCH_PREC(B.prec, S, k_b_update2<S><<<B.nblocks, kBlock, 0, B.stream>>>(B));
 }
 
-void launch_b_stencil(const BatchLaunch &B) {
-    DP_DISPATCH_PREC(B.prec, S, b_stencil<S>(B));
+void launch_b_stencil(const BatchLaunch &B, hipEvent_t ev0, hipEvent_t ev1) {
+    DP_DISPATCH_PREC(B.prec, S, b_stencil<S>(B, ev0, ev1));
 }
 
 void launch_b_update1(const BatchLaunch &B) {

@@ -201,8 +201,13 @@ double stencil_alg_bytes(const Lat &lat, int nc, int W, int prec, bool links) {
 }
 
 static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L, const StencilArgs &a) {
-    return timed_launch(ctx, cfg.profile != 0, L.stream, stencil_alg_bytes(L.lat, L.nc, L.W, cfg.inner, a.links),
-                        [&] { launch_stencil(L, cfg.inner, a); });
+    return timed_launch(ctx, cfg.profile != 0, stencil_alg_bytes(L.lat, L.nc, L.W, cfg.inner, a.links),
+                        [&](hipEvent_t e0, hipEvent_t e1) {
+                            StencilArgs ta = a;
+                            ta.ev0 = e0;
+                            ta.ev1 = e1;
+                            launch_stencil(L, cfg.inner, ta);
+                        });
 }
 
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
@@ -429,8 +434,8 @@ static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, 
     iter();
     iter();
     hipEvent_t e0, e1;
-    DP_HIP(hipEventCreate(&e0));
-    DP_HIP(hipEventCreate(&e1));
+    DP_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    DP_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     DP_HIP(hipEventRecord(e0, s));
     for (int i = 0; i < 6; ++i) iter();
     DP_HIP(hipEventRecord(e1, s));
