@@ -295,7 +295,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             }
             DP_HIP(hipGraphLaunch(g->second, s));
         } else {
-            // update2 on a freshly initialised slot is harmless: beta = 0 and p = r = b
+            // update2 on a freshly initialised slot is harmless: alpha = beta = 0 and p = r = b
             double bytes = 0;
             for (int k = 0; k < nslots; ++k)
                 if (hsd[k].flags & kSlotIter) bytes += stencil_alg_bytes(hsd[k].L.lat, nc, W, cfg.inner, B.links);

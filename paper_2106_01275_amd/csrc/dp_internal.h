@@ -133,10 +133,11 @@ struct StencilArgs {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // if set: the stencil kernel's own start and stop times
 };
 void launch_stencil(const Launch &L, int prec, const StencilArgs &a);
-void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r, const void *q,
-                    const Red &rd, const CgState &cs);
-void launch_update2(const Launch &L, int prec, const void *r, void *p, const CgState &cs);
-void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
+void launch_update1(const Launch &L, int prec, void *r, const void *q, const Red &rd, const CgState &cs);
+// x += alpha p (deferred), p = r + beta p
+void launch_update2(const Launch &L, int prec, const void *r, void *p, void *x, const CgState &cs);
+// x64 += xlo + alpha p, xlo = 0 (xlo null: FP64, x64 += alpha p)
+void launch_fold(const Launch &L, int prec, double *x64, void *xlo, const void *p, const CgState &cs);
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
                        const double *x64, const void *U64, const int *nbr, void *r, int ru_mode,
                        const Red &rd, const CgState &cs);

@@ -328,6 +328,7 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
         }
     } else if (EPI == kEpiRU || EPI == kEpiStats) {
         cs.true_rr[j] = t;
+        cs.alpha[j] = 0.0;  // the fold before applied the deferred solution update
         if (EPI == kEpiRU && cs.active[j]) {
             // restart the direction (beta = 0) after a low-precision
             // breakdown or when the true residual grew since the last update
@@ -785,12 +786,13 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
     k_stencil_body<S, LS, NC, LINKS, MODE>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
 }
 
-// x += alpha p, r -= alpha q and |r|^2 per lane (second kernel of a CG
-// iteration).
+// r -= alpha q and |r|^2 per lane (second kernel of a CG iteration).  The
+// solution update x += alpha p of the iteration is deferred to the next
+// update2 (or fold), which reads p anyway: 10 vector passes per iteration
+// instead of 11.
 template <typename S>
-__device__ __forceinline__ void k_update1_body(const Blk &bk, Launch L, S *__restrict__ xlo, const S *__restrict__ p,
-                                                    S *__restrict__ r, const S *__restrict__ q, Red rd,
-                                                    CgState cs) {
+__device__ __forceinline__ void k_update1_body(const Blk &bk, Launch L, S *__restrict__ r, const S *__restrict__ q,
+                                               Red rd, CgState cs) {
     using R = typename St<S>::R;
     __shared__ double sm[kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
@@ -807,12 +809,9 @@ __device__ __forceinline__ void k_update1_body(const Blk &bk, Launch L, S *__res
     R part = 0;
     int cnt = 0;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
-        R xr, xi, pr, pi, rr_, ri, qr, qi;
-        St<S>::ld(xlo, e, xr, xi);
-        St<S>::ld(p, e, pr, pi);
+        R rr_, ri, qr, qi;
         St<S>::ld(r, e, rr_, ri);
         St<S>::ld(q, e, qr, qi);
-        St<S>::st(xlo, e, fmaR(alpha, pr, xr), fmaR(alpha, pi, xi));
         rr_ = fmaR(-alpha, qr, rr_);
         ri = fmaR(-alpha, qi, ri);
         St<S>::st(r, e, rr_, ri);
@@ -830,64 +829,81 @@ __device__ __forceinline__ void k_update1_body(const Blk &bk, Launch L, S *__res
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ xlo, const S *__restrict__ p,
-                                                    S *__restrict__ r, const S *__restrict__ q, Red rd,
+__global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ r, const S *__restrict__ q, Red rd,
                                                     CgState cs) {
-    k_update1_body<S>(own_blk(), L, xlo, p, r, q, rd, cs);
+    k_update1_body<S>(own_blk(), L, r, q, rd, cs);
 }
 
-// p = r + beta p (third kernel of a CG iteration)
+// x += alpha p (the previous iteration's deferred solution update), then
+// p = r + beta p (third kernel of a CG iteration).  A held lane keeps its
+// direction (its deferred update still lands).
 template <typename S>
 __device__ __forceinline__ void k_update2_body(const Blk &bk, Launch L, const S *__restrict__ r, S *__restrict__ p,
-                                                    CgState cs) {
+                                               S *__restrict__ x, CgState cs) {
     using R = typename St<S>::R;
     const int tid = threadIdx.x, W = L.W;
     const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> L.logW;
+    const R alpha = (R)cs.alpha[j];
     const R beta = (R)cs.beta[j];
-    if (cs.flags[j] & kFlagHold) return;  // a held lane keeps its direction
+    const bool keep = cs.flags[j] & kFlagHold;
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
     const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
-        R rr_, ri, pr, pi;
-        St<S>::ld(r, e, rr_, ri);
+        R rr_, ri, pr, pi, xr, xi;
         St<S>::ld(p, e, pr, pi);
+        St<S>::ld(x, e, xr, xi);
+        St<S>::st(x, e, fmaR(alpha, pr, xr), fmaR(alpha, pi, xi));
+        if (keep) continue;
+        St<S>::ld(r, e, rr_, ri);
         St<S>::st(p, e, fmaR(beta, pr, rr_), fmaR(beta, pi, ri));
     }
 }
 
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restrict__ r, S *__restrict__ p,
-                                                    CgState cs) {
-    k_update2_body<S>(own_blk(), L, r, p, cs);
+                                                    S *__restrict__ x, CgState cs) {
+    k_update2_body<S>(own_blk(), L, r, p, x, cs);
 }
 
-// x64 += xlo, xlo = 0 (mixed precision)
+// Mixed precision (xlo set): x64 += xlo + alpha p, xlo = 0.  FP64 (xlo null,
+// x64 is the iterate): x64 += alpha p.  Either way the deferred solution
+// update lands; the epilogue that follows sets alpha to 0.
 template <typename S>
-__device__ __forceinline__ void k_fold_body(const Blk &bk, Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
+__device__ __forceinline__ void k_fold_body(const Blk &bk, Launch L, double2 *__restrict__ x64, S *__restrict__ xlo,
+                                            const S *__restrict__ p, CgState cs) {
     using R = typename St<S>::R;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, W = L.W;
+    const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> L.logW;
+    const double alpha = cs.alpha[j];
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
-    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * L.W;
-    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * L.W;
+    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
-        R xr, xi;
-        St<S>::ld(xlo, e, xr, xi);
+        R pr, pi;
+        St<S>::ld(p, e, pr, pi);
         double2 v = x64[e];
-        v.x += (double)xr;
-        v.y += (double)xi;
+        v.x = fma(alpha, (double)pr, v.x);
+        v.y = fma(alpha, (double)pi, v.y);
+        if (xlo) {
+            R xr, xi;
+            St<S>::ld(xlo, e, xr, xi);
+            v.x += (double)xr;
+            v.y += (double)xi;
+            St<S>::st(xlo, e, 0, 0);
+        }
         x64[e] = v;
-        St<S>::st(xlo, e, 0, 0);
     }
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
-    k_fold_body<S>(own_blk(), L, x64, xlo);
+__global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo,
+                                                 const S *__restrict__ p, CgState cs) {
+    k_fold_body<S>(own_blk(), L, x64, xlo, p, cs);
 }
 
 // FP64 true residual r = b - A x64 with FP64 links.  Stores r in the
@@ -1171,7 +1187,7 @@ __global__ __launch_bounds__(kBlock) void k_b_update1(BatchLaunch B) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
-    k_update1_body<S>(bk, d->L, (S *)d->xlo, (const S *)d->p, (S *)d->r, (const S *)d->q, d->rd, d->cs);
+    k_update1_body<S>(bk, d->L, (S *)d->r, (const S *)d->q, d->rd, d->cs);
 }
 
 template <typename S>
@@ -1179,7 +1195,7 @@ __global__ __launch_bounds__(kBlock) void k_b_update2(BatchLaunch B) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
-    k_update2_body<S>(bk, d->L, (const S *)d->r, (S *)d->p, d->cs);
+    k_update2_body<S>(bk, d->L, (const S *)d->r, (S *)d->p, (S *)d->xlo, d->cs);
 }
 
 template <typename S>
@@ -1187,7 +1203,8 @@ __global__ __launch_bounds__(kBlock) void k_b_fold(BatchLaunch B, int phase) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, phase);
     if (!d) return;
-    k_fold_body<S>(bk, d->L, d->x64 ? (double2 *)d->x64 : nullptr, (S *)d->xlo);
+    // FP64: the iterate is x64 itself (xlo aliases it)
+    k_fold_body<S>(bk, d->L, (double2 *)d->x64, B.prec == kF64 ? nullptr : (S *)d->xlo, (const S *)d->p, d->cs);
 }
 
 template <typename S, int NC, bool LINKS, int MODE>
@@ -1328,20 +1345,19 @@ void launch_stencil(const Launch &L, int prec, const StencilArgs &a) {
     if (a.cg) k_finish<1, kEpiAlpha><<<L.W, kBlock, 0, L.stream>>>(a.rd, a.cs);
 }
 
-void launch_update1(const Launch &L, int prec, void *xlo, const void *p, void *r, const void *q, const Red &rd,
-                    const CgState &cs) {
-    DP_DISPATCH_PREC(prec, S,
-                     k_update1<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)xlo, (const S *)p, (S *)r,
-                                                                   (const S *)q, rd, cs));
+void launch_update1(const Launch &L, int prec, void *r, const void *q, const Red &rd, const CgState &cs) {
+    DP_DISPATCH_PREC(prec, S, k_update1<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)r, (const S *)q, rd, cs));
     k_finish<1, kEpiBeta><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
-void launch_update2(const Launch &L, int prec, const void *r, void *p, const CgState &cs) {
-    DP_DISPATCH_PREC(prec, S, k_update2<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (const S *)r, (S *)p, cs));
+void launch_update2(const Launch &L, int prec, const void *r, void *p, void *x, const CgState &cs) {
+    DP_DISPATCH_PREC(prec, S,
+                     k_update2<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (const S *)r, (S *)p, (S *)x, cs));
 }
 
-void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {
-    DP_DISPATCH_PREC(prec, S, k_fold<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (double2 *)x64, (S *)xlo));
+void launch_fold(const Launch &L, int prec, double *x64, void *xlo, const void *p, const CgState &cs) {
+    DP_DISPATCH_PREC(prec, S,
+                     k_fold<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (double2 *)x64, (S *)xlo, (const S *)p, cs));
 }
 
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64, const double *x64,
@@ -1487,7 +1503,7 @@ static void b_tr_t(const BatchLaunch &B, int phase) {
 void launch_b_ru(const BatchLaunch &B, int final_stats) {
     const int phase = final_stats ? kSlotFinal : kSlotRU;
     DP_DISPATCH_PREC(B.prec, S, {
-        if (B.prec != kF64) k_b_fold<S><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+        k_b_fold<S><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
         if (B.nc == 3)
             B.links ? b_tr_t<S, 3, true>(B, phase) : b_tr_t<S, 3, false>(B, phase);
         else

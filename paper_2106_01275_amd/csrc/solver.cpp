@@ -270,9 +270,9 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
                 hipGraphExec_t exec = nullptr;
                 DP_HIP(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal));
                 for (int c = 0; c < steps; ++c) {
-                    launch_update2(L, cfg.inner, r, p, cs);
+                    launch_update2(L, cfg.inner, r, p, xlo, cs);
                     launch_stencil(L, cfg.inner, a);
-                    launch_update1(L, cfg.inner, xlo, p, r, q, rd, cs);
+                    launch_update1(L, cfg.inner, r, q, rd, cs);
                 }
                 DP_HIP(hipStreamEndCapture(L.stream, &graph));
                 const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -283,9 +283,9 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             DP_HIP(hipGraphLaunch(g->second, L.stream));
         } else {
             for (int c = 0; c < steps; ++c) {
-                if (pending) launch_update2(L, cfg.inner, r, p, cs);
+                if (pending) launch_update2(L, cfg.inner, r, p, xlo, cs);
                 DP_TRY(timed_stencil(ctx, cfg, L, a));
-                launch_update1(L, cfg.inner, xlo, p, r, q, rd, cs);
+                launch_update1(L, cfg.inner, r, q, rd, cs);
                 pending = true;
             }
         }
@@ -307,7 +307,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
              it - it_ru >= cfg.ru_gap)) {
             it_ru = it;
             // reliable update: x64 += xlo, r = b - A x64 in FP64, beta from it
-            launch_fold(L, cfg.inner, x64, xlo);
+            launch_fold(L, cfg.inner, x64, xlo, p, cs);
             launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 1,
                               rd, cs);
             DP_HIP(hipGetLastError());
@@ -316,7 +316,8 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             nactive = ctx->ctrl_host[0];
         }
     }
-    if (mixed) launch_fold(L, cfg.inner, x64, xlo);
+    // the deferred solution update of the last iteration (and xlo, mixed)
+    launch_fold(L, cfg.inner, x64, mixed ? xlo : nullptr, p, cs);
     // final FP64 true residual (statistics only)
     launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs);
     DP_HIP(hipGetLastError());
@@ -427,9 +428,9 @@ static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, 
     a.rd = rd;
     a.cs = cs;
     auto iter = [&]() {
-        launch_update2(L, cfg.inner, ctx->at(kSlotR), ctx->at(kSlotP), cs);
+        launch_update2(L, cfg.inner, ctx->at(kSlotR), ctx->at(kSlotP), xlo, cs);
         launch_stencil(L, cfg.inner, a);
-        launch_update1(L, cfg.inner, xlo, ctx->at(kSlotP), ctx->at(kSlotR), ctx->at(kSlotQ), rd, cs);
+        launch_update1(L, cfg.inner, ctx->at(kSlotR), ctx->at(kSlotQ), rd, cs);
     };
     iter();
     iter();
