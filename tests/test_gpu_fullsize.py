@@ -85,19 +85,21 @@ def test_gauge32_solution_residual_by_oracle_operator(ctx):
 
 def test_gauge32_gradient_finite_differences(ctx):
     """32^4 x 3, m2 = 0.01, eps = 0.5, p = 8, distance-8 colouring (32
-    colours), 96 diluted probes: the adjoint dT/dm2 and dT/dU (recomputed
-    solves, no Krylov history) against central differences of the GPU
-    estimate in m2 and along a random su(3) link direction.  At m2 = 0.01 the
-    O(h^2) truncation error of a central difference is not negligible; it is
-    estimated from the same difference at 2h (D(2h) - D(h) = 3 c h^2 for
-    D(h) = g + c h^2), so the check is |D(h) - g| <= 1e-6 |g| + |D(2h) - D(h)|."""
+    colours), 96 diluted probes, FP64 solves: the adjoint dT/dm2 and dT/dU
+    (recomputed solves, no Krylov history) against central differences of
+    the GPU estimate (h = 1e-4) in m2 and along 16 random su(3) link
+    directions U(t) = exp(i t X) U.  At m2 = 0.01 the O(h^2) truncation error
+    of a central difference is not negligible; it is estimated from the same
+    difference at 2h (D(2h) - D(h) = 3 c h^2 for D(h) = g + c h^2), so the
+    check is |D(h) - g| <= 1e-6 |g| + |D(2h) - D(h)|."""
     w = workloads.GAUGE_32
     _say("32^4 gradient")
     col, n, _ = dp.build_coloring(w.dims, w.p, 8, "best")
     assert n == 32
     U = w.links()
     colg = torch.from_numpy(col).cuda()
-    opts = ctx.opts(tol=1e-11, inner="f32", rhs_block=32, reliable_delta=1e-3)
+    # FP64 solves to 1e-13: a difference quotient divides the solves' error by 2h
+    opts = ctx.opts(tol=1e-13, inner="f64", rhs_block=32)
     ps = ctx.probe_spec(w.dims, 3, colg, n, 0, 0, 1, "z2_complex", True)
     Ug = torch.from_numpy(U).cuda()
     op = ctx.operator(w.dims, 3, w.m2, Ug)
@@ -115,19 +117,34 @@ def test_gauge32_gradient_finite_differences(ctx):
     fd2 = (T_at(w.m2 + 2 * h, Ug) - T_at(w.m2 - 2 * h, Ug)) / (4 * h)
     assert abs(fd - g) <= 1e-6 * abs(g) + abs(fd2 - fd), (fd, fd2, g)
     assert abs(fd - g) < 1e-4 * abs(g)
-    rng = np.random.default_rng(1)
+
+    def expi(t, X):
+        # exp(i t X) by its Taylor series (|t X| <= 1e-3 here: order 8 is exact in FP64)
+        E = torch.eye(3, dtype=X.dtype, device=X.device).expand_as(X).contiguous()
+        term = E
+        for k in range(1, 9):
+            term = torch.matmul(term, (1j * t / k) * X).contiguous()
+            E = E + term
+        return E
+
     N = w.volume
-    G = rng.standard_normal((4, N, 3, 3)) + 1j * rng.standard_normal((4, N, 3, 3))
-    X = 0.5 * (G + np.conj(np.swapaxes(G, -1, -2)))
-    wv, Q = np.linalg.eigh(X)
+    for d in range(16):
+        gen = torch.Generator(device="cuda").manual_seed(100 + d)
+        G = torch.complex(torch.randn((4, N, 3, 3), generator=gen, device="cuda", dtype=torch.float64),
+                          torch.randn((4, N, 3, 3), generator=gen, device="cuda", dtype=torch.float64))
+        X = 0.5 * (G + G.conj().transpose(-1, -2))
+        X = X - (torch.diagonal(X, dim1=-2, dim2=-1).sum(-1).real / 3)[..., None, None] * torch.eye(
+            3, dtype=X.dtype, device="cuda")
+        X = X.contiguous()
+        del G
 
-    def rot(t):
-        E = (Q * np.exp(1j * t * wv)[..., None, :]) @ np.conj(np.swapaxes(Q, -1, -2))
-        return torch.from_numpy(E @ U).cuda()
+        def rot(t):
+            return torch.matmul(expi(t, X), Ug).contiguous()
 
-    fdU = (T_at(w.m2, rot(h)) - T_at(w.m2, rot(-h))) / (2 * h)
-    fdU2 = (T_at(w.m2, rot(2 * h)) - T_at(w.m2, rot(-2 * h))) / (4 * h)
-    dUdt = torch.from_numpy(1j * X @ U).cuda()
-    an = (torch.sum(dU * dUdt) + torch.sum(dUb * torch.conj(dUdt))).item()
-    assert abs(fdU - an) <= 1e-6 * abs(an) + abs(fdU2 - fdU), (fdU, fdU2, an)
-    assert abs(fdU - an) < 1e-4 * abs(an)
+        fdU = (T_at(w.m2, rot(h)) - T_at(w.m2, rot(-h))) / (2 * h)
+        fdU2 = (T_at(w.m2, rot(2 * h)) - T_at(w.m2, rot(-2 * h))) / (4 * h)
+        dUdt = torch.matmul(1j * X, Ug)
+        an = (torch.sum(dU * dUdt) + torch.sum(dUb * torch.conj(dUdt))).item()
+        _say("  direction", d, fdU, an)
+        assert abs(fdU - an) <= 1e-6 * abs(an) + abs(fdU2 - fdU), (d, fdU, fdU2, an)
+        assert abs(fdU - an) < 1e-4 * abs(an), (d, fdU, an)
