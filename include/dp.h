@@ -208,6 +208,22 @@ dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops,
                             dp_trace_result *out, hipStream_t stream);
 
 /*
+ * One probe set, many displacements (Sec. 4.3): the probes of ps (built from
+ * a colouring for one (p0, k0)) are solved once and every solution is
+ * contracted with each displacement disp[n] (any sign),
+ *     t_j(n) = sum_x sum_b conj(v_j(x,b)) x_j(x + disp[n] e0, b),
+ * giving the estimate of Tr(P_n A^{-1}) for all n at the cost of one set of
+ * solves.  By Thm. Clearance the (p0, k0) colouring still removes every
+ * neighbour up to distance max(0, k0 - |p0 - n|) for displacement n.
+ *   disp   host int32[ndisp], ndisp >= 1.
+ *   out    host dp_trace_result[ndisp], written (out[n] for disp[n]; each
+ *          carries the same solve statistics).
+ * Single instance; the other conventions are those of dp_trace_estimate. */
+dp_status dp_trace_multi(dp_ctx *ctx, const dp_operator *op, const int32_t *disp, int32_t ndisp,
+                         const dp_probe_spec *ps, const dp_solve_opts *o, dp_trace_result *out,
+                         hipStream_t stream);
+
+/*
  * Adjoint gradient of the probed estimate T (same probes as dp_trace_estimate).
  * With x_j = A^{-1} v_j and lambda_j = A^{-1} P^T v_j ((P^T v)(y) = v(y - p e0)),
  * recomputed here (no Krylov history is kept):

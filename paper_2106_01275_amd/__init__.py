@@ -5,8 +5,8 @@ Argument marshalling only: every step of the method runs in the library's
 HIP kernels (or, for the colouring, its host code).  PyTorch provides device
 memory and streams.  The names follow the C ABI in include/dp.h:
 
-    build_coloring, make_probes, solve_batch, trace_estimate, trace_grad,
-    apply (the operator, for verification)
+    build_coloring, make_probes, solve_batch, trace_estimate, trace_multi,
+    trace_grad, apply (the operator, for verification)
 
 plus ProbedTrace, a torch.autograd.Function over trace_estimate/trace_grad.
 The library must be built (python -m paper_2106_01275_amd.build); importing
@@ -74,7 +74,7 @@ class TraceResult(ctypes.Structure):
 
 
 EXPORTS = ["dp_create", "dp_destroy", "dp_last_error", "dp_build_coloring", "dp_make_probes",
-           "dp_solve_batch", "dp_trace_estimate", "dp_trace_grad", "dp_apply"]
+           "dp_solve_batch", "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply"]
 
 _lib = None
 
@@ -98,11 +98,13 @@ def lib():
                                      ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
         L.dp_trace_estimate.argtypes = [vp, i32, ctypes.POINTER(Operator), vp, ctypes.POINTER(ProbeSpec),
                                         ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp]
+        L.dp_trace_multi.argtypes = [vp, ctypes.POINTER(Operator), vp, i32, ctypes.POINTER(ProbeSpec),
+                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp]
         L.dp_trace_grad.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(ProbeSpec),
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp, vp, vp, vp]
         L.dp_apply.argtypes = [vp, ctypes.POINTER(Operator), i32, vp, vp, i64, vp]
         for name in ("dp_create", "dp_build_coloring", "dp_make_probes", "dp_solve_batch",
-                     "dp_trace_estimate", "dp_trace_grad", "dp_apply"):
+                     "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -264,6 +266,29 @@ class Context:
             out.append({"T": complex(res[i].tr[0], res[i].tr[1]), "stderr": res[i].stderr_,
                         "per_sample": bufs[i][0].view(np.complex128).copy(),
                         "tj": bufs[i][1].view(np.complex128).copy(), "solve": res[i].solve.asdict()})
+        if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
+            self._err(st, out)
+        return out
+
+    def trace_multi(self, op, ps, disps, opts, check=True):
+        """One probe set solved once, contracted with every displacement in
+        disps (any sign).  Returns a list of dicts (one per displacement)."""
+        n = len(disps)
+        arr_d = (ctypes.c_int32 * n)(*[int(v) for v in disps])
+        res = (TraceResult * n)()
+        ndil = ps.nc if ps.dilute else 1
+        nrhs = ps.nsamples * ps.ncolors * ndil
+        bufs = []
+        for i in range(n):
+            per_s, per_r = np.zeros(2 * ps.nsamples), np.zeros(2 * nrhs)
+            bufs.append((per_s, per_r))
+            res[i].per_sample = per_s.ctypes.data
+            res[i].per_rhs = per_r.ctypes.data
+        st = lib().dp_trace_multi(self.h, ctypes.byref(op), arr_d, n, ctypes.byref(ps), ctypes.byref(opts), res,
+                                  self._stream())
+        out = [{"p": int(disps[i]), "T": complex(res[i].tr[0], res[i].tr[1]), "stderr": res[i].stderr_,
+                "per_sample": bufs[i][0].view(np.complex128).copy(), "tj": bufs[i][1].view(np.complex128).copy(),
+                "solve": res[i].solve.asdict()} for i in range(n)]
         if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
             self._err(st, out)
         return out

@@ -346,14 +346,13 @@ static void combine(const dp_probe_spec &ps, const std::vector<double> &tj, dp_t
     if (out.per_rhs) std::memcpy(out.per_rhs, tj.data(), tj.size() * sizeof(double));
 }
 
-static dp_status trace_one(dp_ctx *ctx, const dp_operator &opd, int32_t p, const dp_probe_spec &ps,
-                           const dp_solve_opts *o, const SolveCfg &cfg, dp_trace_result &out, hipStream_t stream) {
+// The probes of ps solved once; every solution contracted with each of the
+// ndisp displacements (any sign).  outs[n] gets the estimate for disp[n].
+static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const int32_t *disp, int ndisp,
+                                     const dp_probe_spec &ps, const dp_solve_opts *o, const SolveCfg &cfg,
+                                     dp_trace_result *outs, hipStream_t stream) {
     const double t0 = now_s();
     DP_TRY(check_spec(ctx, ps, &opd));
-    if (p < 0) {
-        ctx->err = "trace_estimate: p must be >= 0";
-        return DP_EINVAL;
-    }
     OpPrep op;
     DP_TRY(prepare_operator(ctx, opd, cfg.inner, op, stream));
     const int ndil = ps.dilute ? ps.nc : 1;
@@ -366,7 +365,7 @@ static dp_status trace_one(dp_ctx *ctx, const dp_operator &opd, int32_t p, const
     DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
     dp_solve_stats s{};
     s.rhs_block = W;
-    std::vector<double> tj(2 * nrhs, 0.0);
+    std::vector<std::vector<double>> tj(ndisp, std::vector<double>(2 * nrhs, 0.0));
     for (long long r0 = 0; r0 < nrhs; r0 += W) {
         const long long nv = std::min<long long>(W, nrhs - r0);
         BlockStats bs;
@@ -374,15 +373,30 @@ static dp_status trace_one(dp_ctx *ctx, const dp_operator &opd, int32_t p, const
         InitProbe init{&L, cfg.inner, make_gen(ps, r0, nv, 0), &rd, &cs, ctx};
         double *x64 = (double *)ctx->at(kSlotX64);
         DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s));
-        launch_displaced_dot(L, make_gen(ps, r0, nv, 0), p, x64, rd, cs);
-        DP_HIP(hipGetLastError());
-        DP_HIP(hipMemcpyAsync(tj.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        for (int n = 0; n < ndisp; ++n) {
+            // each contraction reads x only at the probe's sites shifted by disp[n]
+            launch_displaced_dot(L, make_gen(ps, r0, nv, 0), disp[n], x64, rd, cs);
+            DP_HIP(hipGetLastError());
+            DP_HIP(hipMemcpyAsync(tj[n].data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost,
+                                  stream));
+        }
     }
     DP_HIP(hipStreamSynchronize(stream));
-    combine(ps, tj, out);
     s.seconds = now_s() - t0;
-    out.solve = s;
+    for (int n = 0; n < ndisp; ++n) {
+        combine(ps, tj[n], outs[n]);
+        outs[n].solve = s;
+    }
     return final_status(s);
+}
+
+static dp_status trace_one(dp_ctx *ctx, const dp_operator &opd, int32_t p, const dp_probe_spec &ps,
+                           const dp_solve_opts *o, const SolveCfg &cfg, dp_trace_result &out, hipStream_t stream) {
+    if (p < 0) {
+        ctx->err = "trace_estimate: p must be >= 0";
+        return DP_EINVAL;
+    }
+    return trace_displacements(ctx, opd, &p, 1, ps, o, cfg, &out, stream);
 }
 
 dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, const int32_t *p,
@@ -454,6 +468,27 @@ dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, 
     if (worst == DP_ENOCONV) ctx->err = "trace_estimate: some right-hand sides did not converge";
     if (worst == DP_EBREAKDOWN) ctx->err = "trace_estimate: CG breakdown";
     return worst;
+}
+
+dp_status dp_trace_multi(dp_ctx *ctx, const dp_operator *op, const int32_t *disp, int32_t ndisp,
+                         const dp_probe_spec *ps, const dp_solve_opts *o, dp_trace_result *out, hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!op || !disp || ndisp < 1 || !ps || !out) {
+        ctx->err = "trace_multi: bad arguments";
+        return DP_EINVAL;
+    }
+    SolveCfg cfg;
+    DP_TRY(solve_cfg(ctx, o, cfg));
+    WorkStream ws_;
+    DP_TRY(ws_.enter(ctx, stream, cfg.use_graph));
+    struct Leave {
+        WorkStream &w;
+        ~Leave() { (void)w.leave(); }
+    } leave_{ws_};
+    dp_status st = trace_displacements(ctx, *op, disp, ndisp, *ps, o, cfg, out, ws_.s);
+    if (st == DP_ENOCONV) ctx->err = "trace_multi: some right-hand sides did not converge";
+    if (st == DP_EBREAKDOWN) ctx->err = "trace_multi: CG breakdown";
+    return st;
 }
 
 dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *opd, int32_t p, const dp_probe_spec *ps,
