@@ -97,6 +97,50 @@ dp_status dp_build_coloring(const int32_t dims[4], int32_t p, const int32_t *ks,
                             int32_t nlevels, int32_t order, int32_t *colors,
                             int32_t *ncolors, int32_t *order_used);
 
+/*
+ * Colouring for several displacements at once (Sec. 3.4): the greedy
+ * colouring of N(x, [p_1..p_n], k) = N(x, p_1, k) u ... u N(x, p_n, k).
+ *   disp   host int32[ndisp], each >= 0, ndisp >= 1 (ndisp = 1 is
+ *          dp_build_coloring).  The other arguments are those of
+ *          dp_build_coloring (nested levels included).
+ * Host only; deterministic. */
+dp_status dp_build_coloring_multi(const int32_t dims[4], const int32_t *disp, int32_t ndisp,
+                                  const int32_t *ks, int32_t nlevels, int32_t order, int32_t *colors,
+                                  int32_t *ncolors, int32_t *order_used);
+
+/*
+ * Tile of the displaced distance-k colouring (Sec. 3.5): along dimension 0
+ * (the displacement) at least 2(p+k)+1 sites, along the others at least
+ * 2k+1, each rounded up to a power of two and capped at the lattice extent
+ * (an extent the power of two does not divide takes its smallest divisor
+ * that is at least the minimum).
+ *   tile   host int32[4], written. */
+dp_status dp_tile_shape(const int32_t dims[4], int32_t p, int32_t k, int32_t tile[4]);
+
+/*
+ * Tiled colouring (Sec. 3.5): the greedy (p, k) colouring of the tile torus
+ * (dp_tile_shape), repeated over the lattice; valid on the lattice because
+ * every tile side holds a whole neighbourhood or equals the lattice extent.
+ * With the environment variable DP_COLOR_CACHE naming a directory, tile
+ * colourings are read from and written to files there (one per tile, p, k
+ * and order), the colouring database of Sec. 3.5.
+ *   colors  host int32[N], ncolors host int32, order_used host int32 (may
+ *           be NULL), tile host int32[4] (may be NULL): written. */
+dp_status dp_build_coloring_tiled(const int32_t dims[4], int32_t p, int32_t k, int32_t order,
+                                  int32_t *colors, int32_t *ncolors, int32_t *order_used,
+                                  int32_t tile[4]);
+
+/*
+ * Clearance of a colouring for displacement p (Sec. 4.3, Table Clearance):
+ * for k = 0..kmax, the percentage of the sites at torus L1 distance exactly k
+ * from x + p e0 or from x - p e0 (x excluded) that share the colour of x,
+ * averaged over all sites x; 0 means distance k is cleared (for a (p0, k0)
+ * colouring every k <= k0 - |p0 - p|, Thm. Clearance).
+ *   colors  host int32[N]; pct host double[kmax+1], written.
+ * Host only; cost N times the number of offsets within reach. */
+dp_status dp_clearance(const int32_t dims[4], const int32_t *colors, int32_t p, int32_t kmax,
+                       double *pct);
+
 /* Which probing vectors to use (Sec. 2.1-2.2, eqs. (3)-(4)). */
 typedef struct {
     int32_t dims[4];

@@ -56,6 +56,9 @@ def lib():
         L.or_color.argtypes = [i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, i32p]
         L.or_color.restype = ctypes.c_int
+        L.or_color_multi.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, i32p]
+        L.or_color_multi.restype = ctypes.c_int
         L.or_color_nested.argtypes = [i32p, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
                                       ctypes.c_int32, i32p, i32p]
         L.or_color_nested.restype = ctypes.c_int
@@ -140,6 +143,16 @@ def coloring(dims, p: int, k: int, order: int = NATURAL, d: int = 4):
     col = np.zeros(volume(D), dtype=np.int32)
     n = lib().or_color(D, d, p, k, order, col)
     return col, n, order
+
+
+def coloring_multi(dims, ps, k: int, order: int = NATURAL, d: int = 4):
+    """Greedy colouring of N(x, [p_1..p_n], k), the union of the displaced
+    neighbourhoods (Sec. 3.4).  Returns (colors int32[N], ncolors)."""
+    D = _dims(dims)
+    ps = np.ascontiguousarray(ps, dtype=np.int32)
+    col = np.zeros(volume(D), dtype=np.int32)
+    n = lib().or_color_multi(D, d, ps, len(ps), k, order, col)
+    return col, n
 
 
 def coloring_nested(dims, p: int, ks, order: int = NATURAL, d: int = 4):

@@ -122,12 +122,10 @@ void or_order(const int32_t *D, int32_t order, int64_t *out) {
 /* (used for the nested levels, see or_color_nested).                  */
 /* ------------------------------------------------------------------ */
 
-static int greedy(const int32_t *D, int32_t d, int32_t p, int32_t k, int32_t order,
-                  const int32_t *parent, int32_t *col) {
+/* greedy first fit over the neighbourhood given by the S offsets st[S][4] */
+static int greedy_offsets(const int32_t *D, const int32_t *st, int S, int32_t order,
+                          const int32_t *parent, int32_t *col) {
     int64_t N = volume(D);
-    int S = or_stencil(p, k, d, NULL, 0);
-    int32_t *st = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(S > 0 ? S : 1));
-    or_stencil(p, k, d, st, S);
     int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
     or_order(D, order, ord);
     /* at most |stencil| neighbours, so at most S+1 colours (Sec. 3.1) */
@@ -150,6 +148,15 @@ static int greedy(const int32_t *D, int32_t d, int32_t p, int32_t k, int32_t ord
     }
     free(used);
     free(ord);
+    return ncol;
+}
+
+static int greedy(const int32_t *D, int32_t d, int32_t p, int32_t k, int32_t order,
+                  const int32_t *parent, int32_t *col) {
+    int S = or_stencil(p, k, d, NULL, 0);
+    int32_t *st = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(S > 0 ? S : 1));
+    or_stencil(p, k, d, st, S);
+    int ncol = greedy_offsets(D, st, S, order, parent, col);
     free(st);
     return ncol;
 }
@@ -157,6 +164,25 @@ static int greedy(const int32_t *D, int32_t d, int32_t p, int32_t k, int32_t ord
 int or_color(const int32_t *D, int32_t d, int32_t p, int32_t k, int32_t order,
              int32_t *colors) {
     return greedy(D, d, p, k, order, NULL, colors);
+}
+
+/* Multiple displacements (Sec. 3.4): the neighbourhood is the union
+ * N(x,p_1,k) u ... u N(x,p_n,k); the offsets of the n stencils are simply
+ * concatenated (an offset listed twice marks the same colour twice). */
+int or_color_multi(const int32_t *D, int32_t d, const int32_t *ps, int32_t np, int32_t k,
+                   int32_t order, int32_t *colors) {
+    int S = 0;
+    for (int i = 0; i < np; ++i) S += or_stencil(ps[i], k, d, NULL, 0);
+    int32_t *st = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(S > 0 ? S : 1));
+    int at = 0;
+    for (int i = 0; i < np; ++i) {
+        int Si = or_stencil(ps[i], k, d, NULL, 0);
+        or_stencil(ps[i], k, d, st + 4 * at, Si);
+        at += Si;
+    }
+    int ncol = greedy_offsets(D, st, S, order, NULL, colors);
+    free(st);
+    return ncol;
 }
 
 /* Nested (hierarchical) displaced colouring for distances ks[0] < ks[1] < ...

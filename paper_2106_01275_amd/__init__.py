@@ -5,7 +5,8 @@ Argument marshalling only: every step of the method runs in the library's
 HIP kernels (or, for the colouring, its host code).  PyTorch provides device
 memory and streams.  The names follow the C ABI in include/dp.h:
 
-    build_coloring, make_probes, solve_batch, trace_estimate, trace_multi,
+    build_coloring, build_coloring_multi, tile_shape, build_coloring_tiled,
+    clearance, make_probes, solve_batch, trace_estimate, trace_multi,
     trace_grad, apply (the operator, for verification)
 
 plus ProbedTrace, a torch.autograd.Function over trace_estimate/trace_grad.
@@ -73,8 +74,9 @@ class TraceResult(ctypes.Structure):
                 ("per_sample", ctypes.c_void_p), ("per_rhs", ctypes.c_void_p), ("solve", SolveStats)]
 
 
-EXPORTS = ["dp_create", "dp_destroy", "dp_last_error", "dp_build_coloring", "dp_make_probes",
-           "dp_solve_batch", "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply"]
+EXPORTS = ["dp_create", "dp_destroy", "dp_last_error", "dp_build_coloring", "dp_build_coloring_multi",
+           "dp_tile_shape", "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
+           "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply"]
 
 _lib = None
 
@@ -93,6 +95,10 @@ def lib():
         L.dp_last_error.argtypes = [vp]
         L.dp_last_error.restype = ctypes.c_char_p
         L.dp_build_coloring.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp]
+        L.dp_build_coloring_multi.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, vp]
+        L.dp_tile_shape.argtypes = [vp, i32, i32, vp]
+        L.dp_build_coloring_tiled.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+        L.dp_clearance.argtypes = [vp, vp, i32, i32, vp]
         L.dp_make_probes.argtypes = [vp, ctypes.POINTER(ProbeSpec), i64, i64, vp, vp]
         L.dp_solve_batch.argtypes = [vp, i32, ctypes.POINTER(Operator), vp, vp, vp,
                                      ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
@@ -103,7 +109,8 @@ def lib():
         L.dp_trace_grad.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(ProbeSpec),
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp, vp, vp, vp]
         L.dp_apply.argtypes = [vp, ctypes.POINTER(Operator), i32, vp, vp, i64, vp]
-        for name in ("dp_create", "dp_build_coloring", "dp_make_probes", "dp_solve_batch",
+        for name in ("dp_create", "dp_build_coloring", "dp_build_coloring_multi", "dp_tile_shape",
+                     "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
                      "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
@@ -139,6 +146,66 @@ def build_coloring(dims, p, ks, order="natural"):
     if flat:
         return col[0], int(nc[0]), used_name
     return col, nc, used_name
+
+
+def build_coloring_multi(dims, disps, ks, order="natural"):
+    """Greedy colouring of the union of the displaced neighbourhoods of the
+    displacements disps (Sec. 3.4).  Same returns as build_coloring."""
+    flat = np.isscalar(ks)
+    ks = _i32([ks] if flat else list(ks))
+    d = _i32(_dims4(dims))
+    ds = _i32(list(disps))
+    N = int(np.prod(d))
+    col = np.zeros((len(ks), N), dtype=np.int32)
+    nc = np.zeros(len(ks), dtype=np.int32)
+    used = np.zeros(1, dtype=np.int32)
+    st = lib().dp_build_coloring_multi(d.ctypes.data, ds.ctypes.data, len(ds), ks.ctypes.data, len(ks),
+                                       ORDER[order], col.ctypes.data, nc.ctypes.data, used.ctypes.data)
+    if st != OK:
+        raise DPError(st, lib().dp_last_error(None).decode())
+    used_name = {v: k for k, v in ORDER.items()}[int(used[0])]
+    if flat:
+        return col[0], int(nc[0]), used_name
+    return col, nc, used_name
+
+
+def tile_shape(dims, p, k):
+    """Tile of the (p, k) colouring (Sec. 3.5), a tuple of 4 extents."""
+    d = _i32(_dims4(dims))
+    t = np.zeros(4, dtype=np.int32)
+    st = lib().dp_tile_shape(d.ctypes.data, int(p), int(k), t.ctypes.data)
+    if st != OK:
+        raise DPError(st, lib().dp_last_error(None).decode())
+    return tuple(int(v) for v in t)
+
+
+def build_coloring_tiled(dims, p, k, order="natural"):
+    """Tiled (p, k) colouring (Sec. 3.5): returns (colors int32[N], ncolors,
+    order used, tile).  DP_COLOR_CACHE (a directory) caches tile colourings."""
+    d = _i32(_dims4(dims))
+    N = int(np.prod(d))
+    col = np.zeros(N, dtype=np.int32)
+    nc = np.zeros(1, dtype=np.int32)
+    used = np.zeros(1, dtype=np.int32)
+    t = np.zeros(4, dtype=np.int32)
+    st = lib().dp_build_coloring_tiled(d.ctypes.data, int(p), int(k), ORDER[order], col.ctypes.data,
+                                       nc.ctypes.data, used.ctypes.data, t.ctypes.data)
+    if st != OK:
+        raise DPError(st, lib().dp_last_error(None).decode())
+    return col, int(nc[0]), {v: k_ for k_, v in ORDER.items()}[int(used[0])], tuple(int(v) for v in t)
+
+
+def clearance(dims, colors, p, kmax):
+    """Table Clearance (Sec. 4.3): percentage of the sites at distance
+    exactly k (k = 0..kmax) from x +- p e0 that share the colour of x,
+    averaged over x.  Returns float64[kmax + 1]."""
+    d = _i32(_dims4(dims))
+    col = _i32(colors)
+    out = np.zeros(kmax + 1)
+    st = lib().dp_clearance(d.ctypes.data, col.ctypes.data, int(p), int(kmax), out.ctypes.data)
+    if st != OK:
+        raise DPError(st, lib().dp_last_error(None).decode())
+    return out
 
 
 class Context:

@@ -130,6 +130,20 @@ dp_status final_status(const dp_solve_stats &st) {
 
 }  // namespace
 
+// host-only colouring utilities: exceptions become status codes
+template <typename F>
+static dp_status host_call(const char *name, F f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        g_err = std::string(name) + ": out of host memory";
+        return DP_ENOMEM;
+    } catch (...) {
+        g_err = std::string(name) + ": internal error";
+        return DP_EINVAL;
+    }
+}
+
 extern "C" {
 
 dp_status dp_create(dp_ctx **out, int32_t hip_device) {
@@ -200,6 +214,51 @@ dp_status dp_build_coloring(const int32_t dims[4], int32_t p, const int32_t *ks,
         g_err = "build_coloring: internal error";
         return DP_EINVAL;
     }
+}
+
+dp_status dp_build_coloring_multi(const int32_t dims[4], const int32_t *disp, int32_t ndisp, const int32_t *ks,
+                                  int32_t nlevels, int32_t order, int32_t *colors, int32_t *ncolors,
+                                  int32_t *order_used) {
+    if (!dims) {
+        g_err = "build_coloring_multi: null dims";
+        return DP_EINVAL;
+    }
+    return host_call("build_coloring_multi", [&] {
+        return build_coloring_multi(dims, disp, ndisp, ks, nlevels, order, colors, ncolors, order_used, g_err);
+    });
+}
+
+dp_status dp_tile_shape(const int32_t dims[4], int32_t p, int32_t k, int32_t tile[4]) {
+    if (!dims || !tile || p < 0 || k < 0) {
+        g_err = "tile_shape: bad arguments";
+        return DP_EINVAL;
+    }
+    for (int d = 0; d < 4; ++d)
+        if (dims[d] < 1) {
+            g_err = "tile_shape: dims must be >= 1";
+            return DP_EINVAL;
+        }
+    tile_shape(dims, p, k, tile);
+    return DP_OK;
+}
+
+dp_status dp_build_coloring_tiled(const int32_t dims[4], int32_t p, int32_t k, int32_t order, int32_t *colors,
+                                  int32_t *ncolors, int32_t *order_used, int32_t tile[4]) {
+    if (!dims) {
+        g_err = "build_coloring_tiled: null dims";
+        return DP_EINVAL;
+    }
+    return host_call("build_coloring_tiled", [&] {
+        return build_coloring_tiled(dims, p, k, order, colors, ncolors, order_used, tile, g_err);
+    });
+}
+
+dp_status dp_clearance(const int32_t dims[4], const int32_t *colors, int32_t p, int32_t kmax, double *pct) {
+    if (!dims) {
+        g_err = "clearance: null dims";
+        return DP_EINVAL;
+    }
+    return host_call("clearance", [&] { return clearance(dims, colors, p, kmax, pct, g_err); });
 }
 
 dp_status dp_make_probes(dp_ctx *ctx, const dp_probe_spec *ps, int64_t rhs0, int64_t nrhs, void *out,

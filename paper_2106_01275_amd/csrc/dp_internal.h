@@ -12,9 +12,18 @@ namespace dp {
 
 // ---------------------------------------------------------------- colouring
 std::vector<std::array<int32_t, 4>> displaced_stencil(int32_t p, int32_t k);
+std::vector<std::array<int32_t, 4>> displaced_stencil(const int32_t *ps, int32_t np, int32_t k);
 dp_status build_coloring(const int32_t dims[4], int32_t p, const int32_t *ks, int32_t nlevels,
                          int32_t order, int32_t *colors, int32_t *ncolors, int32_t *order_used,
                          std::string &err);
+dp_status build_coloring_multi(const int32_t dims[4], const int32_t *ps, int32_t np, const int32_t *ks,
+                               int32_t nlevels, int32_t order, int32_t *colors, int32_t *ncolors,
+                               int32_t *order_used, std::string &err);
+void tile_shape(const int32_t dims[4], int32_t p, int32_t k, int32_t tile[4]);
+dp_status build_coloring_tiled(const int32_t dims[4], int32_t p, int32_t k, int32_t order, int32_t *colors,
+                               int32_t *ncolors, int32_t *order_used, int32_t tile[4], std::string &err);
+dp_status clearance(const int32_t dims[4], const int32_t *colors, int32_t p, int32_t kmax, double *pct,
+                    std::string &err);
 
 // ---------------------------------------------------------------- device side
 constexpr int kBlock = 256;      // threads per workgroup of every lattice kernel

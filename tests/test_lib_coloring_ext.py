@@ -1,0 +1,151 @@
+"""Host checks (no GPU) of the colouring extensions of the library against
+the oracle and against brute force:
+
+* multiple displacements (Sec. 3.4): bit-exact with the oracle's greedy over
+  the union of the displaced neighbourhoods, and valid by brute force;
+* tiles (Sec. 3.5): the tile policy equals the oracle's (itself pinned to all
+  90 entries of Table Tiles); the tiled colouring is the oracle's tile
+  colouring repeated, and valid on the whole lattice by brute force;
+* the colouring database (DP_COLOR_CACHE);
+* Table Clearance's measure (Sec. 4.3): brute force on small tori, zeros where
+  Thm. Clearance puts them, 100% for one colour and 0% for all-distinct."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bounds
+import paper_2106_01275_amd as dp
+
+ORD = {"natural": oracle.NATURAL, "redblack": oracle.REDBLACK}
+
+
+def _coords(dims):
+    return np.array(list(itertools.product(*[range(D) for D in dims])), dtype=np.int64)
+
+
+def _index(x, dims):
+    i = np.zeros(len(x), dtype=np.int64)
+    for d in range(4):
+        i = i * dims[d] + np.mod(x[:, d], dims[d])
+    return i
+
+
+def _valid(dims, col, ps, k):
+    """No two sites of N(x, [ps], k) share a colour (brute force)."""
+    X = _coords(dims)
+    for p in ps:
+        for o in oracle.stencil(p, k):
+            y = _index(X + o, dims)
+            x = _index(X, dims)
+            clash = (col[y] == col[x]) & (y != x)
+            if clash.any():
+                return False
+    return True
+
+
+@pytest.mark.parametrize("dims,ps,k,order", [
+    ((8, 4, 4, 4), [1, 2], 1, "natural"), ((8, 4, 4, 4), [0, 3], 1, "redblack"),
+    ((12, 6, 4, 4), [1, 2, 3], 2, "natural"), ((16, 4, 4, 2), [2, 6], 1, "natural"),
+    ((6, 6, 6, 6), [1], 2, "natural")])
+def test_multi_displacement_matches_oracle_and_is_valid(dims, ps, k, order):
+    col, n, _ = dp.build_coloring_multi(dims, ps, k, order)
+    ocol, on = oracle.coloring_multi(dims, ps, k, ORD[order])
+    assert n == on and np.array_equal(col, ocol)
+    assert _valid(dims, col, ps, k)
+    if len(ps) == 1:
+        c1, n1, _ = dp.build_coloring(dims, ps[0], k, order)
+        assert n1 == n and np.array_equal(c1, col)
+    # the union colouring is valid for every single displacement as well
+    for p in ps:
+        assert _valid(dims, col, [p], k)
+
+
+def test_tile_policy_matches_oracle():
+    """Table Tiles lattice (32^3 x 64, displacement along the first extent)
+    for p = 0..8, k = 1..10, and lattices whose extents are not powers of two."""
+    for p in range(9):
+        for k in range(1, 11):
+            assert dp.tile_shape((32, 32, 32, 64), p, k) == bounds.tile_shape((32, 32, 32, 64), p, k), (p, k)
+    for dims in [(24, 24, 24, 48), (12, 10, 6, 8), (48, 36, 20, 16), (7, 7, 7, 7)]:
+        for p in range(4):
+            for k in range(1, 5):
+                assert dp.tile_shape(dims, p, k) == bounds.tile_shape(dims, p, k), (dims, p, k)
+
+
+@pytest.mark.parametrize("dims,p,k,order", [
+    ((32, 8, 8, 8), 1, 1, "natural"), ((16, 16, 8, 8), 2, 1, "redblack"),
+    ((24, 12, 12, 12), 1, 2, "natural"), ((16, 8, 8, 16), 0, 2, "natural")])
+def test_tiled_coloring_is_the_repeated_tile_and_valid(dims, p, k, order):
+    col, n, used, tile = dp.build_coloring_tiled(dims, p, k, order)
+    assert tile == bounds.tile_shape(dims, p, k)
+    assert all(D % t == 0 for D, t in zip(dims, tile))
+    tcol, tn, _ = oracle.coloring(tile, p, k, ORD[order])
+    assert n == tn
+    X = _coords(dims)
+    assert np.array_equal(col, tcol[_index(X % np.array(tile), tile)])
+    assert _valid(dims, col, [p], k)
+
+
+def test_coloring_cache(tmp_path, monkeypatch):
+    monkeypatch.setenv("DP_COLOR_CACHE", str(tmp_path))
+    dims, p, k = (16, 8, 8, 8), 1, 1
+    c1, n1, u1, t1 = dp.build_coloring_tiled(dims, p, k, "natural")
+    files = list(tmp_path.iterdir())
+    assert len(files) == 1 and files[0].name.startswith("tile_8x4x4x4_p1_k1_")
+    c2, n2, u2, t2 = dp.build_coloring_tiled(dims, p, k, "natural")
+    assert np.array_equal(c1, c2) and n1 == n2 and u1 == u2 and t1 == t2
+    # a damaged entry is ignored and rewritten
+    files[0].write_bytes(files[0].read_bytes()[:40])
+    c3, n3, _, _ = dp.build_coloring_tiled(dims, p, k, "natural")
+    assert np.array_equal(c1, c3) and n1 == n3
+    assert files[0].stat().st_size > 40
+
+
+def _clearance_brute(dims, col, p, kmax):
+    """Per site x: the sites y != x at torus L1 distance exactly k from
+    x + p e0 or from x - p e0, the share with the colour of x."""
+    X = _coords(dims)
+    N = len(X)
+    Dv = np.array(dims)
+
+    def tdist(a, b):
+        d = np.abs(a - b) % Dv
+        return np.minimum(d, Dv - d).sum(-1)
+
+    same = np.zeros(kmax + 1)
+    tot = np.zeros(kmax + 1)
+    e0 = np.array([p, 0, 0, 0])
+    for i in range(N):
+        dp_ = tdist(X, X[i] + e0)
+        dm_ = tdist(X, X[i] - e0)
+        for k in range(kmax + 1):
+            m = ((dp_ == k) | (dm_ == k))
+            m[i] = False
+            tot[k] += m.sum()
+            same[k] += (m & (col == col[i])).sum()
+    return np.where(tot > 0, 100.0 * same / np.maximum(tot, 1), 0.0)
+
+
+@pytest.mark.parametrize("dims,p0,k0", [((6, 4, 4, 4), 1, 2), ((8, 4, 4, 2), 2, 1), ((5, 3, 4, 4), 0, 2)])
+def test_clearance_matches_brute_force_and_theorem(dims, p0, k0):
+    col, n, _ = dp.build_coloring(dims, p0, k0, "natural")
+    for p in range(0, 4):
+        got = dp.clearance(dims, col, p, 4)
+        assert np.allclose(got, _clearance_brute(dims, col, p, 4), atol=1e-12), p
+        # Thm. Clearance: a (p0, k0) colouring clears every k <= k0 - |p0 - p| for displacement p
+        for k in range(0, max(0, k0 - abs(p0 - p)) + 1):
+            if not (k == 0 and p == 0):
+                assert got[k] == 0.0, (p, k, got)
+
+
+def test_clearance_extremes():
+    dims = (4, 4, 4, 4)
+    one = np.zeros(256, dtype=np.int32)
+    allc = np.arange(256, dtype=np.int32)
+    for p in (0, 1, 2):
+        g1 = dp.clearance(dims, one, p, 3)
+        ga = dp.clearance(dims, allc, p, 3)
+        assert np.all(ga == 0.0)
+        assert np.all(g1[1:] == 100.0) and (p == 0 or g1[0] == 100.0)
