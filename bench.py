@@ -175,6 +175,16 @@ def run_gauge16(a, torch, dp, workloads):
               "T_mean": [Ts.mean().real, Ts.mean().imag]}
     extra = {"time_to_trace_1e-3": tt}
     if not a.no_plain:
+        # one probe set for the displacements n = 0..8 (Sec. 4.3): the same solves, nine contractions
+        ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, 0, 1, "z2_complex", True)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        rm = c.trace_multi(op, ps, list(range(9)), c.opts(tol=w.tol, inner=inner, rhs_block=W))
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - tm
+        extra["multi_displacement"] = {"displacements": list(range(9)), "seconds": tm,
+                                       "seconds_one_displacement": sec_per_sample,
+                                       "T": [[r_["T"].real, r_["T"].imag] for r_ in rm]}
         # plain single-RHS FP64 GPU solver on a few of the same right-hand sides
         nplain = 8
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, 0, 1, "z2_complex", True)
