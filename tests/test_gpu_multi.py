@@ -137,3 +137,15 @@ def test_variance_and_speedup_from_gpu_samples(ctx):
     # the estimate itself is unbiased: within 5 standard errors of the exact trace
     exact = np.trace(B)
     assert abs(r["T"] - exact) < 5 * np.sqrt(v_probed_exact / ns)
+
+
+def test_trace_multi_rejects_bad_arguments(ctx):
+    dims = (4, 4, 4, 4)
+    col, m, _ = oracle.coloring(dims, 1, 1, oracle.NATURAL)
+    ps = ctx.probe_spec(dims, 1, cuda(col), m, 0, 0, 1, "real_z2", False)
+    op = ctx.operator(dims, 1, 0.5, None)
+    with pytest.raises(dp.DPError):
+        ctx.trace_multi(op, ps, [], ctx.opts())
+    ps_bad = ctx.probe_spec((4, 4, 4, 2), 1, cuda(col[:128]), m, 0, 0, 1, "real_z2", False)
+    with pytest.raises(dp.DPError):
+        ctx.trace_multi(op, ps_bad, [0, 1], ctx.opts())

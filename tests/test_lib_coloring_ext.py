@@ -149,3 +149,22 @@ def test_clearance_extremes():
         ga = dp.clearance(dims, allc, p, 3)
         assert np.all(ga == 0.0)
         assert np.all(g1[1:] == 100.0) and (p == 0 or g1[0] == 100.0)
+
+
+def test_extensions_reject_bad_arguments():
+    with pytest.raises(dp.DPError):
+        dp.build_coloring_multi((4, 4, 4, 4), [], 1)
+    with pytest.raises(dp.DPError):
+        dp.build_coloring_multi((4, 4, 4, 4), [1, -2], 1)
+    with pytest.raises(dp.DPError):
+        dp.build_coloring_multi((4, 4, 4, 4), [1, 2], [2, 1])
+    with pytest.raises(dp.DPError):
+        dp.tile_shape((4, 0, 4, 4), 1, 1)
+    with pytest.raises(dp.DPError):
+        dp.tile_shape((4, 4, 4, 4), -1, 1)
+    with pytest.raises(dp.DPError):
+        dp.build_coloring_tiled((4, 4, 4, 4), 1, -1)
+    with pytest.raises(dp.DPError):
+        dp.clearance((4, 4, 4, 4), np.zeros(256, np.int32), -1, 2)
+    with pytest.raises(dp.DPError):
+        dp.clearance((4, 4, 4, 4), np.zeros(256, np.int32), 1, -1)
