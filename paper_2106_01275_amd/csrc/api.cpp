@@ -183,6 +183,8 @@ void dp_destroy(dp_ctx *ctx) {
     (void)hipDeviceSynchronize();
     for (int s = 0; s < kNumSlots; ++s)
         if (ctx->slot[s]) (void)hipFree(ctx->slot[s]);
+    for (auto &b : ctx->pool) (void)hipFree(b.first);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto &pr : ctx->ev_pending) {
         (void)hipEventDestroy(pr.first);

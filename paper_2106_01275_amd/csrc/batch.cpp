@@ -24,19 +24,23 @@ namespace {
 
 constexpr int kMaxSlots = 64;
 
+// Buffers of one call, taken from the context's pool and returned to it at
+// the end of the call (the stream is synchronised before that).
 struct DevBuf {
-    std::vector<void *> ptrs;
+    dp_ctx *ctx;
+    hipStream_t s;
+    std::vector<std::pair<void *, size_t>> ptrs;
+    DevBuf(dp_ctx *c, hipStream_t st) : ctx(c), s(st) {}
     ~DevBuf() {
-        for (void *p : ptrs) (void)hipFree(p);
+        (void)hipStreamSynchronize(s);
+        for (auto &b : ptrs) ctx->pool_put(b.first, b.second);
     }
-    dp_status alloc(dp_ctx *ctx, void **out, size_t bytes, bool zero = false) {
+    dp_status alloc(dp_ctx *, void **out, size_t bytes, bool zero = false) {
         void *p = nullptr;
-        if (hipMalloc(&p, bytes ? bytes : 256) != hipSuccess) {
-            ctx->err = "batch: out of device memory";
-            return DP_ENOMEM;
-        }
-        ptrs.push_back(p);
-        if (zero) DP_HIP(hipMemset(p, 0, bytes ? bytes : 256));
+        size_t got = 0;
+        DP_TRY(ctx->pool_get(bytes, &p, &got));
+        ptrs.emplace_back(p, got);
+        if (zero) DP_HIP(hipMemsetAsync(p, 0, bytes ? bytes : 256, s));
         *out = p;
         return DP_OK;
     }
@@ -61,7 +65,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     const bool links = in[0].links;
     int logW = 0;
     while ((1 << logW) < W) ++logW;
-    DevBuf mem;
+    DevBuf mem(ctx, s);
 
     // per-instance operator data: neighbour table and converted links
     int maxN = 0;
@@ -104,6 +108,15 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     std::vector<SlotDesc> hsd(nslots);
     int *ctrl_all = nullptr;
     DP_TRY(mem.alloc(ctx, (void **)&ctrl_all, (size_t)nslots * 8 * sizeof(double), true));
+    // CG state of all slots in one block (one stride per slot), mirrored in
+    // pinned host memory for the read-back of finished slots
+    const size_t st_doubles = 9 * kMaxW + 8, st_ints = 3 * kMaxW + 8;
+    const size_t st_stride = (st_doubles * sizeof(double) + st_ints * sizeof(int) + 255) / 256 * 256;
+    char *st_all = nullptr;
+    DP_TRY(mem.alloc(ctx, (void **)&st_all, st_stride * nslots));
+    char *st_host = nullptr;
+    DP_TRY(ctx->host_pinned(st_stride * nslots + sizeof(int) * 16 * nslots, (void **)&st_host));
+    int *hctrl = (int *)(st_host + st_stride * nslots);
     for (int k = 0; k < nslots; ++k) {
         SlotDesc &d = hsd[k];
         std::memset(&d, 0, sizeof d);
@@ -118,8 +131,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             d.xlo = d.x64;
         DP_TRY(mem.alloc(ctx, (void **)&d.rd.part1, (size_t)W * nblk * 2 * sizeof(double)));
         d.rd.nblk = nblk;
-        double *st = nullptr;
-        DP_TRY(mem.alloc(ctx, (void **)&st, (9 * kMaxW + 8) * sizeof(double) + (3 * kMaxW + 8) * sizeof(int)));
+        double *st = (double *)(st_all + st_stride * k);
         CgState &cs = d.cs;
         cs.rr = st;
         cs.rr_prev = st + kMaxW;
@@ -218,16 +230,15 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             if (d.flags & kSlotInit) d.flags = kSlotIter;
         return upload();
     };
-    std::vector<int> hctrl((size_t)nslots * 16);
     auto read_ctrl_all = [&]() -> dp_status {
         launch_b_ctrl(B);
-        DP_HIP(hipMemcpyAsync(hctrl.data(), ctrl_all, sizeof(int) * 16 * nslots, hipMemcpyDeviceToHost, s));
+        DP_HIP(hipMemcpyAsync(hctrl, ctrl_all, sizeof(int) * 16 * nslots, hipMemcpyDeviceToHost, s));
         DP_HIP(hipStreamSynchronize(s));
         if (cfg.profile) DP_TRY(finish_profile(ctx, &in[0].st));
         return DP_OK;
     };
     // contract / copy out the slots flagged kSlotFinal and record statistics
-    std::vector<double> hres(6 * kMaxW);
+    // (one copy per finished slot into its pinned mirror, one synchronisation)
     auto finish_slots = [&]() -> dp_status {
         DP_TRY(upload());
         launch_b_ru(B, 1);
@@ -236,27 +247,30 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         for (int k = 0; k < nslots; ++k) {
             if (!(hsd[k].flags & kSlotFinal)) continue;
             const Job &jb = jobs[slot_job[k]];
+            if (!trace_mode) launch_to_abi(hsd[k].L, hsd[k].x64, in[jb.inst].xabi, jb.r0, jb.nv);
+            DP_HIP(hipMemcpyAsync(st_host + st_stride * k, st_all + st_stride * k, st_stride, hipMemcpyDeviceToHost,
+                                  s));
+        }
+        DP_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < nslots; ++k) {
+            if (!(hsd[k].flags & kSlotFinal)) continue;
+            const Job &jb = jobs[slot_job[k]];
             BatchInst &I = in[jb.inst];
-            const CgState &cs = hsd[k].cs;
-            if (!trace_mode) launch_to_abi(hsd[k].L, hsd[k].x64, I.xabi, jb.r0, jb.nv);
-            double *h = hres.data();
-            int *hi = (int *)(h + 4 * kMaxW);
-            DP_HIP(hipMemcpyAsync(h, cs.true_rr, W * sizeof(double), hipMemcpyDeviceToHost, s));
-            DP_HIP(hipMemcpyAsync(h + kMaxW, cs.bb, W * sizeof(double), hipMemcpyDeviceToHost, s));
-            DP_HIP(hipMemcpyAsync(h + 2 * kMaxW, cs.tj, 2 * W * sizeof(double), hipMemcpyDeviceToHost, s));
-            DP_HIP(hipMemcpyAsync(hi, cs.iters, W * sizeof(int), hipMemcpyDeviceToHost, s));
-            DP_HIP(hipMemcpyAsync(hi + kMaxW, cs.flags, W * sizeof(int), hipMemcpyDeviceToHost, s));
-            DP_HIP(hipStreamSynchronize(s));
+            // the slot's state block: doubles rr .. tj as laid out above, then the ints
+            const double *hs = (const double *)(st_host + st_stride * k);
+            const double *true_rr = hs + 6 * kMaxW, *bbv = hs + 3 * kMaxW, *tj = hs + 7 * kMaxW;
+            const int *iv = (const int *)(hs + st_doubles);
+            const int *iters = iv + kMaxW, *flags = iv + 2 * kMaxW;
             for (int j = 0; j < jb.nv; ++j) {
-                const double bb = h[kMaxW + j];
-                I.st.max_true_resid = std::max(I.st.max_true_resid, bb > 0 ? std::sqrt(h[j] / bb) : 0.0);
-                I.st.rhs_iters += hi[j];
-                I.st.max_iters = std::max(I.st.max_iters, hi[j]);
-                if (hi[kMaxW + j] & kFlagBreakdown) ++I.st.nbreakdown;
-                else if (hi[kMaxW + j] & kFlagConverged) ++I.st.nconverged;
+                const double bb = bbv[j];
+                I.st.max_true_resid = std::max(I.st.max_true_resid, bb > 0 ? std::sqrt(true_rr[j] / bb) : 0.0);
+                I.st.rhs_iters += iters[j];
+                I.st.max_iters = std::max(I.st.max_iters, iters[j]);
+                if (flags[j] & kFlagBreakdown) ++I.st.nbreakdown;
+                else if (flags[j] & kFlagConverged) ++I.st.nconverged;
                 if (trace_mode) {
-                    I.tj[2 * (jb.r0 + j)] = h[2 * kMaxW + 2 * j];
-                    I.tj[2 * (jb.r0 + j) + 1] = h[2 * kMaxW + 2 * j + 1];
+                    I.tj[2 * (jb.r0 + j)] = tj[2 * j];
+                    I.tj[2 * (jb.r0 + j) + 1] = tj[2 * j + 1];
                 }
             }
             I.st.nrhs += jb.nv;
@@ -315,7 +329,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         for (int k = 0; k < nslots; ++k) {
             SlotDesc &d = hsd[k];
             if (!(d.flags & kSlotIter)) continue;
-            const int *c = hctrl.data() + 16 * k;
+            const int *c = hctrl + 16 * k;
             double ratio, ru_ratio;
             std::memcpy(&ratio, c + 8, sizeof(double));
             std::memcpy(&ru_ratio, c + 10, sizeof(double));

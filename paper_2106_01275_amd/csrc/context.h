@@ -67,8 +67,18 @@ struct dp_ctx {
     hipStream_t gstream = nullptr;            // library stream for graph capture
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::map<int, hipGraphExec_t> graphs;     // iteration groups by length (one solve)
+    // device buffers of the multi-instance engine, kept for the next call
+    // (hipMalloc / hipFree synchronise the device and cost far more than a
+    // small batch's solves)
+    std::vector<std::pair<void *, size_t>> pool;
+    void *pinned = nullptr;                   // pinned host staging of the multi-instance engine
+    size_t pinned_bytes = 0;
+    dp_status host_pinned(size_t bytes, void **out);  // at least `bytes`, kept for later calls
 
     void drop_graphs();
+    // smallest pooled buffer of at least `bytes`, else a new one; *got = its size
+    dp_status pool_get(size_t bytes, void **out, size_t *got);
+    void pool_put(void *p, size_t bytes);
 
     dp_status ensure(int s, size_t bytes, bool zero = false);
     void *at(int s) const { return slot[s]; }

@@ -46,6 +46,50 @@ dp_status dp_ctx::ensure(int s, size_t bytes, bool zero) {
     return DP_OK;
 }
 
+dp_status dp_ctx::pool_get(size_t bytes, void **out, size_t *got) {
+    if (bytes == 0) bytes = 256;
+    size_t best = pool.size();
+    for (size_t i = 0; i < pool.size(); ++i)
+        if (pool[i].second >= bytes && (best == pool.size() || pool[i].second < pool[best].second)) best = i;
+    if (best < pool.size()) {
+        *out = pool[best].first;
+        *got = pool[best].second;
+        pool.erase(pool.begin() + (long)best);
+        return DP_OK;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        // release the pooled buffers and try once more
+        for (auto &b : pool) (void)hipFree(b.first);
+        pool.clear();
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            err = "out of device memory (" + std::to_string(bytes) + " bytes)";
+            return DP_ENOMEM;
+        }
+    }
+    *out = p;
+    *got = bytes;
+    return DP_OK;
+}
+
+void dp_ctx::pool_put(void *p, size_t bytes) { pool.emplace_back(p, bytes ? bytes : 256); }
+
+dp_status dp_ctx::host_pinned(size_t bytes, void **out) {
+    if (pinned_bytes < bytes) {
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        pinned_bytes = 0;
+        if (hipHostMalloc(&pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+            pinned = nullptr;
+            err = "pinned host allocation failed";
+            return DP_ENOMEM;
+        }
+        pinned_bytes = bytes;
+    }
+    *out = pinned;
+    return DP_OK;
+}
+
 void dp_ctx::drop_graphs() {
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
