@@ -406,6 +406,17 @@ def main():
                   "max_true_resid": max(s["max_true_resid"] for s in stats),
                   "nconverged": sum(s["nconverged"] for s in stats), "nrhs": sum(s["nrhs"] for s in stats)},
     }
+    # whole-job bandwidth of the CG iterations: per stencil launch (one per CG iteration and slot)
+    # an iteration moves 10 vector passes plus the links, (10 V W + 4 L) / (2 V W + 4 L) times the
+    # stencil's own algorithmic bytes (every workload here is 3-colour with links); over the timed
+    # wall time, with reliable updates, checks and contractions inside it but not counted
+    cb = {"f64": 16, "f32": 8, "bf16": 4}[inner]
+    vw, lk = cb * 3 * config["rhs_block"], cb * 9
+    st_bytes = sum(s_["stencil_bytes"] for s_ in stats)
+    if st_bytes > 0:
+        cg_bytes = st_bytes * (10 * vw + 4 * lk) / (2 * vw + 4 * lk)
+        out["cg_bandwidth"] = {"alg_bytes": cg_bytes, "achieved": cg_bytes / elapsed / 1e9, "unit": "GB/s",
+                               "frac": cg_bytes / elapsed / 1e9 / HBM_PEAK_GBS}
     out.update(extra)
     if a.copy_ref_mib:
         # a plain copy kernel of known size: reads and writes copy_ref_mib MiB

@@ -653,7 +653,7 @@ dp_status dp_apply(dp_ctx *ctx, const dp_operator *opd, int32_t prec, const void
         sa.diag = op.m2 + 8.0;
         sa.pin = ctx->at(kSlotP);
         sa.q = ctx->at(kSlotQ);
-        sa.U = op.ULo;
+        sa.U = op.U8;
         sa.nbr = op.nbr;
         launch_stencil(L, prec, sa);
         launch_internal_to_abi_prec(L, prec, ctx->at(kSlotQ), (double *)y, r0, nv);

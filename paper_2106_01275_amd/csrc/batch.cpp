@@ -77,12 +77,8 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             const size_t nl = (size_t)I.lat.N * 4 * nc * nc;
             DP_TRY(mem.alloc(ctx, &I.U64, nl * 16));
             convert_links(kF64, I.lat, nc, I.links_abi, I.U64, s);
-            if (mixed) {
-                DP_TRY(mem.alloc(ctx, &I.ULo, nl * prec_bytes(cfg.inner)));
-                convert_links(cfg.inner, I.lat, nc, I.links_abi, I.ULo, s);
-            } else {
-                I.ULo = I.U64;
-            }
+            DP_TRY(mem.alloc(ctx, &I.U8, 2 * nl * prec_bytes(cfg.inner)));
+            gather_links(cfg.inner, I.lat, nc, I.links_abi, I.nbr, I.U8, s);
         }
     }
     DP_HIP(hipGetLastError());
@@ -187,7 +183,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         d.L.ntiles = (I.lat.N + spt - 1) / spt;
         d.L.stream = s;
         d.diag = I.m2 + 8.0;
-        d.U = I.ULo;
+        d.U = I.U8;
         d.U64 = I.U64;
         d.nbr = I.nbr;
         ProbeGen g{};

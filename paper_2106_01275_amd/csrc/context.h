@@ -27,7 +27,7 @@
 namespace dp {
 
 enum Slot {
-    kSlotNbr, kSlotU64, kSlotULo, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotXLo,
+    kSlotNbr, kSlotU64, kSlotU8, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotXLo,
     kSlotPart1, kSlotState, kSlotColors, kSlotVec, kNumSlots
 };
 
@@ -37,8 +37,8 @@ struct OpPrep {
     int nc = 1;
     double m2 = 0;
     bool links = false;
-    const void *U64 = nullptr;  // FP64 links [N][4][nc][nc]
-    const void *ULo = nullptr;  // inner-precision links
+    const void *U64 = nullptr;  // FP64 links [N][4][nc][nc] (the FP64 true residual)
+    const void *U8 = nullptr;   // hop links of the inner precision [N][8][nc][nc]: U_mu(x), then U_mu(x-mu)
     const int *nbr = nullptr;
     int inner = kF64;
 };
@@ -160,7 +160,7 @@ struct BatchInst {
     double m2 = 0;
     bool links = false;
     const void *links_abi = nullptr;   // caller's complex128 [4][N][nc][nc]
-    void *U64 = nullptr, *ULo = nullptr;
+    void *U64 = nullptr, *U8 = nullptr;
     int *nbr = nullptr;
     long long nrhs = 0;
     dp_probe_spec ps{};                // trace mode

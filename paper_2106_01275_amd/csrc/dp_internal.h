@@ -91,7 +91,7 @@ struct SlotDesc {
     int blk0;
     int flags;           // kSlot* phases this slot takes part in
     double diag;         // m2 + 8
-    const void *U;       // inner-precision links
+    const void *U;       // inner-precision hop links [N][8][nc][nc]
     const void *U64;     // FP64 links
     const int *nbr;
     void *r, *p, *q, *xlo;
@@ -122,6 +122,11 @@ void launch_b_ctrl(const BatchLaunch &B);
 int grid_blocks(int ntiles);
 void build_neighbours(const Lat &lat, int *nbr, hipStream_t s);
 void convert_links(int prec, const Lat &lat, int nc, const void *abi_links, void *out, hipStream_t s);
+// hop links [N][8][nc][nc] of storage precision prec: entry (x, mu) = U_mu(x),
+// entry (x, 4 + mu) = U_mu(x - mu) (not conjugated), gathered with the
+// neighbour table, so a site's eight hops are one contiguous record
+void gather_links(int prec, const Lat &lat, int nc, const void *abi_links, const int *nbr, void *out,
+                  hipStream_t s);
 
 void launch_init_probe(const Launch &L, int prec, const ProbeGen &g, double *b64, void *r, void *p,
                        void *xlo, double *x64, int mixed, const Red &rd, const CgState &cs);
@@ -134,7 +139,7 @@ struct StencilArgs {
     double diag = 0;
     const void *pin = nullptr;
     void *q = nullptr;
-    const void *U = nullptr;
+    const void *U = nullptr;     // hop links [N][8][nc][nc] (gather_links)
     const int *nbr = nullptr;
     int cg = 0;
     Red rd{};

@@ -435,6 +435,22 @@ __global__ void k_convert_links(Lat L, int nc, const double2 *__restrict__ in, L
                (typename St<LS>::R)v.y);
 }
 
+// ABI links -> hop links [N][8][nc][nc] of storage LS: (x, mu) = U_mu(x),
+// (x, 4 + mu) = U_mu(x - mu)
+template <typename LS>
+__global__ void k_gather_links(Lat L, int nc, const double2 *__restrict__ in, const int *__restrict__ nbr,
+                               LS *__restrict__ out) {
+    const long long n = 8LL * L.N * nc * nc;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int ab = (int)(e % (nc * nc));
+    const long long t = e / (nc * nc);
+    const int dir = (int)(t % 8), site = (int)(t / 8);
+    const int src = dir < 4 ? site : nbr[(size_t)site * 8 + dir];
+    const double2 v = in[((size_t)(dir & 3) * L.N + src) * nc * nc + ab];
+    St<LS>::st(out, e, (typename St<LS>::R)v.x, (typename St<LS>::R)v.y);
+}
+
 // Initialise one block of W right-hand sides: b (FP64), r = p = b (storage
 // precision), x = 0, and |b|^2 per lane; the finishing workgroup sets up
 // the CG scalars.  SRC 0: probes generated from ProbeGen; 1: from ABI b.
@@ -575,8 +591,9 @@ __device__ __forceinline__ void hop_words(uint32_t w, bool dag, uint32_t &A, uin
     B = dag ? n : w;
 }
 
-// Stages the hop words (A, B) of the tile's sites, element (a, b) of every
-// hop already transposed for the backward ones, and the neighbour indices.
+// Stages the hop words (A, B) of the tile's sites from the hop-link array,
+// element (a, b) of every hop already transposed for the backward ones, and
+// the neighbour indices.
 template <int NC>
 __device__ __forceinline__ void stage_tile_bf16(uint32_t *su, int *snb, const SiteWalk &wk, int item0,
                                                 int sites_per_tile, const bf16x2 *__restrict__ U,
@@ -591,10 +608,9 @@ __device__ __forceinline__ void stage_tile_bf16(uint32_t *su, int *snb, const Si
         uint32_t A = 0, B = 0;
         if (item0 + s_l < wk.items) {
             const int gs = walk_site(wk, item0 + s_l);
-            const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
             const int a = ab / NC, b = ab - a * NC;
             const int el = dir < 4 ? ab : b * NC + a;
-            hop_words(U[((size_t)src * 4 + (dir & 3)) * NC * NC + el].v, dir >= 4, A, B);
+            hop_words(U[((size_t)gs * 8 + dir) * NC * NC + el].v, dir >= 4, A, B);
         }
         su[2 * e] = A;
         su[2 * e + 1] = B;
@@ -667,9 +683,8 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
                         A = su[((sl * 8 + dir) * NC * NC + a * NC + b) * 2];
                         B = su[((sl * 8 + dir) * NC * NC + a * NC + b) * 2 + 1];
                     } else {
-                        const int src = dir < 4 ? site : y[dir + 1];
                         const int el = dir < 4 ? a * NC + b : b * NC + a;
-                        hop_words(U[((size_t)src * 4 + (dir & 3)) * NC * NC + el].v, dir >= 4, A, B);
+                        hop_words(U[((size_t)site * 8 + dir) * NC * NC + el].v, dir >= 4, A, B);
                     }
                     hr[a] = dot2_bf16(A, v[dir + 1][b], hr[a]);
                     hi[a] = dot2_bf16(B, vs[dir + 1][b], hi[a]);
@@ -692,6 +707,43 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
     if (!cg) return;
     double acc[1] = {acc_pq};
     block_partials<1>(bk, acc, W, logW, rd, sm);
+}
+
+// Stages the hop links of the tile's sites (one contiguous record of 8 links
+// per site) converted to R, and their neighbour indices.  All threads call
+// it; it ends with a barrier.
+template <typename LS, typename R, int NC, bool LINKS>
+__device__ __forceinline__ void stage_hops(R *su, int *snb, const SiteWalk &wk, int item0, int sites_per_tile,
+                                           const LS *__restrict__ U8, const int *__restrict__ nbr) {
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if (LINKS) {
+        const int ne = sites_per_tile * 8 * NC * NC;
+        for (int e = tid; e < ne; e += kBlock) {
+            const int s_l = e / (8 * NC * NC);
+            const int rem = e - s_l * 8 * NC * NC;
+            typename St<LS>::R re = 0, im = 0;
+            if (item0 + s_l < wk.items) St<LS>::ld(U8, (size_t)walk_site(wk, item0 + s_l) * 8 * NC * NC + rem, re, im);
+            su[2 * e] = (R)re;
+            su[2 * e + 1] = (R)im;
+        }
+    }
+    for (int e = tid; e < sites_per_tile * 8; e += kBlock)
+        snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
+    __syncthreads();
+}
+
+// hop link dir of site from the hop-link array, converted to R
+template <typename LS, typename R, int NC>
+__device__ __forceinline__ void ld_hop(const LS *__restrict__ U8, int site, int dir, R *u) {
+    const LS *base = U8 + ((size_t)site * 8 + dir) * NC * NC;
+#pragma unroll
+    for (int e = 0; e < NC * NC; ++e) {
+        typename St<LS>::R re, im;
+        St<LS>::ld(base, e, re, im);
+        u[2 * e] = (R)re;
+        u[2 * e + 1] = (R)im;
+    }
 }
 
 // The stencil q = A p for one block of right-hand sides, with p^H q summed
@@ -727,7 +779,7 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
     const SiteWalk wk = site_walk(L.lat, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
-        if (MODE == 1) stage_tile<LS, R, NC, LINKS>(su, snb, wk, item0, sites_per_tile, U, nbr);
+        if (MODE == 1) stage_hops<LS, R, NC, LINKS>(su, snb, wk, item0, sites_per_tile, U, nbr);
         if (item0 + sl >= wk.items) continue;
         const int site = walk_site(wk, item0 + sl);
         int y[9];
@@ -758,7 +810,7 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
 #pragma unroll
                 for (int e = 0; e < 2 * NC * NC; ++e) u[e] = su[(sl * 8 + dir) * NC * NC * 2 + e];
             } else {
-                ld_link<LS, R, NC>(U, dir < 4 ? site : y[dir + 1], dir & 3, u);
+                ld_hop<LS, R, NC>(U, site, dir, u);
             }
             if (dir < 4)
                 mul_sub<R, NC, false>(u, vr[dir + 1], vi[dir + 1], ar, ai);
@@ -1252,6 +1304,17 @@ int grid_blocks(int ntiles) {
 
 void build_neighbours(const Lat &lat, int *nbr, hipStream_t s) {
     k_neighbours<<<blocks_for(lat.N), kBlock, 0, s>>>(lat, nbr);
+}
+
+void gather_links(int prec, const Lat &lat, int nc, const void *abi, const int *nbr, void *out, hipStream_t s) {
+    const long long n = 8LL * lat.N * nc * nc;
+    const double2 *in = (const double2 *)abi;
+    if (prec == kF64)
+        k_gather_links<double2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (double2 *)out);
+    else if (prec == kF32)
+        k_gather_links<float2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (float2 *)out);
+    else
+        k_gather_links<bf16x2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (bf16x2 *)out);
 }
 
 void convert_links(int prec, const Lat &lat, int nc, const void *abi, void *out, hipStream_t s) {

@@ -163,13 +163,9 @@ dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep
         DP_TRY(ctx->ensure(kSlotU64, nl * 16));
         convert_links(kF64, out.lat, op.nc, op.links, ctx->at(kSlotU64), s);
         out.U64 = ctx->at(kSlotU64);
-        if (inner == kF64) {
-            out.ULo = out.U64;
-        } else {
-            DP_TRY(ctx->ensure(kSlotULo, nl * prec_bytes(inner)));
-            convert_links(inner, out.lat, op.nc, op.links, ctx->at(kSlotULo), s);
-            out.ULo = ctx->at(kSlotULo);
-        }
+        DP_TRY(ctx->ensure(kSlotU8, 2 * nl * prec_bytes(inner)));
+        gather_links(inner, out.lat, op.nc, op.links, out.nbr, ctx->at(kSlotU8), s);
+        out.U8 = ctx->at(kSlotU8);
     }
     DP_HIP(hipGetLastError());
     return DP_OK;
@@ -294,7 +290,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     a.diag = diag;
     a.pin = p;
     a.q = q;
-    a.U = op.ULo;
+    a.U = op.U8;
     a.nbr = op.nbr;
     a.cg = 1;
     a.rd = rd;
@@ -466,7 +462,7 @@ static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, 
     a.diag = op.m2 + 8.0;
     a.pin = ctx->at(kSlotP);
     a.q = ctx->at(kSlotQ);
-    a.U = op.ULo;
+    a.U = op.U8;
     a.nbr = op.nbr;
     a.cg = 1;
     a.rd = rd;
