@@ -198,6 +198,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         g.rhs0 = jb.r0;
         g.nvalid = jb.nv;
         d.g = g;
+        d.gen_b = trace_mode ? 1 : 0;
         d.disp = I.disp;
         d.flags = kSlotInit;
         slot_job[k] = jidx;

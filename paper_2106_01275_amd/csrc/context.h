@@ -185,6 +185,7 @@ struct InitProbe {
         launch_init_probe(*L, prec, g, (double *)ctx->at(kSlotB64), ctx->at(kSlotR), ctx->at(kSlotP), xlo, x64,
                           prec != kF64, *rd, *cs);
     }
+    const ProbeGen *probe() const { return &g; }  // b is these probes
 };
 
 struct InitAbi {
@@ -199,6 +200,7 @@ struct InitAbi {
         launch_init_abi(*L, prec, babi, rhs0, nvalid, (double *)ctx->at(kSlotB64), ctx->at(kSlotR),
                         ctx->at(kSlotP), xlo, x64, prec != kF64, *rd, *cs);
     }
+    const ProbeGen *probe() const { return nullptr; }  // b is read back from b64
 };
 
 

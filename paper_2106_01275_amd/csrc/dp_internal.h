@@ -99,6 +99,7 @@ struct SlotDesc {
     Red rd;
     CgState cs;
     ProbeGen g;          // probes of the slot's right-hand sides
+    int gen_b;           // 1: b is those probes (the true residual regenerates it)
     int disp;            // displacement of the contraction
 };
 enum { kSlotIter = 1, kSlotInit = 2, kSlotRU = 4, kSlotFinal = 8 };
@@ -152,9 +153,10 @@ void launch_update1(const Launch &L, int prec, void *r, const void *q, const Red
 void launch_update2(const Launch &L, int prec, const void *r, void *p, void *x, const CgState &cs);
 // x64 += xlo + alpha p, xlo = 0 (xlo null: FP64, x64 += alpha p)
 void launch_fold(const Launch &L, int prec, double *x64, void *xlo, const void *p, const CgState &cs);
+// gen set: b is regenerated from those probes instead of read from b64
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
                        const double *x64, const void *U64, const int *nbr, void *r, int ru_mode,
-                       const Red &rd, const CgState &cs);
+                       const Red &rd, const CgState &cs, const ProbeGen *gen = nullptr);
 void launch_displaced_dot(const Launch &L, const ProbeGen &g, int p, const double *x64, const Red &rd,
                           const CgState &cs);
 void launch_dot(const Launch &L, const double *a64, const double *b64, const Red &rd,

@@ -964,7 +964,8 @@ template <typename S, int NC, bool LINKS, int MODE>
 __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, double diag, const double2 *__restrict__ b64,
                                                        const double2 *__restrict__ x64,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
-                                                       S *__restrict__ rout, Red rd, CgState cs) {
+                                                       S *__restrict__ rout, Red rd, CgState cs, ProbeGen g,
+                                                       int gen) {
     constexpr int kMaxSites = kBlock / 16;
     __shared__ double su[MODE == 1 && LINKS ? kMaxSites * 8 * NC * NC * 2 : 1];
     __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
@@ -987,7 +988,17 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
         double vr[9][NC], vi[9][NC], br[NC], bi[NC];
 #pragma unroll
         for (int k = 0; k < 9; ++k) ld_site<double2, NC>(x64, y[k], logW, j, vr[k], vi[k]);
-        ld_site<double2, NC>(b64, site, logW, j, br, bi);
+        if (gen) {
+            // probes are regenerated instead of read back (exact values)
+            const unsigned long long seedmix = mix64(g.seed);
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                br[a] = bi[a] = 0.0;
+                if (j < g.nvalid) probe_value(g, seedmix, L.lat, NC, g.rhs0 + j, site, a, br[a], bi[a]);
+            }
+        } else {
+            ld_site<double2, NC>(b64, site, logW, j, br, bi);
+        }
         // r = b - diag x + sum of hops: accumulated with the sign flipped
         double ar[NC], ai[NC];
 #pragma unroll
@@ -1031,8 +1042,8 @@ template <typename S, int NC, bool LINKS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
                                                        const double2 *__restrict__ x64,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
-                                                       S *__restrict__ rout, Red rd, CgState cs) {
-    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, U, nbr, rout, rd, cs);
+                                                       S *__restrict__ rout, Red rd, CgState cs, ProbeGen g, int gen) {
+    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, U, nbr, rout, rd, cs, g, gen);
 }
 
 // t_j = sum_x sum_b conj(v_j(x,b)) x_j(x + p e0, b), probes regenerated.
@@ -1265,7 +1276,7 @@ __global__ __launch_bounds__(kBlock) void k_b_true_resid(BatchLaunch B, int phas
     const SlotDesc *d = slot_of_block(B, bk, phase);
     if (!d) return;
     k_true_resid_body<S, NC, LINKS, MODE>(bk, d->L, d->diag, (const double2 *)d->b64, (const double2 *)d->x64,
-                                          (const double2 *)d->U64, d->nbr, (S *)d->r, d->rd, d->cs);
+                                          (const double2 *)d->U64, d->nbr, (S *)d->r, d->rd, d->cs, d->g, d->gen_b);
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_dot(BatchLaunch B) {
@@ -1424,10 +1435,13 @@ void launch_fold(const Launch &L, int prec, double *x64, void *xlo, const void *
 }
 
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64, const double *x64,
-                       const void *U64, const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs) {
+                       const void *U64, const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs,
+                       const ProbeGen *gen) {
+    const ProbeGen g = gen ? *gen : ProbeGen{};
+    const int use_gen = gen ? 1 : 0;
     const double2 *b = (const double2 *)b64, *x = (const double2 *)x64, *u = (const double2 *)U64;
 #define DP_TR(NC_, LK_, M_)                                                                                  \
-    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, rd, cs)
+    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, rd, cs, g, use_gen)
     DP_DISPATCH_PREC(prec, S, {
         const int m = L.W >= 64 ? 2 : (L.W >= 16 ? 1 : 0);
         if (L.nc == 3) {

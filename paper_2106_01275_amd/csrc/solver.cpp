@@ -349,7 +349,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             // reliable update: x64 += xlo, r = b - A x64 in FP64, beta from it
             launch_fold(L, cfg.inner, x64, xlo, p, cs);
             launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 1,
-                              rd, cs);
+                              rd, cs, init.probe());
             DP_HIP(hipGetLastError());
             ++bs.ru;
             DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
@@ -359,7 +359,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     // the deferred solution update of the last iteration (and xlo, mixed)
     launch_fold(L, cfg.inner, x64, mixed ? xlo : nullptr, p, cs);
     // final FP64 true residual (statistics only)
-    launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs);
+    launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs, init.probe());
     DP_HIP(hipGetLastError());
     const int W = L.W;
     double *h = ctx->state_host;
