@@ -218,19 +218,38 @@ __device__ __forceinline__ int shift0(const Lat &L, int site, int p) {
     return site + (y0 - x0) * stride0;
 }
 
+// The sample s, colour c and dilution index a that lane-enumeration index J
+// stands for (J = ((s - sample0) * ncolors + c) * n_dil + a); computed once
+// per lane, outside the site loops (64-bit divisions).
+struct ProbeLane {
+    long long s;
+    int c, a;
+};
+
+__device__ __forceinline__ ProbeLane probe_lane(const ProbeGen &g, int nc, long long J) {
+    const int ndil = g.dilute ? nc : 1;
+    ProbeLane pl;
+    pl.s = g.sample0 + J / ((long long)g.ncolors * ndil);
+    pl.c = (int)((J / ndil) % g.ncolors);
+    pl.a = (int)(J % ndil);
+    return pl;
+}
+
+// value of that lane's probe at (site, colour b); 0 outside its support
+__device__ __forceinline__ void probe_at(const ProbeGen &g, unsigned long long seedmix, const Lat &L, int nc,
+                                         const ProbeLane &pl, int site, int b, double &re, double &im) {
+    re = 0.0;
+    im = 0.0;
+    const int x = g.shift ? shift0(L, site, -g.shift) : site;
+    if (g.colors[x] != pl.c) return;
+    if (g.dilute && b != pl.a) return;
+    noise(seedmix, pl.s, L.N, x, nc, b, g.noise, re, im);
+}
+
 // probe value of lane-enumeration index J at (site, colour b); 0 outside
 __device__ __forceinline__ void probe_value(const ProbeGen &g, unsigned long long seedmix, const Lat &L,
                                             int nc, long long J, int site, int b, double &re, double &im) {
-    re = 0.0;
-    im = 0.0;
-    const int ndil = g.dilute ? nc : 1;
-    const long long s = g.sample0 + J / ((long long)g.ncolors * ndil);
-    const int c = (int)((J / ndil) % g.ncolors);
-    const int a = (int)(J % ndil);
-    const int x = g.shift ? shift0(L, site, -g.shift) : site;
-    if (g.colors[x] != c) return;
-    if (g.dilute && b != a) return;
-    noise(seedmix, s, L.N, x, nc, b, g.noise, re, im);
+    probe_at(g, seedmix, L, nc, probe_lane(g, nc, J), site, b, re, im);
 }
 
 // ------------------------------------------------------------ reductions
@@ -464,6 +483,7 @@ __device__ __forceinline__ void k_init_body(const Blk &bk, Launch L, ProbeGen g,
     const int j = tid & (W - 1);
     const int nc = L.nc;
     const unsigned long long seedmix = SRC == 0 ? mix64(g.seed) : 0ull;
+    const ProbeLane pl = SRC == 0 ? probe_lane(g, nc, g.rhs0 + j) : ProbeLane{};
     double acc[1] = {0.0};
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
@@ -473,7 +493,7 @@ __device__ __forceinline__ void k_init_body(const Blk &bk, Launch L, ProbeGen g,
         for (int a = 0; a < nc; ++a) {
             double re = 0.0, im = 0.0;
             if (SRC == 0) {
-                if (j < g.nvalid) probe_value(g, seedmix, L.lat, nc, g.rhs0 + j, site, a, re, im);
+                if (j < g.nvalid) probe_at(g, seedmix, L.lat, nc, pl, site, a, re, im);
             } else if (j < nvalid) {
                 const double2 v = babi[((size_t)(rhs0 + j) * L.lat.N + site) * nc + a];
                 re = v.x;
@@ -976,6 +996,8 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
     const int sites_per_tile = kBlock >> logW;
     double acc[1] = {0.0};
     const SiteWalk wk = site_walk(L.lat, bk);
+    const unsigned long long seedmix = gen ? mix64(g.seed) : 0ull;
+    const ProbeLane pl = gen ? probe_lane(g, NC, g.rhs0 + j) : ProbeLane{};
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         if (MODE == 1) stage_tile<double2, double, NC, LINKS>(su, snb, wk, t * sites_per_tile, sites_per_tile, U, nbr);
         if (t * sites_per_tile + sl >= wk.items) continue;
@@ -990,11 +1012,10 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
         for (int k = 0; k < 9; ++k) ld_site<double2, NC>(x64, y[k], logW, j, vr[k], vi[k]);
         if (gen) {
             // probes are regenerated instead of read back (exact values)
-            const unsigned long long seedmix = mix64(g.seed);
 #pragma unroll
             for (int a = 0; a < NC; ++a) {
                 br[a] = bi[a] = 0.0;
-                if (j < g.nvalid) probe_value(g, seedmix, L.lat, NC, g.rhs0 + j, site, a, br[a], bi[a]);
+                if (j < g.nvalid) probe_at(g, seedmix, L.lat, NC, pl, site, a, br[a], bi[a]);
             }
         } else {
             ld_site<double2, NC>(b64, site, logW, j, br, bi);
@@ -1058,16 +1079,14 @@ __device__ __forceinline__ void k_displaced_dot_body(const Blk &bk, Launch L, Pr
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
     if (j < g.nvalid) {
-        const long long J = g.rhs0 + j;
-        const int ndil = g.dilute ? nc : 1;
-        const int c = (int)((J / ndil) % g.ncolors);
+        const ProbeLane pl = probe_lane(g, nc, g.rhs0 + j);
         for (int t = t0; t < t1; ++t) {
             const int site = t * sites_per_tile + sl;
-            if (site >= L.lat.N || g.colors[site] != c) continue;
+            if (site >= L.lat.N || g.colors[site] != pl.c) continue;
             const int y = shift0(L.lat, site, p);
             for (int b = 0; b < nc; ++b) {
                 double zr, zi;
-                probe_value(g, seedmix, L.lat, nc, J, site, b, zr, zi);
+                probe_at(g, seedmix, L.lat, nc, pl, site, b, zr, zi);
                 if (zr == 0.0 && zi == 0.0) continue;
                 const double2 xv = x64[((size_t)(y * nc + b) << logW) + j];
                 acc[0] += zr * xv.x + zi * xv.y;  // conj(z) * x
