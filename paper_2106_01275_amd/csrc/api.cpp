@@ -41,7 +41,7 @@ dp_status solve_cfg(dp_ctx *ctx, const dp_solve_opts *o, SolveCfg &c) {
     c.inner = o->inner;
     // default residual drop between reliable updates: about what the storage
     // precision resolves (BF16 keeps ~3 digits, FP32 ~7)
-    c.delta = o->reliable_delta > 0 ? o->reliable_delta : (c.inner == kBF16 ? 0.1 : 1e-3);
+    c.delta = o->reliable_delta > 0 ? o->reliable_delta : (c.inner == kBF16 ? 0.05 : 1e-3);
     c.profile = o->profile;
     c.use_graph = o->use_graph;
     c.ru_gap = c.inner == kBF16 ? 24 : 100;
@@ -326,7 +326,9 @@ dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, con
                     imax = i;
             OpPrep opm;
             DP_TRY(prepare_operator(ctx, ops[imax], cfg.inner, opm, stream));
-            DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W));
+            std::vector<std::pair<long long, long long>> work;
+            for (auto &I : in) work.emplace_back(I.nrhs, (long long)I.lat.N);
+            DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W, &work));
         }
         DP_TRY(run_batch(ctx, in, cfg, W, false, stream));
         for (int i = 0; i < ninst; ++i) {
@@ -506,7 +508,9 @@ dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, 
                     imax = i;
             OpPrep opm;
             DP_TRY(prepare_operator(ctx, ops[imax], cfg.inner, opm, stream));
-            DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W));
+            std::vector<std::pair<long long, long long>> work;
+            for (auto &I : in) work.emplace_back(I.nrhs, (long long)I.lat.N);
+            DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W, &work));
         }
         DP_TRY(run_batch(ctx, in, cfg, W, true, stream));
         for (int i = 0; i < ninst; ++i) {

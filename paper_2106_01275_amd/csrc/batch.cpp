@@ -4,10 +4,13 @@
 // longest first.  Up to kMaxSlots jobs are resident at once, each in a slot
 // with its own buffers and CG state; every kernel of a CG iteration is ONE
 // launch over all slots (a device-side slot table maps workgroups to slots),
-// so small lattices share the GPU instead of each underfilling it.  At each
-// host check the finished slots are contracted and refilled with the next
-// jobs; the slot table is rewritten in device memory, so the captured graph
-// of an iteration group stays valid for the whole batch.
+// so small lattices share the GPU instead of each underfilling it.  The
+// workgroups of a launch are shared among the busy slots in proportion to
+// their site tiles, so a launch is not as long as its largest lattice needs
+// with an equal share.  At each host check the finished slots are contracted
+// and refilled with the next jobs; the slot table is rewritten in device
+// memory, so the captured graph of an iteration group stays valid for the
+// whole batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +25,10 @@ namespace dp {
 
 namespace {
 
-constexpr int kMaxSlots = 64;
+constexpr int kMaxSlots = 256;
+constexpr int kSlotMaxBlk = 2048;           // workgroups of one slot (partial sums per lane)
+constexpr int kLaunchBlk = 2048 * 8;        // workgroups of one multi-instance launch
+constexpr size_t kSlotBudget = 48ull << 30;  // device bytes of all slot buffers
 
 // Buffers of one call, taken from the context's pool and returned to it at
 // the end of the call (the stream is synchronised before that).
@@ -91,17 +97,26 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             jobs.push_back({i, r0, nv, (double)in[i].lat.N * nv * std::sqrt(9.0 / std::max(in[i].m2, 1e-6))});
         }
     std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.cost > b.cost; });
-    const int nslots = std::max(1, std::min<int>((int)jobs.size(), kMaxSlots));
-
-    // workgroups per slot: enough for the largest lattice, a multiple of 8
-    const int spt = kBlock >> logW;
-    int nblk = std::min(grid_blocks((maxN + spt - 1) / spt), 2048 * 8 / nslots);
-    nblk = std::max(8, nblk - nblk % 8);
-
-    // slot buffers
+    // resident slots: about 8192 right-hand sides in flight, within the
+    // memory budget
     const size_t vec = (size_t)maxN * nc * W;
     const size_t lo = vec * prec_bytes(cfg.inner);
-    std::vector<SlotDesc> hsd(nslots);
+    const size_t part_bytes = (size_t)W * kSlotMaxBlk * 2 * sizeof(double);
+    const size_t slot_bytes = vec * 32 + lo * (mixed ? 4 : 3) + part_bytes;
+    int slot_cap = std::min(kMaxSlots, std::max(64, 8192 / W));
+    slot_cap = (int)std::min<size_t>(slot_cap, std::max<size_t>(1, kSlotBudget / slot_bytes));
+    const int nslots = std::max(1, std::min<int>((int)jobs.size(), slot_cap));
+
+    // workgroups of a launch: enough for every slot to run its largest
+    // lattice with a full grid, at most kLaunchBlk, a multiple of 8
+    const int spt = kBlock >> logW;
+    const int maxtiles = (maxN + spt - 1) / spt;
+    int gblk = (int)std::min<long long>(kLaunchBlk, (long long)nslots * grid_blocks(maxtiles));
+    gblk = std::max(8 * nslots, gblk - gblk % 8);
+
+    // slot buffers; descriptor nslots is an idle one for unused workgroups
+    std::vector<SlotDesc> hsd(nslots + 1);
+    std::memset(&hsd[nslots], 0, sizeof(SlotDesc));
     int *ctrl_all = nullptr;
     DP_TRY(mem.alloc(ctx, (void **)&ctrl_all, (size_t)nslots * 8 * sizeof(double), true));
     // CG state of all slots in one block (one stride per slot), mirrored in
@@ -125,8 +140,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             DP_TRY(mem.alloc(ctx, &d.xlo, lo));
         else
             d.xlo = d.x64;
-        DP_TRY(mem.alloc(ctx, (void **)&d.rd.part1, (size_t)W * nblk * 2 * sizeof(double)));
-        d.rd.nblk = nblk;
+        DP_TRY(mem.alloc(ctx, (void **)&d.rd.part1, part_bytes));
         double *st = (double *)(st_all + st_stride * k);
         CgState &cs = d.cs;
         cs.rr = st;
@@ -147,21 +161,18 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         cs.delta2 = cfg.delta * cfg.delta;
         cs.hold = cfg.inner == kBF16;
         cs.exact = !mixed;
-        d.blk0 = k * nblk;
     }
-    std::vector<int> slot_of((size_t)nslots * nblk);
-    for (size_t w = 0; w < slot_of.size(); ++w) slot_of[w] = (int)(w / nblk);
+    std::vector<int> slot_of((size_t)gblk, nslots);
     SlotDesc *d_sd = nullptr;
     int *d_slot_of = nullptr;
-    DP_TRY(mem.alloc(ctx, (void **)&d_sd, sizeof(SlotDesc) * nslots));
+    DP_TRY(mem.alloc(ctx, (void **)&d_sd, sizeof(SlotDesc) * (nslots + 1)));
     DP_TRY(mem.alloc(ctx, (void **)&d_slot_of, sizeof(int) * slot_of.size()));
-    DP_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int) * slot_of.size(), hipMemcpyHostToDevice, s));
 
     BatchLaunch B;
     B.sd = d_sd;
     B.slot_of = d_slot_of;
     B.nslots = nslots;
-    B.nblocks = nslots * nblk;
+    B.nblocks = gblk;
     B.W = W;
     B.nc = nc;
     B.prec = cfg.inner;
@@ -179,7 +190,6 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         d.L.nc = nc;
         d.L.W = W;
         d.L.logW = logW;
-        d.L.nblk = nblk;
         d.L.ntiles = (I.lat.N + spt - 1) / spt;
         d.L.stream = s;
         d.diag = I.m2 + 8.0;
@@ -205,8 +215,50 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         slot_it[k] = 0;
         slot_ru[k] = 0;
     };
+    // Shares the workgroups among the slots that take part in any phase: 8
+    // each, the rest in proportion to their site tiles, every share a
+    // multiple of 8 (so b % 8 is still the XCD) and at most kSlotMaxBlk or
+    // the slot's tiles; workgroups left over go to the idle descriptor.
+    std::vector<int> share(nslots, 0);
+    auto balance = [&]() -> bool {
+        long long tot = 0;
+        int nbusy = 0;
+        for (int k = 0; k < nslots; ++k)
+            if (hsd[k].flags) {
+                tot += hsd[k].L.ntiles;
+                ++nbusy;
+            }
+        const long long spare = gblk - 8LL * nbusy;
+        bool changed = false;
+        for (int k = 0; k < nslots; ++k) {
+            int nb = 0;
+            if (hsd[k].flags) {
+                const int t = hsd[k].L.ntiles;
+                const long long extra = spare * t / std::max(1LL, tot);
+                nb = 8 + (int)(extra - extra % 8);
+                const int cap = std::min(kSlotMaxBlk, std::max(8, (t + 7) / 8 * 8));
+                nb = std::min(nb, cap);
+            }
+            changed |= nb != share[k];
+            share[k] = nb;
+        }
+        if (!changed) return false;
+        int b0 = 0;
+        for (int k = 0; k < nslots; ++k) {
+            SlotDesc &d = hsd[k];
+            d.blk0 = b0;
+            d.L.nblk = share[k];
+            d.rd.nblk = share[k];
+            for (int w = 0; w < share[k]; ++w) slot_of[b0 + w] = k;
+            b0 += share[k];
+        }
+        for (int w = b0; w < gblk; ++w) slot_of[w] = nslots;
+        return true;
+    };
     auto upload = [&]() -> dp_status {
-        DP_HIP(hipMemcpyAsync(d_sd, hsd.data(), sizeof(SlotDesc) * nslots, hipMemcpyHostToDevice, s));
+        if (balance())
+            DP_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int) * slot_of.size(), hipMemcpyHostToDevice, s));
+        DP_HIP(hipMemcpyAsync(d_sd, hsd.data(), sizeof(SlotDesc) * (nslots + 1), hipMemcpyHostToDevice, s));
         return DP_OK;
     };
     // initialise the slots flagged kSlotInit, then make them iterate

@@ -105,8 +105,10 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
 template <typename Init>
 dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
                       const CgState &cs, double *x64_dst, Init init, BlockStats &bs, dp_solve_stats *acc);
+// For a batch, `work` lists (right-hand sides, sites) of every instance: the
+// cost of a width then counts the padded lanes of each instance's last job.
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
-                       hipStream_t s, int &W);
+                       hipStream_t s, int &W, const std::vector<std::pair<long long, long long>> *work = nullptr);
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
 // runs launch(ev0, ev1); when profiling, with two events from the pool that
 // the launch attaches to the kernel's own start and stop (finish_profile()

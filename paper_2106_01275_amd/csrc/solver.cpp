@@ -396,9 +396,12 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
 // within a memory budget) a block of dense random right-hand sides runs
 // 2 + 6 CG iterations of the real kernels; the 6 are timed with HIP events
 // and the cost per useful right-hand side and iteration,
-// time / min(W, nrhs), decides.  Results are cached per (N, nc, precision,
-// links, next power of two of nrhs) in the context, and in the JSON file
-// named by DP_TUNE_CACHE when that variable is set.
+// time / min(W, nrhs), decides.  For a batch of instances the cost is
+// time / W times the padded share of the work, sum ceil(n_i / W) W N_i over
+// sum n_i N_i (n_i right-hand sides on N_i sites).  Choices (single
+// instance) and timings in nanoseconds (batches) are cached per (N, nc,
+// precision, links, next power of two of nrhs) in the context, and in the
+// JSON file named by DP_TUNE_CACHE when that variable is set.
 static std::string tune_key(const OpPrep &op, const SolveCfg &cfg, long long nrhs) {
     long long b = 1;
     while (b < nrhs && b < kMaxW) b *= 2;
@@ -489,7 +492,7 @@ static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, 
 }
 
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
-                       hipStream_t s, int &W) {
+                       hipStream_t s, int &W, const std::vector<std::pair<long long, long long>> *work) {
     if (requested > 0) {
         if (requested > kMaxW || (requested & (requested - 1))) {
             ctx->err = "rhs_block must be a power of two <= 256";
@@ -505,27 +508,44 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
     load_tune_file(ctx);
     const std::string key = tune_key(op, cfg, nrhs);
     auto it = ctx->tuned_w.find(key);
-    if (it != ctx->tuned_w.end()) {
+    if (!work && it != ctx->tuned_w.end()) {
         W = it->second;
         return DP_OK;
     }
     const size_t bytes_per_w = (size_t)op.lat.N * op.nc * (2 * 16 + 4 * (cfg.inner == kF64 ? 16 : 8));
     double best = 1e300;
     int best_w = 1;
+    bool timed = false;
     for (int w = 8; w <= 128; w *= 2) {
         if (w > 8 && w / 2 >= nrhs) break;
         if (bytes_per_w * w > ((size_t)32 << 30)) break;
         float ms = 0;
-        DP_TRY(time_width(ctx, op, cfg, w, s, ms));
-        const double cost = ms / (double)std::min<long long>(w, nrhs);
+        const std::string tkey = key + " W=" + std::to_string(w) + " ns";
+        auto t = ctx->tuned_w.find(tkey);
+        if (work && t != ctx->tuned_w.end()) {
+            ms = (float)(t->second * 1e-6);
+        } else {
+            DP_TRY(time_width(ctx, op, cfg, w, s, ms));
+            if (work) ctx->tuned_w[tkey] = (int)std::min(2e9, ms * 1e6);
+            timed = true;
+        }
+        double cost = ms / (double)std::min<long long>(w, nrhs);
+        if (work) {
+            double padded = 0, useful = 0;
+            for (auto &nw : *work) {
+                padded += (double)((nw.first + w - 1) / w) * w * nw.second;
+                useful += (double)nw.first * nw.second;
+            }
+            cost = ms / (double)w * (useful > 0 ? padded / useful : 1.0);
+        }
         if (cost < best) {
             best = cost;
             best_w = w;
         }
     }
     W = best_w;
-    ctx->tuned_w[key] = W;
-    save_tune_file(ctx);
+    if (!work) ctx->tuned_w[key] = W;
+    if (timed) save_tune_file(ctx);
     return DP_OK;
 }
 
