@@ -1324,9 +1324,11 @@ __global__ void k_b_ctrl(BatchLaunch B) {
 static int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 int grid_blocks(int ntiles) {
-    // enough workgroups to fill 256 CUs several times over, a multiple of 8
-    // (one contiguous share per XCD); never more than there are tiles
-    const int cap = 2048;
+    // four workgroups per CU, a multiple of 8 (one contiguous share per
+    // XCD); never more than there are tiles.  All of them are resident at
+    // once, so they walk their slabs in step (16^4 sites, FP32, W = 32: a
+    // CG iteration took 3% less time than with 2048, 14% less than with 512)
+    const int cap = 1024;
     if (ntiles <= 8) return ntiles;
     int n = ntiles < cap ? ntiles : cap;
     return n - n % 8;
