@@ -293,3 +293,53 @@ def trace_grad(dims, nc, m2, links, p, colors, ncolors, seed, sample0, nsamples,
 
 def noise_norm(kind: int) -> float:
     return 0.5 if kind == Z2_COMPLEX else 1.0
+
+
+# ----------------------------------------------------------------- deflation (Sec. Deflation)
+
+
+def lowest_eigenpairs(dims, nc, m2, links, nvec):
+    """The nvec smallest eigenvalues of the Hermitian operator (ascending) and
+    orthonormal eigenvectors [nvec, N, nc], from the dense matrix (numpy eigh).
+    Small lattices only."""
+    N = volume(dims)
+    w, V = np.linalg.eigh(dense(dims, nc, m2, links))
+    return w[:nvec], np.ascontiguousarray(V[:, :nvec].T).reshape(nvec, N, nc)
+
+
+def shift(dims, v, p):
+    """(P v)(x) = v(x + p e0) for v [N, nc] (dim 0 slowest)."""
+    D = [int(d) for d in _dims(dims)]
+    return np.roll(np.asarray(v).reshape(D + [-1]), -p, axis=0).reshape(np.shape(v))
+
+
+def trace_deflated(dims, nc, m2, links, p, colors, ncolors, seed, sample0, nsamples, kind, dilute, V):
+    """Deflated probed estimate of Tr(P A^{-1}) (Sec. Deflation).
+
+    With the basis V [k, N, nc] (any full-rank set), M = V^H A V and the
+    oblique projector Q = A V M^{-1} V^H, the trace splits as
+    Tr(P A^{-1} Q) + Tr(P A^{-1} (I - Q)).  Since A^{-1} Q = V M^{-1} V^H the
+    first term is evaluated exactly; the second is estimated with the probes,
+    t_j = z_j^H P A^{-1} (I - Q) z_j (dense solves).  Per sample
+    T_s = T_defl + norm * sum_j t_j.  Small lattices only."""
+    N = volume(dims)
+    n = N * nc
+    A = dense(dims, nc, m2, links)
+    Vm = np.asarray(V, dtype=np.complex128).reshape(-1, n).T          # n x k
+    AV = A @ Vm
+    Minv = np.linalg.inv(Vm.conj().T @ AV)
+    # Tr(P V M^{-1} V^H) = sum_x sum_b (V M^{-1} V^H)[(x + p e0, b), (x, b)]
+    Dm = Vm @ Minv @ Vm.conj().T
+    rows = shift(dims, np.arange(n).reshape(N, nc), p).reshape(n)   # index of (x + p e0, b)
+    T_defl = complex(np.sum(Dm[rows, np.arange(n)]))
+    Z = probes(dims, nc, colors, ncolors, seed, sample0, nsamples, kind, dilute).reshape(-1, n)
+    B = Z.T - AV @ (Minv @ (Vm.conj().T @ Z.T))                     # (I - Q) z, columns
+    X = np.linalg.solve(A, B)
+    tj = np.array([np.vdot(Z[j], shift(dims, X[:, j].reshape(N, nc), p).reshape(n))
+                   for j in range(Z.shape[0])])
+    norm = noise_norm(kind)
+    per = Z.shape[0] // nsamples
+    Ts = T_defl + norm * tj.reshape(nsamples, per).sum(axis=1)
+    T = complex(Ts.mean())
+    stderr = float(np.sqrt(np.sum(np.abs(Ts - T) ** 2) / (nsamples - 1) / nsamples)) if nsamples > 1 else float("nan")
+    return {"T": T, "T_defl": T_defl, "per_sample": Ts, "tj": tj, "stderr": stderr}
