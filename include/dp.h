@@ -290,6 +290,72 @@ dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *op, int32_t p, const dp_
 dp_status dp_apply(dp_ctx *ctx, const dp_operator *op, int32_t prec, const void *v, void *y,
                    int64_t nrhs, hipStream_t stream);
 
+/*
+ * Deflation (Sec. Deflation): with V the Ritz vectors of the nvec smallest
+ * eigenvalues of the Hermitian A (orthonormal, V^H A V = Theta) and the
+ * oblique projector Q = A V (V^H A V)^{-1} V^H, the trace splits exactly as
+ *     Tr(P A^{-1}) = Tr(P A^{-1} Q) + Tr(P A^{-1} (I - Q)),
+ * where A^{-1} Q = V Theta^{-1} V^H, so the first term is the sum over the
+ * vectors of theta_i^{-1} sum_x sum_b conj(v_i(x,b)) v_i(x + p e0, b), and
+ * the probes estimate only the second: t_j = z_j^H P A^{-1} (I - Q) z_j.
+ * The identity holds for any V; how much variance the split removes (and how
+ * many CG iterations the deflated right-hand sides save) depends on how well
+ * V spans the low modes.
+ *
+ * The vectors come from a Chebyshev-filtered subspace iteration with
+ * Rayleigh-Ritz (FP64, on the device) over a subspace of
+ * W = next power of two of nvec + max(4, nvec / 4) vectors (W <= 128): each
+ * outer iteration applies a degree-`degree` Chebyshev polynomial of A that
+ * damps [theta_max, bound] (bound: a Gershgorin-type bound of the spectrum
+ * from the links), then orthonormalises and rotates to Ritz vectors.  It
+ * stops when the relative Ritz residual |A v_i - theta_i v_i| / theta_i of
+ * every kept vector is <= tol, or after max_outer iterations.
+ */
+typedef struct dp_deflation dp_deflation;
+
+typedef struct {
+    int32_t degree;     /* Chebyshev degree per outer iteration (0: 16) */
+    int32_t max_outer;  /* outer iterations (0: 60) */
+    double tol;         /* relative Ritz residual of the kept vectors (0: 1e-10) */
+    uint64_t seed;      /* start vectors */
+} dp_eig_opts;
+
+/*
+ *   op     the operator (the same one must be passed to dp_trace_deflated).
+ *   nvec   kept vectors, 1 <= nvec <= 103 (so that W <= 128).
+ *   o      may be NULL (defaults).
+ *   out    written: a deflation object owning its device memory (free it
+ *          with dp_deflation_destroy; it stays valid after the context is
+ *          destroyed only as long as the device is alive).
+ * Returns DP_ENOCONV (the object is still written) when max_outer was
+ * reached before tol. */
+dp_status dp_deflation_create(dp_ctx *ctx, const dp_operator *op, int32_t nvec, const dp_eig_opts *o,
+                              dp_deflation **out, hipStream_t stream);
+
+/*   evals, resid  host double[nvec] (may be NULL): Ritz values (ascending)
+ *                 and relative Ritz residuals; outer, subspace (may be NULL):
+ *                 outer iterations run and the subspace size W. */
+dp_status dp_deflation_info(const dp_deflation *d, double *evals, double *resid, int32_t *outer,
+                            int32_t *subspace);
+
+/*   out    device complex128 [nvec][N][nc], caller-owned, written (the Ritz
+ *          vectors in the ABI layout). */
+dp_status dp_deflation_vectors(dp_ctx *ctx, const dp_deflation *d, void *out, hipStream_t stream);
+
+/*
+ * Deflated probed estimate of Tr(P A^{-1}): right-hand sides
+ * b_j = (I - Q) z_j = z_j - A V Theta^{-1} V^H z_j (formed on the device,
+ * FP64), solved and contracted as in dp_trace_estimate;
+ *     T_s = tr_defl + norm * sum_{j in sample s} t_j,   T = mean over samples.
+ *   tr_defl  host double[2] (may be NULL): Tr(P A^{-1} Q), written.
+ * out.per_sample holds the T_s (each an unbiased estimate of the whole
+ * trace), out.per_rhs the t_j. Single instance, p >= 0. */
+dp_status dp_trace_deflated(dp_ctx *ctx, const dp_operator *op, const dp_deflation *d, int32_t p,
+                            const dp_probe_spec *ps, const dp_solve_opts *o, dp_trace_result *out,
+                            double tr_defl[2], hipStream_t stream);
+
+void dp_deflation_destroy(dp_deflation *d);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,9 +74,15 @@ class TraceResult(ctypes.Structure):
                 ("per_sample", ctypes.c_void_p), ("per_rhs", ctypes.c_void_p), ("solve", SolveStats)]
 
 
+class EigOpts(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
 EXPORTS = ["dp_create", "dp_destroy", "dp_last_error", "dp_build_coloring", "dp_build_coloring_multi",
            "dp_tile_shape", "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
-           "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply"]
+           "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply", "dp_deflation_create",
+           "dp_deflation_info", "dp_deflation_vectors", "dp_trace_deflated", "dp_deflation_destroy"]
 
 _lib = None
 
@@ -109,9 +115,18 @@ def lib():
         L.dp_trace_grad.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(ProbeSpec),
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp, vp, vp, vp]
         L.dp_apply.argtypes = [vp, ctypes.POINTER(Operator), i32, vp, vp, i64, vp]
+        L.dp_deflation_create.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(EigOpts),
+                                          ctypes.POINTER(vp), vp]
+        L.dp_deflation_info.argtypes = [vp, vp, vp, vp, vp]
+        L.dp_deflation_vectors.argtypes = [vp, vp, vp, vp]
+        L.dp_trace_deflated.argtypes = [vp, ctypes.POINTER(Operator), vp, i32, ctypes.POINTER(ProbeSpec),
+                                        ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp, vp]
+        L.dp_deflation_destroy.argtypes = [vp]
+        L.dp_deflation_destroy.restype = None
         for name in ("dp_create", "dp_build_coloring", "dp_build_coloring_multi", "dp_tile_shape",
                      "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
-                     "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply"):
+                     "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply",
+                     "dp_deflation_create", "dp_deflation_info", "dp_deflation_vectors", "dp_trace_deflated"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -383,6 +398,40 @@ class Context:
             self._err(st, out)
         return out
 
+    def deflation(self, op, nvec, degree=0, max_outer=0, tol=0.0, seed=1, check=True):
+        """Ritz vectors of the nvec smallest eigenvalues of A (Sec. Deflation).
+        Returns a Deflation (with .evals, .resid, .outer, .subspace)."""
+        eo = EigOpts()
+        eo.degree, eo.max_outer, eo.tol, eo.seed = int(degree), int(max_outer), float(tol), int(seed)
+        h = ctypes.c_void_p()
+        st = lib().dp_deflation_create(self.h, ctypes.byref(op), int(nvec), ctypes.byref(eo), ctypes.byref(h),
+                                       self._stream())
+        d = Deflation(self, h, int(nvec)) if h.value else None
+        if st != OK and (check or st != ENOCONV or d is None):
+            if d is not None:
+                d.close()
+            self._err(st)
+        return d
+
+    def trace_deflated(self, op, defl, p, ps, opts, check=True):
+        """Deflated probed estimate of Tr(P A^{-1}); dict as trace_estimate
+        plus "T_defl" = Tr(P A^{-1} Q)."""
+        res = TraceResult()
+        ndil = ps.nc if ps.dilute else 1
+        nrhs = ps.nsamples * ps.ncolors * ndil
+        per_s, per_r = np.zeros(2 * ps.nsamples), np.zeros(2 * nrhs)
+        res.per_sample = per_s.ctypes.data
+        res.per_rhs = per_r.ctypes.data
+        td = (ctypes.c_double * 2)()
+        st = lib().dp_trace_deflated(self.h, ctypes.byref(op), defl.h, int(p), ctypes.byref(ps), ctypes.byref(opts),
+                                     ctypes.byref(res), td, self._stream())
+        out = {"T": complex(res.tr[0], res.tr[1]), "stderr": res.stderr_, "T_defl": complex(td[0], td[1]),
+               "per_sample": per_s.view(np.complex128).copy(), "tj": per_r.view(np.complex128).copy(),
+               "solve": res.solve.asdict()}
+        if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
+            self._err(st, out)
+        return out
+
     def apply(self, op, v, prec="f64"):
         torch = self.torch
         y = torch.empty_like(v)
@@ -391,6 +440,39 @@ class Context:
         if st != OK:
             self._err(st)
         return y
+
+
+class Deflation:
+    """Deflation vectors of one operator, owned by the library (device memory)."""
+
+    def __init__(self, ctx, h, nvec):
+        self.ctx, self.h, self.nvec = ctx, h, nvec
+        ev, rs = np.zeros(nvec), np.zeros(nvec)
+        outer, sub = ctypes.c_int32(), ctypes.c_int32()
+        lib().dp_deflation_info(h, ev.ctypes.data, rs.ctypes.data, ctypes.byref(outer), ctypes.byref(sub))
+        self.evals, self.resid, self.outer, self.subspace = ev, rs, int(outer.value), int(sub.value)
+
+    def vectors(self, dims, nc):
+        """The Ritz vectors, complex128 cuda tensor [nvec, N, nc]."""
+        torch = self.ctx.torch
+        N = int(np.prod(list(dims)))
+        out = torch.empty((self.nvec, N, nc), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        st = lib().dp_deflation_vectors(self.ctx.h, self.h, self.ctx._cdev(out, torch.complex128),
+                                        self.ctx._stream())
+        if st != OK:
+            self.ctx._err(st)
+        return out
+
+    def close(self):
+        if self.h:
+            lib().dp_deflation_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _ctx_cache = {}

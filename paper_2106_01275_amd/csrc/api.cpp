@@ -667,4 +667,134 @@ dp_status dp_apply(dp_ctx *ctx, const dp_operator *opd, int32_t prec, const void
     return DP_OK;
 }
 
+// ------------------------------------------------------------ deflation
+
+dp_status dp_deflation_create(dp_ctx *ctx, const dp_operator *op, int32_t nvec, const dp_eig_opts *o,
+                              dp_deflation **out, hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!op || !out) {
+        ctx->err = "deflation_create: bad arguments";
+        return DP_EINVAL;
+    }
+    *out = nullptr;
+    dp_eig_opts eo{};
+    if (o) eo = *o;
+    if (eo.degree < 0 || eo.max_outer < 0 || !(eo.tol >= 0) || eo.degree > 200) {
+        ctx->err = "deflation_create: bad options";
+        return DP_EINVAL;
+    }
+    dp_deflation *d = new dp_deflation;
+    d->device = ctx->device;
+    const dp_status st = deflation_build(ctx, *op, nvec, eo, *d, stream);
+    if (st != DP_OK && st != DP_ENOCONV) {
+        dp_deflation_destroy(d);
+        return st;
+    }
+    if (st == DP_ENOCONV) ctx->err = "deflation_create: Ritz residuals above tol after max_outer iterations";
+    *out = d;
+    return st;
+}
+
+dp_status dp_deflation_info(const dp_deflation *d, double *evals, double *resid, int32_t *outer,
+                            int32_t *subspace) {
+    if (!d) return DP_EINVAL;
+    if (evals) std::memcpy(evals, d->theta.data(), d->theta.size() * sizeof(double));
+    if (resid) std::memcpy(resid, d->resid.data(), d->resid.size() * sizeof(double));
+    if (outer) *outer = d->outer;
+    if (subspace) *subspace = d->W;
+    return DP_OK;
+}
+
+dp_status dp_deflation_vectors(dp_ctx *ctx, const dp_deflation *d, void *out, hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!d || !out) {
+        ctx->err = "deflation_vectors: bad arguments";
+        return DP_EINVAL;
+    }
+    return deflation_vectors(ctx, *d, (double *)out, stream);
+}
+
+void dp_deflation_destroy(dp_deflation *d) {
+    if (!d) return;
+    (void)hipSetDevice(d->device);
+    if (d->V) (void)hipFree(d->V);
+    if (d->Z) (void)hipFree(d->Z);
+    if (d->scratch) (void)hipFree(d->scratch);
+    delete d;
+}
+
+dp_status dp_trace_deflated(dp_ctx *ctx, const dp_operator *opd, const dp_deflation *d, int32_t p,
+                            const dp_probe_spec *ps, const dp_solve_opts *o, dp_trace_result *out,
+                            double tr_defl[2], hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!opd || !d || !ps || !out || p < 0) {
+        ctx->err = "trace_deflated: bad arguments";
+        return DP_EINVAL;
+    }
+    bool same = opd->nc == d->nc && opd->m2 == d->m2 && (opd->links != nullptr) == d->links;
+    for (int k = 0; k < 4; ++k) same = same && opd->dims[k] == d->lat.D[k];
+    if (!same) {
+        ctx->err = "trace_deflated: the deflation was built for another operator";
+        return DP_EINVAL;
+    }
+    const double t0 = now_s();
+    SolveCfg cfg;
+    DP_TRY(solve_cfg(ctx, o, cfg));
+    DP_TRY(check_spec(ctx, *ps, opd));
+    WorkStream ws_;
+    DP_TRY(ws_.enter(ctx, stream, cfg.use_graph));
+    struct Leave {
+        WorkStream &w;
+        ~Leave() { (void)w.leave(); }
+    } leave_{ws_};
+    stream = ws_.s;
+    double td[2] = {0.0, 0.0};
+    DP_TRY(deflation_trace_part(ctx, *d, p, stream, td));
+    OpPrep op;
+    DP_TRY(prepare_operator(ctx, *opd, cfg.inner, op, stream));
+    const int ndil = ps->dilute ? ps->nc : 1;
+    const long long nrhs = (long long)ps->nsamples * ps->ncolors * ndil;
+    int W = 1;
+    DP_TRY(choose_width(ctx, op, cfg, nrhs, o->rhs_block, stream, W));
+    Launch L;
+    Red rd;
+    CgState cs;
+    DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
+    dp_solve_stats s{};
+    s.rhs_block = W;
+    std::vector<double> tj(2 * nrhs, 0.0);
+    dp_status proj = DP_OK;
+    for (long long r0 = 0; r0 < nrhs; r0 += W) {
+        const long long nv = std::min<long long>(W, nrhs - r0);
+        BlockStats bs;
+        bs.nvalid = (int)nv;
+        InitDeflated init{&L, cfg.inner, make_gen(*ps, r0, nv, 0), &rd, &cs, ctx, d, &proj};
+        double *x64 = (double *)ctx->at(kSlotX64);
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s));
+        DP_TRY(proj);
+        launch_displaced_dot(L, make_gen(*ps, r0, nv, 0), p, x64, rd, cs);
+        DP_HIP(hipGetLastError());
+        DP_HIP(hipMemcpyAsync(tj.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    DP_HIP(hipStreamSynchronize(stream));
+    s.seconds = now_s() - t0;
+    combine(*ps, tj, *out);
+    out->tr[0] += td[0];
+    out->tr[1] += td[1];
+    if (out->per_sample)
+        for (int k = 0; k < ps->nsamples; ++k) {
+            out->per_sample[2 * k] += td[0];
+            out->per_sample[2 * k + 1] += td[1];
+        }
+    out->solve = s;
+    if (tr_defl) {
+        tr_defl[0] = td[0];
+        tr_defl[1] = td[1];
+    }
+    const dp_status fs = final_status(s);
+    if (fs == DP_ENOCONV) ctx->err = "trace_deflated: some right-hand sides did not converge";
+    if (fs == DP_EBREAKDOWN) ctx->err = "trace_deflated: CG breakdown";
+    return fs;
+}
+
 }  // extern "C"

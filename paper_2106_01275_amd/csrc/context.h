@@ -205,5 +205,48 @@ struct InitAbi {
     const ProbeGen *probe() const { return nullptr; }  // b is read back from b64
 };
 
+// deflation.cpp: the eigensolve, b64 -= Z (V^H b64) for one block of W
+// right-hand sides, Tr(P A^{-1} Q), and the vectors in the ABI layout
+dp_status deflation_build(dp_ctx *ctx, const dp_operator &op, int nvec, const dp_eig_opts &eo, dp_deflation &d,
+                          hipStream_t s);
+dp_status deflate_rhs(dp_ctx *ctx, const dp_deflation &d, const Launch &L, double *b64);
+dp_status deflation_trace_part(dp_ctx *ctx, const dp_deflation &d, int p, hipStream_t s, double out[2]);
+dp_status deflation_vectors(dp_ctx *ctx, const dp_deflation &d, double *out, hipStream_t s);
+
+// Probes with the deflation applied: z is generated into b64, projected
+// there, and the CG vectors are initialised from the result; the true
+// residual then reads b64 (the probes are no longer the right-hand sides).
+struct InitDeflated {
+    const Launch *L;
+    int prec;
+    ProbeGen g;
+    const Red *rd;
+    const CgState *cs;
+    dp_ctx *ctx;
+    const dp_deflation *d;
+    dp_status *status;  // set when the projection fails
+    void operator()(void *xlo, double *x64) const {
+        double *b64 = (double *)ctx->at(kSlotB64);
+        launch_init_probe(*L, prec, g, b64, ctx->at(kSlotR), ctx->at(kSlotP), xlo, x64, prec != kF64, *rd, *cs);
+        const dp_status e = deflate_rhs(ctx, *d, *L, b64);
+        if (e != DP_OK) *status = e;
+        launch_init_b64(*L, prec, b64, ctx->at(kSlotR), ctx->at(kSlotP), xlo, x64, prec != kF64, *rd, *cs);
+    }
+    const ProbeGen *probe() const { return nullptr; }
+};
 
 }  // namespace dp
+
+// Deflation vectors of one operator (Sec. Deflation), device memory owned here.
+struct dp_deflation {
+    int device = 0;
+    int nvec = 0, W = 0, outer = 0;
+    dp::Lat lat{};
+    int nc = 1;
+    double m2 = 0;
+    bool links = false;
+    double *V = nullptr;  // Ritz vectors, internal layout [N][nc][W] (FP64 complex)
+    double *Z = nullptr;  // A V Theta^{-1} in the kept lanes, zero in the others
+    double *scratch = nullptr;  // device: tj [2W], true_rr [W], alpha [W], partial sums
+    std::vector<double> theta, resid;
+};

@@ -164,6 +164,29 @@ void launch_dot(const Launch &L, const double *a64, const double *b64, const Red
 void launch_force(const Launch &L, const double *x64, const double *l64, const int *nbr, double scale,
                   int first, double *dU, double *dUbar);
 void launch_ctrl(const CgState &cs, int W, hipStream_t s);
+
+// Deflation (dense pieces over FP64 blocks [n rows][width], internal layout)
+// r = p = b read from b64 in place, xlo = 0, |b|^2 (the init of probes that
+// were modified in b64)
+void launch_init_b64(const Launch &L, int prec, double *b64, void *r, void *p, void *xlo, double *x64, int mixed,
+                     const Red &rd, const CgState &cs);
+// cs.tj[j] = sum_x sum_b conj(u_j(x,b)) w_j(x + p e0, b)
+void launch_dot_shift(const Launch &L, const double *u, const double *w, int p, const Red &rd, const CgState &cs);
+// cs.true_rr[j] = |u_j - theta_j w_j|^2 (theta: device double[W])
+void launch_resid_norm(const Launch &L, const double *u, const double *w, const double *theta, const Red &rd,
+                       const CgState &cs);
+void launch_axpby(long long n, double a, const double *q, double b, const double *v, double *out, hipStream_t s);
+void launch_rand_fill(long long n, unsigned long long seed, double *v, hipStream_t s);
+void launch_scale_lanes(long long n, int W, const double *sc, const double *v, double *out, hipStream_t s);
+// H [WX][WY] = scale * X^H Y over n rows; part: workspace of gram_row_blocks(n)
+// * ceil(WX / 64) * ceil(WY / 64) * 64 * 64 complex numbers
+int gram_row_blocks(long long n);
+void launch_gram(long long n, int WX, int WY, const double *X, const double *Y, double *part, double scale, double *H,
+                 hipStream_t s);
+// out [n][WY] (+)= X [n][WX] C [WX][WY]
+void launch_rot(long long n, int WX, int WY, const double *X, const double *C, double *out, int accumulate,
+                hipStream_t s);
+void launch_hop_bound(const Lat &lat, int nc, const double *U8, double *out, hipStream_t s);
 void launch_to_abi(const Launch &L, const double *x64, double *xabi, long long rhs0, long long nvalid);
 void launch_abi_to_internal(const Launch &L, int prec, const double *vabi, long long rhs0,
                             long long nvalid, void *out);

@@ -23,6 +23,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -492,15 +493,21 @@ __device__ __forceinline__ void k_init_body(const Blk &bk, Launch L, ProbeGen g,
         if (site >= L.lat.N) continue;
         for (int a = 0; a < nc; ++a) {
             double re = 0.0, im = 0.0;
+            const size_t i = ((size_t)(site * nc + a) << logW) + j;
             if (SRC == 0) {
                 if (j < g.nvalid) probe_at(g, seedmix, L.lat, nc, pl, site, a, re, im);
-            } else if (j < nvalid) {
-                const double2 v = babi[((size_t)(rhs0 + j) * L.lat.N + site) * nc + a];
+            } else if (SRC == 1) {
+                if (j < nvalid) {
+                    const double2 v = babi[((size_t)(rhs0 + j) * L.lat.N + site) * nc + a];
+                    re = v.x;
+                    im = v.y;
+                }
+            } else {
+                const double2 v = b64[i];  // b already in place
                 re = v.x;
                 im = v.y;
             }
-            const size_t i = ((size_t)(site * nc + a) << logW) + j;
-            b64[i] = make_double2(re, im);
+            if (SRC != 2) b64[i] = make_double2(re, im);
             St<S>::st(r, i, (typename St<S>::R)re, (typename St<S>::R)im);
             St<S>::st(p, i, (typename St<S>::R)re, (typename St<S>::R)im);
             St<S>::st(xlo, i, 0, 0);
@@ -1319,6 +1326,183 @@ __global__ void k_b_ctrl(BatchLaunch B) {
     k_ctrl_body(d->cs, B.W);
 }
 
+// ============================================================ deflation
+//
+// Dense pieces of the deflated estimator (Sec. Deflation) on blocks of FP64
+// vectors in the internal layout, read as row-major matrices [n rows =
+// N * nc][width] (width = the block's lanes).
+
+// t_j = sum_x sum_b conj(u_j(x,b)) w_j(x + p e0, b)
+__global__ __launch_bounds__(kBlock) void k_dot_shift(Launch L, const double2 *__restrict__ u,
+                                                      const double2 *__restrict__ w, int p, Red rd) {
+    __shared__ double sm[2 * kBlock];
+    const int tid = threadIdx.x, logW = L.logW, W = L.W;
+    const int j = tid & (W - 1), sl = tid >> logW;
+    const int sites_per_tile = kBlock >> logW, nc = L.nc;
+    double acc[2] = {0.0, 0.0};
+    int t0, t1;
+    const Blk bk = own_blk();
+    tile_range(bk, L.ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int site = t * sites_per_tile + sl;
+        if (site >= L.lat.N) continue;
+        const int y = shift0(L.lat, site, p);
+        for (int b = 0; b < nc; ++b) {
+            const double2 a = u[((size_t)(site * nc + b) << logW) + j];
+            const double2 c = w[((size_t)(y * nc + b) << logW) + j];
+            acc[0] += a.x * c.x + a.y * c.y;
+            acc[1] += a.x * c.y - a.y * c.x;
+        }
+    }
+    block_partials<2>(bk, acc, W, logW, rd, sm);
+}
+
+// per-lane |u_j - theta_j w_j|^2 (Ritz residuals: u = A v, w = v)
+__global__ __launch_bounds__(kBlock) void k_resid_norm(Launch L, const double2 *__restrict__ u,
+                                                       const double2 *__restrict__ w,
+                                                       const double *__restrict__ theta, Red rd) {
+    __shared__ double sm[kBlock];
+    const int tid = threadIdx.x, W = L.W;
+    const int sites_per_tile = kBlock >> L.logW;
+    const double th = theta[tid & (W - 1)];
+    double acc[1] = {0.0};
+    int t0, t1;
+    const Blk bk = own_blk();
+    tile_range(bk, L.ntiles, t0, t1);
+    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
+    for (size_t e = e0 + tid; e < e1; e += kBlock) {
+        const double2 a = u[e], c = w[e];
+        const double dr = a.x - th * c.x, di = a.y - th * c.y;
+        acc[0] += dr * dr + di * di;
+    }
+    block_partials<1>(bk, acc, W, L.logW, rd, sm);
+}
+
+// out = a q + b v (real a, b; out may alias v)
+__global__ void k_axpby(long long n, double a, const double2 *__restrict__ q, double b, const double2 *v,
+                        double2 *out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double2 x = q[e], y = v[e];
+    out[e] = make_double2(a * x.x + b * y.x, a * x.y + b * y.y);
+}
+
+// v[e] = (+-1 +- i) from a SplitMix64 hash of (seed, e): start vectors of
+// the subspace iteration
+__global__ void k_rand_fill(long long n, unsigned long long seed, double2 *__restrict__ v) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const unsigned long long h = mix64(mix64(seed) ^ (unsigned long long)e);
+    v[e] = make_double2((h >> 63) ? -1.0 : 1.0, ((h >> 62) & 1) ? -1.0 : 1.0);
+}
+
+// out lane j = v lane j * s[j] (s[j] = 0 clears the lane)
+__global__ void k_scale_lanes(long long n, int W, const double *__restrict__ s, const double2 *__restrict__ v,
+                              double2 *__restrict__ out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double f = s[e % W];
+    const double2 x = v[e];
+    out[e] = make_double2(f * x.x, f * x.y);
+}
+
+// Partial products H = X^H Y over one range of rows per workgroup (blockIdx.x)
+// for one 64 x 64 output tile (blockIdx.y): part[blockIdx.x][blockIdx.y][64 * 64].
+// Rows are staged through LDS 8 at a time; thread t owns the entries
+// (t / 64 + 4 k, t % 64), k < 16, of the tile.
+constexpr int kGramTile = 64;
+__global__ __launch_bounds__(kBlock) void k_gram(long long n, int WX, int WY, const double2 *__restrict__ X,
+                                                 const double2 *__restrict__ Y, double2 *__restrict__ part) {
+    __shared__ double2 sx[8][kGramTile], sy[8][kGramTile];
+    const int tilesY = (WY + kGramTile - 1) / kGramTile;
+    const int i0 = (blockIdx.y / tilesY) * kGramTile, j0 = (blockIdx.y % tilesY) * kGramTile;
+    const int t = threadIdx.x, jl = t & (kGramTile - 1), il = t / kGramTile;
+    double ar[16], ai[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ar[k] = ai[k] = 0.0;
+    const long long r0 = n * blockIdx.x / gridDim.x, r1 = n * (blockIdx.x + 1) / gridDim.x;
+    for (long long rb = r0; rb < r1; rb += 8) {
+        __syncthreads();
+        for (int e = t; e < 8 * kGramTile; e += kBlock) {
+            const int rr = e / kGramTile, c = e % kGramTile;
+            const long long r = rb + rr;
+            sx[rr][c] = (r < r1 && i0 + c < WX) ? X[r * WX + i0 + c] : make_double2(0.0, 0.0);
+            sy[rr][c] = (r < r1 && j0 + c < WY) ? Y[r * WY + j0 + c] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+            const double2 y = sy[rr][jl];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const double2 x = sx[rr][il + 4 * k];
+                ar[k] = fma(x.x, y.x, fma(x.y, y.y, ar[k]));   // conj(x) y
+                ai[k] = fma(x.x, y.y, fma(-x.y, y.x, ai[k]));
+            }
+        }
+    }
+    double2 *o = part + ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * kGramTile * kGramTile;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) o[k * kBlock + t] = make_double2(ar[k], ai[k]);
+}
+
+// H[i][j] = scale * sum over the row ranges (in order) of the partials
+__global__ void k_gram_reduce(int nrb, int WX, int WY, const double2 *__restrict__ part, double scale,
+                              double2 *__restrict__ H) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= WX * WY) return;
+    const int i = e / WY, j = e % WY;
+    const int tilesY = (WY + kGramTile - 1) / kGramTile;
+    const int tiles = ((WX + kGramTile - 1) / kGramTile) * tilesY;
+    const int tile = (i / kGramTile) * tilesY + j / kGramTile;
+    const int off = (i % kGramTile) * kGramTile + j % kGramTile;
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < nrb; ++b) {
+        const double2 v = part[((size_t)b * tiles + tile) * kGramTile * kGramTile + off];
+        sr += v.x;
+        si += v.y;
+    }
+    H[e] = make_double2(scale * sr, scale * si);
+}
+
+// out[r][j] (+)= sum_i X[r][i] C[i][j], j < WY, i < WX (out must not alias X)
+__global__ void k_rot(long long n, int WX, int WY, const double2 *__restrict__ X, const double2 *__restrict__ C,
+                      double2 *__restrict__ out, int accumulate) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * WY) return;
+    const long long r = e / WY;
+    const int j = (int)(e - r * WY);
+    double sr = 0.0, si = 0.0;
+    if (accumulate) {
+        sr = out[e].x;
+        si = out[e].y;
+    }
+    const double2 *xr = X + r * WX;
+    for (int i = 0; i < WX; ++i) {
+        const double2 x = xr[i], c = C[(size_t)i * WY + j];
+        sr = fma(x.x, c.x, fma(-x.y, c.y, sr));
+        si = fma(x.x, c.y, fma(x.y, c.x, si));
+    }
+    out[e] = make_double2(sr, si);
+}
+
+// per-site bound sum over the eight hops of |U|_F (FP64 hop links)
+__global__ void k_hop_bound(Lat lat, int nc, const double2 *__restrict__ U8, double *__restrict__ out) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= lat.N) return;
+    double s = 0.0;
+    for (int d = 0; d < 8; ++d) {
+        double f = 0.0;
+        for (int e = 0; e < nc * nc; ++e) {
+            const double2 u = U8[((size_t)site * 8 + d) * nc * nc + e];
+            f += u.x * u.x + u.y * u.y;
+        }
+        s += sqrt(f);
+    }
+    out[site] = s;
+}
+
 // ============================================================ launchers
 
 static int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -1619,5 +1803,60 @@ void launch_b_dot(const BatchLaunch &B) {
 }
 
 void launch_b_ctrl(const BatchLaunch &B) { k_b_ctrl<<<B.nslots, 64, 0, B.stream>>>(B); }
+
+
+void launch_init_b64(const Launch &L, int prec, double *b64, void *r, void *p, void *xlo, double *x64, int mixed,
+                     const Red &rd, const CgState &cs) {
+    ProbeGen g{};
+    DP_DISPATCH_PREC(prec, S,
+                     k_init<S, 2><<<L.nblk, kBlock, 0, L.stream>>>(L, g, nullptr, 0, 0, (double2 *)b64, (S *)r,
+                                                                   (S *)p, (S *)xlo, (double2 *)x64, mixed, rd,
+                                                                   cs));
+    k_finish<1, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_dot_shift(const Launch &L, const double *u, const double *w, int p, const Red &rd, const CgState &cs) {
+    k_dot_shift<<<L.nblk, kBlock, 0, L.stream>>>(L, (const double2 *)u, (const double2 *)w, p, rd);
+    k_finish<2, kEpiTj><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_resid_norm(const Launch &L, const double *u, const double *w, const double *theta, const Red &rd,
+                       const CgState &cs) {
+    k_resid_norm<<<L.nblk, kBlock, 0, L.stream>>>(L, (const double2 *)u, (const double2 *)w, theta, rd);
+    k_finish<1, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_axpby(long long n, double a, const double *q, double b, const double *v, double *out, hipStream_t s) {
+    k_axpby<<<blocks_for(n), kBlock, 0, s>>>(n, a, (const double2 *)q, b, (const double2 *)v, (double2 *)out);
+}
+
+void launch_rand_fill(long long n, unsigned long long seed, double *v, hipStream_t s) {
+    k_rand_fill<<<blocks_for(n), kBlock, 0, s>>>(n, seed, (double2 *)v);
+}
+
+void launch_scale_lanes(long long n, int W, const double *sc, const double *v, double *out, hipStream_t s) {
+    k_scale_lanes<<<blocks_for(n), kBlock, 0, s>>>(n, W, sc, (const double2 *)v, (double2 *)out);
+}
+
+int gram_row_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(256, n / 512)); }
+
+void launch_gram(long long n, int WX, int WY, const double *X, const double *Y, double *part, double scale, double *H,
+                 hipStream_t s) {
+    const int nrb = gram_row_blocks(n);
+    const int tiles = ((WX + kGramTile - 1) / kGramTile) * ((WY + kGramTile - 1) / kGramTile);
+    k_gram<<<dim3(nrb, tiles), kBlock, 0, s>>>(n, WX, WY, (const double2 *)X, (const double2 *)Y, (double2 *)part);
+    k_gram_reduce<<<blocks_for((long long)WX * WY), kBlock, 0, s>>>(nrb, WX, WY, (const double2 *)part, scale,
+                                                                   (double2 *)H);
+}
+
+void launch_rot(long long n, int WX, int WY, const double *X, const double *C, double *out, int accumulate,
+                hipStream_t s) {
+    k_rot<<<blocks_for(n * WY), kBlock, 0, s>>>(n, WX, WY, (const double2 *)X, (const double2 *)C, (double2 *)out,
+                                               accumulate);
+}
+
+void launch_hop_bound(const Lat &lat, int nc, const double *U8, double *out, hipStream_t s) {
+    k_hop_bound<<<blocks_for(lat.N), kBlock, 0, s>>>(lat, nc, (const double2 *)U8, out);
+}
 
 }  // namespace dp

@@ -554,5 +554,7 @@ template dp_status solve_block<InitProbe>(dp_ctx *, const OpPrep &, const SolveC
                                           const CgState &, double *, InitProbe, BlockStats &, dp_solve_stats *);
 template dp_status solve_block<InitAbi>(dp_ctx *, const OpPrep &, const SolveCfg &, const Launch &, const Red &,
                                         const CgState &, double *, InitAbi, BlockStats &, dp_solve_stats *);
+template dp_status solve_block<InitDeflated>(dp_ctx *, const OpPrep &, const SolveCfg &, const Launch &, const Red &,
+                                        const CgState &, double *, InitDeflated, BlockStats &, dp_solve_stats *);
 
 }  // namespace dp
