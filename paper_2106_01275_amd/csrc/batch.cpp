@@ -290,7 +290,11 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     // (one copy per finished slot into its pinned mirror, one synchronisation)
     auto finish_slots = [&]() -> dp_status {
         DP_TRY(upload());
-        launch_b_ru(B, 1);
+        // mixed precision: a slot finishes only after a reliable update
+        // (which folded x and took the true residual of the final x64) or
+        // with no active lane from the start; FP64: apply the deferred
+        // solution update and take the true residual now
+        if (!mixed) launch_b_ru(B, 1);
         if (trace_mode) launch_b_dot(B);
         DP_HIP(hipGetLastError());
         for (int k = 0; k < nslots; ++k) {

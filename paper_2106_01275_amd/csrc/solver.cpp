@@ -356,11 +356,16 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             nactive = ctx->ctrl_host[0];
         }
     }
-    // the deferred solution update of the last iteration (and xlo, mixed)
-    launch_fold(L, cfg.inner, x64, mixed ? xlo : nullptr, p, cs);
-    // final FP64 true residual (statistics only)
-    launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs, init.probe());
-    DP_HIP(hipGetLastError());
+    // Mixed precision: lanes stop only at a reliable update, which folded
+    // x and left the FP64 true residual of the final x64 in true_rr, so
+    // with no lane active there is nothing left to do.  Otherwise (FP64, or
+    // max_iter reached) apply the deferred solution update of the last
+    // iteration (and xlo) and take the final true residual (statistics).
+    if (!(mixed && nactive == 0)) {
+        launch_fold(L, cfg.inner, x64, mixed ? xlo : nullptr, p, cs);
+        launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs, init.probe());
+        DP_HIP(hipGetLastError());
+    }
     const int W = L.W;
     double *h = ctx->state_host;
     DP_HIP(hipMemcpyAsync(h, cs.true_rr, W * sizeof(double), hipMemcpyDeviceToHost, L.stream));
