@@ -133,6 +133,31 @@ def test_deflated_mixed_precision(ctx, gauge4, inner):
     d.close()
 
 
+def test_wide_subspace_and_blocks(ctx, gauge4):
+    """60 vectors (a 128-vector subspace: two 64-wide tiles in the Gram
+    kernel) and 64-wide right-hand-side blocks: Ritz values against dense
+    eigh, the deflated estimate against the oracle, and graph replay equal to
+    the eager launches."""
+    _say("deflation 60 vectors, W 64 blocks, graph replay")
+    U, _, _ = gauge4
+    w, V = oracle.lowest_eigenpairs(D4, 3, 0.1, U, 61)
+    op = ctx.operator(D4, 3, 0.1, cuda(U))
+    d = ctx.deflation(op, 60, tol=1e-11, seed=5)
+    assert d.subspace == 128
+    assert np.max(np.abs(d.evals - w[:60]) / w[:60]) < 1e-10
+    col, m, _ = oracle.coloring(D4, 1, 2, oracle.NATURAL)
+    ps = ctx.probe_spec(D4, 3, cuda(col), m, 6, 0, 2, "z2_complex", True)
+    r = ctx.trace_deflated(op, d, 1, ps, ctx.opts(tol=1e-12, inner="f64", rhs_block=64))
+    rg = ctx.trace_deflated(op, d, 1, ps, ctx.opts(tol=1e-12, inner="f64", rhs_block=64, use_graph=1))
+    assert np.array_equal(r["tj"], rg["tj"])
+    o = oracle.trace_deflated(D4, 3, 0.1, U, 1, col, m, 6, 0, 2, oracle.Z2_COMPLEX, True, V[:60])
+    gap = (w[60] - w[59]) / w[59]
+    tol = max(1e-8, 1e-11 / gap)
+    assert abs(r["T_defl"] - o["T_defl"]) < tol * abs(o["T_defl"])
+    assert np.abs(r["per_sample"] - o["per_sample"]).max() < tol * abs(o["T"])
+    d.close()
+
+
 def test_bad_arguments(ctx):
     op = ctx.operator(D4, 1, 0.5, None)
     for nvec in (0, 104):
