@@ -173,6 +173,11 @@ dp_status dp_create(dp_ctx **out, int32_t hip_device) {
         dp_destroy(ctx);
         return DP_ENOMEM;
     }
+    if (hipHostGetDevicePointer((void **)&ctx->ctrl_dev, ctx->ctrl_host, 0) != hipSuccess) {
+        g_err = "dp_create: hipHostGetDevicePointer failed";
+        dp_destroy(ctx);
+        return DP_EHIP;
+    }
     *out = ctx;
     return DP_OK;
 }

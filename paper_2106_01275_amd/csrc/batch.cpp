@@ -117,8 +117,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     // slot buffers; descriptor nslots is an idle one for unused workgroups
     std::vector<SlotDesc> hsd(nslots + 1);
     std::memset(&hsd[nslots], 0, sizeof(SlotDesc));
-    int *ctrl_all = nullptr;
-    DP_TRY(mem.alloc(ctx, (void **)&ctrl_all, (size_t)nslots * 8 * sizeof(double), true));
+
     // CG state of all slots in one block (one stride per slot), mirrored in
     // pinned host memory for the read-back of finished slots
     const size_t st_doubles = 9 * kMaxW + 8, st_ints = 3 * kMaxW + 8;
@@ -127,7 +126,13 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     DP_TRY(mem.alloc(ctx, (void **)&st_all, st_stride * nslots));
     char *st_host = nullptr;
     DP_TRY(ctx->host_pinned(st_stride * nslots + sizeof(int) * 16 * nslots, (void **)&st_host));
+    // control words of the slots: pinned host memory that k_b_ctrl writes
+    // through its device alias (no copy before the host reads them)
     int *hctrl = (int *)(st_host + st_stride * nslots);
+    std::memset(hctrl, 0, sizeof(int) * 16 * nslots);
+    char *st_dev = nullptr;
+    DP_HIP(hipHostGetDevicePointer((void **)&st_dev, st_host, 0));
+    int *ctrl_all = (int *)(st_dev + st_stride * nslots);
     for (int k = 0; k < nslots; ++k) {
         SlotDesc &d = hsd[k];
         std::memset(&d, 0, sizeof d);
@@ -281,7 +286,6 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     };
     auto read_ctrl_all = [&]() -> dp_status {
         launch_b_ctrl(B);
-        DP_HIP(hipMemcpyAsync(hctrl, ctrl_all, sizeof(int) * 16 * nslots, hipMemcpyDeviceToHost, s));
         DP_HIP(hipStreamSynchronize(s));
         if (cfg.profile) DP_TRY(finish_profile(ctx, &in[0].st));
         return DP_OK;

@@ -57,6 +57,7 @@ struct dp_ctx {
     void *slot[dp::kNumSlots] = {};
     size_t slot_bytes[dp::kNumSlots] = {};
     int *ctrl_host = nullptr;        // pinned [16]: 4 counts, then 2 doubles at [4] and [6]
+    int *ctrl_dev = nullptr;         // the same memory as the device sees it (k_ctrl writes it)
     double *state_host = nullptr;    // pinned staging of per-lane results
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;

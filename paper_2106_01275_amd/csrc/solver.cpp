@@ -204,12 +204,14 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     cs.beta = d + 5 * kMaxW;
     cs.true_rr = d + 6 * kMaxW;
     cs.tj = d + 7 * kMaxW;
-    cs.ctrld = d + 9 * kMaxW;
+    // the control word lives in pinned host memory: k_ctrl writes it there
+    // and the host reads it after the synchronisation, no copy
+    cs.ctrld = (double *)(ctx->ctrl_dev + 4);
     int *iv = (int *)(d + nd);
     cs.active = iv;
     cs.iters = iv + kMaxW;
     cs.flags = iv + 2 * kMaxW;
-    cs.ctrl = iv + 3 * kMaxW;
+    cs.ctrl = ctx->ctrl_dev;
     cs.tol2 = cfg.tol * cfg.tol;
     cs.delta2 = cfg.delta * cfg.delta;
     cs.hold = cfg.inner == kBF16;
@@ -219,8 +221,6 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
 
 static dp_status read_ctrl(dp_ctx *ctx, const CgState &cs, int W, hipStream_t s) {
     launch_ctrl(cs, W, s);
-    DP_HIP(hipMemcpyAsync(ctx->ctrl_host, cs.ctrl, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-    DP_HIP(hipMemcpyAsync(ctx->ctrl_host + 4, cs.ctrld, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     DP_HIP(hipStreamSynchronize(s));
     return DP_OK;
 }
