@@ -193,6 +193,30 @@ def run_gauge16(a, torch, dp, workloads):
         tt = {"samples": s_star, "seconds": s_star * sec_per_sample, "per_sample_var": var,
               "T_mean": [Ts.mean().real, Ts.mean().imag]}
     extra = {"time_to_trace_1e-3": tt}
+    if not a.no_plain and tt is not None:
+        # time to 1e-3 relative error per nested level (k = 1, 2, 4, 8) and for plain Hutchinson (one
+        # colour): per-sample variance from 8 samples (the finest level: the timed samples), samples
+        # needed = var / (1e-3 |T|)^2, seconds = that many samples at the measured seconds per sample
+        opts.profile = 0
+        levels = []
+        lv_cols = [(f"k={k}", cols[i], int(ncols[i])) for i, k in enumerate(w.ks)]
+        lv_cols.insert(0, ("hutchinson", np.zeros(N, dtype=np.int32), 1))
+        for name, cl, ml in lv_cols:
+            if name == f"k={w.ks[level]}":
+                sec, var, Tm = sec_per_sample, tt["per_sample_var"], complex(*tt["T_mean"])
+            else:
+                ps = c.probe_spec(dims, nc, torch.from_numpy(np.ascontiguousarray(cl)).cuda(), ml, w.noise_seed,
+                                  0, 8, "z2_complex", True)
+                torch.cuda.synchronize()
+                tl = time.perf_counter()
+                r = c.trace_estimate([op], [ps], [p], opts)[0]
+                torch.cuda.synchronize()
+                sec = (time.perf_counter() - tl) / 8
+                var, Tm = float(np.var(r["per_sample"], ddof=1)), r["T"]
+            need = max(1, int(np.ceil(var / (1e-3 * abs(Tm)) ** 2)))
+            levels.append({"level": name, "colours": ml, "rhs_per_sample": ml * nc, "seconds_per_sample": sec,
+                           "per_sample_var": var, "samples_for_1e-3": need, "seconds_to_1e-3": need * sec})
+        extra["levels_time_to_1e-3"] = levels
     if not a.no_plain:
         # one probe set for the displacements n = 0..8 (Sec. 4.3): the same solves, nine contractions
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, 0, 1, "z2_complex", True)
