@@ -148,3 +148,23 @@ def test_gauge32_gradient_finite_differences(ctx):
         _say("  direction", d, fdU, an)
         assert abs(fdU - an) <= 1e-6 * abs(an) + abs(fdU2 - fdU), (d, fdU, fdU2, an)
         assert abs(fdU - an) < 1e-4 * abs(an), (d, fdU, an)
+
+
+def test_gauge32_fp32_storage_matches_fp64(ctx):
+    """The 32^4 gradient workload as the benchmark runs it (FP32 storage,
+    FP64 reliable updates, W = 32, tol 1e-10) against FP64 storage at the
+    same tolerance: T, dT/dm2 and both link gradients agree to the
+    mixed-precision bar of 1e-6, and every FP64 true residual is <= 1e-10."""
+    w = workloads.GAUGE_32
+    _say("32^4 gradient, FP32 storage vs FP64")
+    col, n, _ = dp.build_coloring(w.dims, w.p, 8, "natural")
+    colg = torch.from_numpy(col).cuda()
+    op = ctx.operator(w.dims, 3, w.m2, torch.from_numpy(w.links()).cuda())
+    ps = ctx.probe_spec(w.dims, 3, colg, n, 0, 0, 1, "z2_complex", True)
+    T64, g64, dU64, dUb64, st64 = ctx.trace_grad(op, ps, w.p, ctx.opts(tol=1e-10, inner="f64", rhs_block=32))
+    T32, g32, dU32, dUb32, st32 = ctx.trace_grad(op, ps, w.p, ctx.opts(tol=1e-10, inner="f32", rhs_block=32))
+    assert st32["nconverged"] == st32["nrhs"] == 2 * 96 and st32["max_true_resid"] <= 1e-10
+    assert abs(T32 - T64) < 1e-6 * abs(T64)
+    assert abs(g32 - g64) < 1e-6 * abs(g64)
+    for a, b in ((dU32, dU64), (dUb32, dUb64)):
+        assert (a - b).abs().max().item() < 1e-6 * b.abs().max().item()
