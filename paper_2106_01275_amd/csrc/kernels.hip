@@ -280,28 +280,46 @@ enum Epi { kEpiInit, kEpiAlpha, kEpiBeta, kEpiRU, kEpiStats, kEpiTj };
 // the scalar epilogue of that lane.
 template <int NV, int EPI>
 __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgState &cs) {
-    __shared__ double sm[NV * kBlock];
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double sm[NV * kWaves];
     const int tid = threadIdx.x;
-    double s[NV];
+    const double *src = rd.part1 + (size_t)lane * rd.nblk * NV;
+    // thread tid adds partials tid, tid + kBlock, ... (four loads in flight),
+    // then a fixed butterfly in each wavefront and the wavefronts in order:
+    // the same summation order on every call
+    double s[NV], s2[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) s[v] = 0.0;
-    for (int b = tid; b < rd.nblk; b += kBlock) {
+    for (int v = 0; v < NV; ++v) s[v] = s2[v] = 0.0;
+    int b = tid;
+    for (; b + 3 * kBlock < rd.nblk; b += 4 * kBlock) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s[v] += rd.part1[((size_t)lane * rd.nblk + b) * NV + v];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sm[v * kBlock + tid] = s[v];
-    __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-        if (tid < h) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sm[v * kBlock + tid] += sm[v * kBlock + tid + h];
+        for (int v = 0; v < NV; ++v) {
+            const double a0 = src[(size_t)b * NV + v], a1 = src[(size_t)(b + kBlock) * NV + v];
+            const double a2 = src[(size_t)(b + 2 * kBlock) * NV + v], a3 = src[(size_t)(b + 3 * kBlock) * NV + v];
+            s[v] += a0 + a1;
+            s2[v] += a2 + a3;
         }
-        __syncthreads();
     }
+    for (; b < rd.nblk; b += kBlock) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s[v] += src[(size_t)b * NV + v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double x = s[v] + s2[v];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if ((tid & 63) == 0) sm[v * kWaves + tid / 64] = x;
+    }
+    __syncthreads();
     if (tid != 0) return;
+    double tot[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        tot[v] = 0.0;
+        for (int w = 0; w < kWaves; ++w) tot[v] += sm[v * kWaves + w];
+    }
     const int j = lane;
-    const double t = sm[0];
+    const double t = tot[0];
     if (EPI == kEpiInit) {
         cs.bb[j] = t;
         cs.rr[j] = t;
@@ -363,8 +381,8 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
             }
         }
     } else {
-        cs.tj[2 * j] = sm[0];
-        cs.tj[2 * j + 1] = NV > 1 ? sm[kBlock] : 0.0;
+        cs.tj[2 * j] = tot[0];
+        cs.tj[2 * j + 1] = NV > 1 ? tot[NV - 1] : 0.0;
     }
 }
 
