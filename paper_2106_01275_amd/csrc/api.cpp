@@ -168,7 +168,7 @@ dp_status dp_create(dp_ctx **out, int32_t hip_device) {
     }
     ctx->device = hip_device;
     if (hipHostMalloc((void **)&ctx->ctrl_host, 64, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->state_host, 8 * kMaxW * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&ctx->state_host, state_bytes(), hipHostMallocDefault) != hipSuccess) {
         g_err = "dp_create: pinned allocation failed";
         dp_destroy(ctx);
         return DP_ENOMEM;
@@ -416,6 +416,23 @@ static void combine(const dp_probe_spec &ps, const std::vector<double> &tj, dp_t
 
 // The probes of ps solved once; every solution contracted with each of the
 // ndisp displacements (any sign).  outs[n] gets the estimate for disp[n].
+// Pinned staging of one call's per-block results: every block's state (for
+// its statistics) and its contractions are copied there in stream order and
+// read once after the call's final synchronisation, so consecutive blocks
+// follow each other on the device without a host round trip.
+struct Staging {
+    char *base = nullptr;
+    size_t sb = 0;
+    long long nblocks = 0;
+    dp_status init(dp_ctx *ctx, long long nblk, size_t result_doubles) {
+        sb = (state_bytes() + 255) / 256 * 256;
+        nblocks = nblk;
+        return ctx->host_pinned((size_t)nblk * sb + result_doubles * sizeof(double), (void **)&base);
+    }
+    void *state(long long k) const { return base + (size_t)k * sb; }
+    double *results() const { return (double *)(base + (size_t)nblocks * sb); }
+};
+
 static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const int32_t *disp, int ndisp,
                                      const dp_probe_spec &ps, const dp_solve_opts *o, const SolveCfg &cfg,
                                      dp_trace_result *outs, hipStream_t stream) {
@@ -433,23 +450,30 @@ static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const 
     DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
     dp_solve_stats s{};
     s.rhs_block = W;
-    std::vector<std::vector<double>> tj(ndisp, std::vector<double>(2 * nrhs, 0.0));
-    for (long long r0 = 0; r0 < nrhs; r0 += W) {
-        const long long nv = std::min<long long>(W, nrhs - r0);
-        BlockStats bs;
-        bs.nvalid = (int)nv;
+    const long long nblocks = (nrhs + W - 1) / W;
+    Staging stg;
+    DP_TRY(stg.init(ctx, nblocks, (size_t)ndisp * 2 * nrhs));
+    std::vector<BlockStats> bss(nblocks);
+    for (long long k = 0; k < nblocks; ++k) {
+        const long long r0 = k * W, nv = std::min<long long>(W, nrhs - r0);
+        bss[k].nvalid = (int)nv;
         InitProbe init{&L, cfg.inner, make_gen(ps, r0, nv, 0), &rd, &cs, ctx};
         double *x64 = (double *)ctx->at(kSlotX64);
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bss[k], &s, stg.state(k)));
         for (int n = 0; n < ndisp; ++n) {
             // each contraction reads x only at the probe's sites shifted by disp[n]
             launch_displaced_dot(L, make_gen(ps, r0, nv, 0), disp[n], x64, rd, cs);
             DP_HIP(hipGetLastError());
-            DP_HIP(hipMemcpyAsync(tj[n].data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost,
-                                  stream));
+            DP_HIP(hipMemcpyAsync(stg.results() + (size_t)n * 2 * nrhs + 2 * r0, cs.tj, 2 * nv * sizeof(double),
+                                  hipMemcpyDeviceToHost, stream));
         }
     }
     DP_HIP(hipStreamSynchronize(stream));
+    DP_TRY(finish_profile(ctx, &s));
+    for (long long k = 0; k < nblocks; ++k) block_stats(stg.state(k), bss[k], &s);
+    std::vector<std::vector<double>> tj(ndisp);
+    for (int n = 0; n < ndisp; ++n)
+        tj[n].assign(stg.results() + (size_t)n * 2 * nrhs, stg.results() + (size_t)(n + 1) * 2 * nrhs);
     s.seconds = now_s() - t0;
     for (int n = 0; n < ndisp; ++n) {
         combine(ps, tj[n], outs[n]);
@@ -597,24 +621,30 @@ dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *opd, int32_t p, const dp
     const double norm = noise_norm(ps->noise) / ps->nsamples;
     dp_solve_stats s{};
     s.rhs_block = W;
-    std::vector<double> tj(2 * nrhs, 0.0), lx(2 * nrhs, 0.0);
-    for (long long r0 = 0; r0 < nrhs; r0 += W) {
-        const long long nv = std::min<long long>(W, nrhs - r0);
-        BlockStats bs1, bs2;
-        bs1.nvalid = bs2.nvalid = (int)nv;
+    const long long nblocks = (nrhs + W - 1) / W;
+    Staging stg;
+    DP_TRY(stg.init(ctx, 2 * nblocks, 4 * (size_t)nrhs));
+    double *tjh = stg.results(), *lxh = stg.results() + 2 * nrhs;
+    std::vector<BlockStats> bss(2 * nblocks);
+    for (long long k = 0; k < nblocks; ++k) {
+        const long long r0 = k * W, nv = std::min<long long>(W, nrhs - r0);
+        bss[2 * k].nvalid = bss[2 * k + 1].nvalid = (int)nv;
         InitProbe ix{&L, cfg.inner, make_gen(*ps, r0, nv, 0), &rd, &cs, ctx};
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, xsol, ix, bs1, &s));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, xsol, ix, bss[2 * k], &s, stg.state(2 * k)));
         launch_displaced_dot(L, make_gen(*ps, r0, nv, 0), p, xsol, rd, cs);
-        DP_HIP(hipMemcpyAsync(tj.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        DP_HIP(hipMemcpyAsync(tjh + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
         InitProbe il{&L, cfg.inner, make_gen(*ps, r0, nv, p), &rd, &cs, ctx};
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, lsol, il, bs2, &s));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, lsol, il, bss[2 * k + 1], &s, stg.state(2 * k + 1)));
         launch_dot(L, lsol, xsol, rd, cs);
-        DP_HIP(hipMemcpyAsync(lx.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        DP_HIP(hipMemcpyAsync(lxh + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
         if (dT_dU || dT_dUbar)
             launch_force(L, xsol, lsol, op.nbr, norm, r0 == 0, (double *)dT_dU, (double *)dT_dUbar);
         DP_HIP(hipGetLastError());
     }
     DP_HIP(hipStreamSynchronize(stream));
+    DP_TRY(finish_profile(ctx, &s));
+    for (long long k = 0; k < 2 * nblocks; ++k) block_stats(stg.state(k), bss[k], &s);
+    std::vector<double> tj(tjh, tjh + 2 * nrhs), lx(lxh, lxh + 2 * nrhs);
     double Tr = 0, Ti = 0, gr = 0, gi = 0;
     for (long long j = 0; j < nrhs; ++j) {
         Tr += tj[2 * j];
@@ -767,21 +797,27 @@ dp_status dp_trace_deflated(dp_ctx *ctx, const dp_operator *opd, const dp_deflat
     DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
     dp_solve_stats s{};
     s.rhs_block = W;
-    std::vector<double> tj(2 * nrhs, 0.0);
+    const long long nblocks = (nrhs + W - 1) / W;
+    Staging stg;
+    DP_TRY(stg.init(ctx, nblocks, 2 * (size_t)nrhs));
+    std::vector<BlockStats> bss(nblocks);
     dp_status proj = DP_OK;
-    for (long long r0 = 0; r0 < nrhs; r0 += W) {
-        const long long nv = std::min<long long>(W, nrhs - r0);
-        BlockStats bs;
-        bs.nvalid = (int)nv;
+    for (long long k = 0; k < nblocks; ++k) {
+        const long long r0 = k * W, nv = std::min<long long>(W, nrhs - r0);
+        bss[k].nvalid = (int)nv;
         InitDeflated init{&L, cfg.inner, make_gen(*ps, r0, nv, 0), &rd, &cs, ctx, d, &proj};
         double *x64 = (double *)ctx->at(kSlotX64);
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bss[k], &s, stg.state(k)));
         DP_TRY(proj);
         launch_displaced_dot(L, make_gen(*ps, r0, nv, 0), p, x64, rd, cs);
         DP_HIP(hipGetLastError());
-        DP_HIP(hipMemcpyAsync(tj.data() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        DP_HIP(hipMemcpyAsync(stg.results() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost,
+                              stream));
     }
     DP_HIP(hipStreamSynchronize(stream));
+    DP_TRY(finish_profile(ctx, &s));
+    for (long long k = 0; k < nblocks; ++k) block_stats(stg.state(k), bss[k], &s);
+    std::vector<double> tj(stg.results(), stg.results() + 2 * nrhs);
     s.seconds = now_s() - t0;
     combine(*ps, tj, *out);
     out->tr[0] += td[0];

@@ -61,7 +61,11 @@ struct dp_ctx {
     double *state_host = nullptr;    // pinned staging of per-lane results
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-    double ev_bytes = 0;                      // algorithmic bytes of the pending timed launches
+    double ev_bytes = 0;                      // algorithmic bytes of the timed launches not yet reported
+    double ev_ms = 0;                         // summed durations of the harvested timed launches
+    int ev_done = 0;                          // number of those
+    unsigned ev_seq = 0;                      // timed-launch candidates so far (sampling)
+    dp_status harvest_events(size_t n);       // reads and recycles the n oldest pending event pairs
     std::map<std::string, int> tuned_w;       // autotuned block widths
     bool tune_loaded = false;
     int check_every = 8;
@@ -103,9 +107,15 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
                       const SolveCfg &cfg);
 // Runs CG on the block initialised by `init` (a callable launching the init
 // kernel).  On return the FP64 solution is in x64_dst (internal layout).
+// With `defer` (pinned host memory of state_bytes()) the block's state is
+// copied there without a synchronisation and block_stats() is left to the
+// caller; otherwise the statistics are added to bs and acc before return.
 template <typename Init>
 dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
-                      const CgState &cs, double *x64_dst, Init init, BlockStats &bs, dp_solve_stats *acc);
+                      const CgState &cs, double *x64_dst, Init init, BlockStats &bs, dp_solve_stats *acc,
+                      void *defer = nullptr);
+size_t state_bytes();
+void block_stats(const void *state, BlockStats &bs, dp_solve_stats *acc);
 // For a batch, `work` lists (right-hand sides, sites) of every instance: the
 // cost of a width then counts the padded lanes of each instance's last job.
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
@@ -117,10 +127,15 @@ dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
 // otherwise with null events
 template <typename F>
 dp_status timed_launch(dp_ctx *ctx, bool profile, double bytes, F launch) {
-    if (!profile) {
+    // every kEventStride-th launch carries the events: two events per launch
+    // cost host time that a launch-bound solve (a few thousand sites) pays
+    // in full; the sampled launches give the same average
+    constexpr unsigned kEventStride = 8;
+    if (!profile || (ctx->ev_seq++ % kEventStride) != 0) {
         launch(hipEvent_t(nullptr), hipEvent_t(nullptr));
         return DP_OK;
     }
+    if (ctx->ev_pool.size() < 2 && ctx->ev_pending.size() >= 256) DP_TRY(ctx->harvest_events(128));
     if (ctx->ev_pool.size() < 2) {
         for (int i = 0; i < 64; ++i) {
             // timing only: no system-scope fence (no L2 writeback around the timed launch)
@@ -189,6 +204,7 @@ struct InitProbe {
                           prec != kF64, *rd, *cs);
     }
     const ProbeGen *probe() const { return &g; }  // b is these probes
+    static constexpr bool kLanesNonzero = true;     // a probe has a site of its colour
 };
 
 struct InitAbi {
@@ -204,6 +220,7 @@ struct InitAbi {
                         ctx->at(kSlotP), xlo, x64, prec != kF64, *rd, *cs);
     }
     const ProbeGen *probe() const { return nullptr; }  // b is read back from b64
+    static constexpr bool kLanesNonzero = false;       // the caller's b may be zero
 };
 
 // deflation.cpp: the eigensolve, b64 -= Z (V^H b64) for one block of W
@@ -234,6 +251,7 @@ struct InitDeflated {
         launch_init_b64(*L, prec, b64, ctx->at(kSlotR), ctx->at(kSlotP), xlo, x64, prec != kF64, *rd, *cs);
     }
     const ProbeGen *probe() const { return nullptr; }
+    static constexpr bool kLanesNonzero = true;  // (assumed; a zero lane only costs one group)
 };
 
 }  // namespace dp

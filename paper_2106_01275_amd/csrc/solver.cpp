@@ -90,6 +90,23 @@ dp_status dp_ctx::host_pinned(size_t bytes, void **out) {
     return DP_OK;
 }
 
+dp_status dp_ctx::harvest_events(size_t n) {
+    dp_ctx *ctx = this;
+    n = std::min(n, ev_pending.size());
+    for (size_t i = 0; i < n; ++i) {
+        auto &pr = ev_pending[i];
+        DP_HIP(hipEventSynchronize(pr.second));
+        float ms = 0;
+        DP_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        ev_ms += ms;
+        ++ev_done;
+        ev_pool.push_back(pr.first);
+        ev_pool.push_back(pr.second);
+    }
+    ev_pending.erase(ev_pending.begin(), ev_pending.begin() + (long)n);
+    return DP_OK;
+}
+
 void dp_ctx::drop_graphs() {
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
@@ -251,29 +268,50 @@ static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L
 }
 
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
-    if (ctx->ev_pending.empty()) return DP_OK;
-    double ms_sum = 0;
-    for (auto &pr : ctx->ev_pending) {
-        DP_HIP(hipEventSynchronize(pr.second));
-        float ms = 0;
-        DP_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-        ms_sum += ms;
-        ctx->ev_pool.push_back(pr.first);
-        ctx->ev_pool.push_back(pr.second);
-    }
+    DP_TRY(ctx->harvest_events(ctx->ev_pending.size()));
     if (st) {
-        st->stencil_ms += ms_sum;
-        st->stencil_launches += (int)ctx->ev_pending.size();
+        st->stencil_ms += ctx->ev_ms;
+        st->stencil_launches += ctx->ev_done;
         st->stencil_bytes += ctx->ev_bytes;
     }
-    ctx->ev_pending.clear();
+    ctx->ev_ms = 0;
+    ctx->ev_done = 0;
     ctx->ev_bytes = 0;
     return DP_OK;
 }
 
+size_t state_bytes() { return (9 * kMaxW + 8) * sizeof(double) + (3 * kMaxW + 8) * sizeof(int); }
+
+void block_stats(const void *state, BlockStats &bs, dp_solve_stats *acc) {
+    // the layout of make_launch: doubles rr .. tj, then the ints active, iters, flags
+    const double *d = (const double *)state;
+    const double *true_rr = d + 6 * kMaxW, *bbv = d + 3 * kMaxW;
+    const int *iv = (const int *)(d + 9 * kMaxW + 8);
+    const int *iters = iv + kMaxW, *flags = iv + 2 * kMaxW;
+    for (int j = 0; j < bs.nvalid; ++j) {
+        const double bb = bbv[j];
+        const double rel = bb > 0 ? std::sqrt(true_rr[j] / bb) : 0.0;
+        bs.max_rel = std::max(bs.max_rel, rel);
+        bs.iters_sum += iters[j];
+        bs.iters_max = std::max(bs.iters_max, iters[j]);
+        if (flags[j] & kFlagBreakdown) ++bs.nbreak;
+        else if (flags[j] & kFlagConverged) ++bs.nconv;
+    }
+    if (acc) {
+        acc->rhs_iters += bs.iters_sum;
+        acc->max_iters = std::max(acc->max_iters, bs.iters_max);
+        acc->nconverged += bs.nconv;
+        acc->nbreakdown += bs.nbreak;
+        acc->reliable_updates += bs.ru;
+        acc->max_true_resid = std::max(acc->max_true_resid, bs.max_rel);
+        acc->nrhs += bs.nvalid;
+    }
+}
+
 template <typename Init>
 dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
-                      const CgState &cs, double *x64, Init init, BlockStats &bs, dp_solve_stats *acc) {
+                      const CgState &cs, double *x64, Init init, BlockStats &bs, dp_solve_stats *acc,
+                      void *defer) {
     const bool mixed = cfg.inner != kF64;
     void *xlo = mixed ? ctx->at(kSlotXLo) : (void *)x64;
     void *r = ctx->at(kSlotR), *p = ctx->at(kSlotP), *q = ctx->at(kSlotQ);
@@ -281,8 +319,11 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     const double diag = op.m2 + 8.0;
     init(xlo, x64);  // b, r = p = b, xlo = 0 (x64 = 0)
     DP_HIP(hipGetLastError());
-    DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
-    int nactive = ctx->ctrl_host[0];
+    int nactive = bs.nvalid;
+    if (!Init::kLanesNonzero) {
+        DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
+        nactive = ctx->ctrl_host[0];
+    }
     int it = 0;
     bool pending = false;  // p = r + beta p not yet applied
     StencilArgs a;
@@ -366,33 +407,18 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
         launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs, init.probe());
         DP_HIP(hipGetLastError());
     }
-    const int W = L.W;
-    double *h = ctx->state_host;
-    DP_HIP(hipMemcpyAsync(h, cs.true_rr, W * sizeof(double), hipMemcpyDeviceToHost, L.stream));
-    DP_HIP(hipMemcpyAsync(h + kMaxW, cs.bb, W * sizeof(double), hipMemcpyDeviceToHost, L.stream));
-    int *hi = (int *)(h + 2 * kMaxW);
-    DP_HIP(hipMemcpyAsync(hi, cs.iters, W * sizeof(int), hipMemcpyDeviceToHost, L.stream));
-    DP_HIP(hipMemcpyAsync(hi + kMaxW, cs.flags, W * sizeof(int), hipMemcpyDeviceToHost, L.stream));
+    // the block's state (one copy); deferred: the caller reads it after its
+    // next synchronisation, so the next block's work queues behind this one
+    // without a host round trip
+    if (defer) {
+        DP_HIP(hipMemcpyAsync(defer, cs.rr, state_bytes(), hipMemcpyDeviceToHost, L.stream));
+        return DP_OK;
+    }
+    void *h = ctx->state_host;
+    DP_HIP(hipMemcpyAsync(h, cs.rr, state_bytes(), hipMemcpyDeviceToHost, L.stream));
     DP_HIP(hipStreamSynchronize(L.stream));
     DP_TRY(finish_profile(ctx, acc));
-    for (int j = 0; j < bs.nvalid; ++j) {
-        const double bb = h[kMaxW + j];
-        const double rel = bb > 0 ? std::sqrt(h[j] / bb) : 0.0;
-        bs.max_rel = std::max(bs.max_rel, rel);
-        bs.iters_sum += hi[j];
-        bs.iters_max = std::max(bs.iters_max, hi[j]);
-        if (hi[kMaxW + j] & kFlagBreakdown) ++bs.nbreak;
-        else if (hi[kMaxW + j] & kFlagConverged) ++bs.nconv;
-    }
-    if (acc) {
-        acc->rhs_iters += bs.iters_sum;
-        acc->max_iters = std::max(acc->max_iters, bs.iters_max);
-        acc->nconverged += bs.nconv;
-        acc->nbreakdown += bs.nbreak;
-        acc->reliable_updates += bs.ru;
-        acc->max_true_resid = std::max(acc->max_true_resid, bs.max_rel);
-        acc->nrhs += bs.nvalid;
-    }
+    block_stats(h, bs, acc);
     return DP_OK;
 }
 
@@ -556,10 +582,13 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
 
 // explicit instantiations used by api.cpp
 template dp_status solve_block<InitProbe>(dp_ctx *, const OpPrep &, const SolveCfg &, const Launch &, const Red &,
-                                          const CgState &, double *, InitProbe, BlockStats &, dp_solve_stats *);
+                                          const CgState &, double *, InitProbe, BlockStats &, dp_solve_stats *,
+                                          void *);
 template dp_status solve_block<InitAbi>(dp_ctx *, const OpPrep &, const SolveCfg &, const Launch &, const Red &,
-                                        const CgState &, double *, InitAbi, BlockStats &, dp_solve_stats *);
+                                        const CgState &, double *, InitAbi, BlockStats &, dp_solve_stats *,
+                                        void *);
 template dp_status solve_block<InitDeflated>(dp_ctx *, const OpPrep &, const SolveCfg &, const Launch &, const Red &,
-                                        const CgState &, double *, InitDeflated, BlockStats &, dp_solve_stats *);
+                                        const CgState &, double *, InitDeflated, BlockStats &, dp_solve_stats *,
+                                        void *);
 
 }  // namespace dp
