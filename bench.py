@@ -451,7 +451,7 @@ def main():
     # wall time, with reliable updates, checks and contractions inside it but not counted
     cb = {"f64": 16, "f32": 8, "bf16": 4}[inner]
     vw, lk = cb * 3 * config["rhs_block"], cb * 9
-    st_bytes = sum(s_["stencil_bytes"] for s_ in stats)
+    st_bytes = sum(s_["stencil_bytes_all"] for s_ in stats)
     if st_bytes > 0:
         cg_bytes = st_bytes * (10 * vw + 4 * lk) / (2 * vw + 4 * lk)
         out["cg_bandwidth"] = {"alg_bytes": cg_bytes, "achieved": cg_bytes / elapsed / 1e9, "unit": "GB/s",

@@ -190,7 +190,8 @@ typedef struct {
                                resolves about 3 digits: smaller values cost extra
                                iterations, larger ones extra FP64 updates */
     int32_t use_graph;      /* 1: replay the iteration loop from a captured hipGraph */
-    int32_t profile;        /* 1: time every 8th stencil kernel launch with HIP events */
+    int32_t profile;        /* 1: time stencil kernel launches with HIP events (every 8th
+                               below 256 MB of algorithmic traffic per launch, else all) */
 } dp_solve_opts;
 
 typedef struct {
@@ -202,7 +203,8 @@ typedef struct {
     int32_t reliable_updates;/* FP64 reliable updates performed (all blocks) */
     double max_true_resid;   /* max over right-hand sides of |b - A x| / |b| (FP64) */
     int32_t rhs_block;       /* W used */
-    int32_t stencil_launches;/* profile = 1: stencil kernel launches timed (every 8th) */
+    int32_t stencil_launches;/* profile = 1: stencil kernel launches timed (every 8th below
+                                256 MB of algorithmic traffic per launch, else all) */
     double stencil_ms;       /* profile = 1: summed duration of those launches */
     double stencil_bytes;    /* profile = 1: their algorithmic bytes, per lattice site of a
                                 launch 2*W*V + 4*L (read p and write q for the W right-hand
@@ -212,6 +214,8 @@ typedef struct {
                                 ninst > 1) covers every instance: its totals are reported
                                 in the stats of instance 0 only */
     double seconds;          /* wall time of the call */
+    double stencil_bytes_all;/* profile = 1: algorithmic bytes of all the stencil launches,
+                                timed or not (same accounting as stencil_bytes) */
 } dp_solve_stats;
 
 /*

@@ -63,7 +63,7 @@ class SolveStats(ctypes.Structure):
                 ("reliable_updates", ctypes.c_int32), ("max_true_resid", ctypes.c_double),
                 ("rhs_block", ctypes.c_int32), ("stencil_launches", ctypes.c_int32),
                 ("stencil_ms", ctypes.c_double), ("stencil_bytes", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("stencil_bytes_all", ctypes.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

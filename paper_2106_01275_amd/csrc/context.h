@@ -65,6 +65,7 @@ struct dp_ctx {
     double ev_ms = 0;                         // summed durations of the harvested timed launches
     int ev_done = 0;                          // number of those
     unsigned ev_seq = 0;                      // timed-launch candidates so far (sampling)
+    double ev_bytes_all = 0;                  // algorithmic bytes of every profiled launch
     dp_status harvest_events(size_t n);       // reads and recycles the n oldest pending event pairs
     std::map<std::string, int> tuned_w;       // autotuned block widths
     bool tune_loaded = false;
@@ -127,11 +128,13 @@ dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
 // otherwise with null events
 template <typename F>
 dp_status timed_launch(dp_ctx *ctx, bool profile, double bytes, F launch) {
-    // every kEventStride-th launch carries the events: two events per launch
-    // cost host time that a launch-bound solve (a few thousand sites) pays
-    // in full; the sampled launches give the same average
-    constexpr unsigned kEventStride = 8;
-    if (!profile || (ctx->ev_seq++ % kEventStride) != 0) {
+    // launches of less than 256 MB of algorithmic traffic: every 8th carries
+    // the events (two events per launch cost host time that a short,
+    // launch-bound solve pays in full; the sampled launches give the same
+    // average); longer launches are all timed
+    const unsigned stride = bytes < 256e6 ? 8 : 1;
+    if (profile) ctx->ev_bytes_all += bytes;
+    if (!profile || (ctx->ev_seq++ % stride) != 0) {
         launch(hipEvent_t(nullptr), hipEvent_t(nullptr));
         return DP_OK;
     }

@@ -273,7 +273,9 @@ dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
         st->stencil_ms += ctx->ev_ms;
         st->stencil_launches += ctx->ev_done;
         st->stencil_bytes += ctx->ev_bytes;
+        st->stencil_bytes_all += ctx->ev_bytes_all;
     }
+    ctx->ev_bytes_all = 0;
     ctx->ev_ms = 0;
     ctx->ev_done = 0;
     ctx->ev_bytes = 0;

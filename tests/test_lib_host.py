@@ -27,7 +27,7 @@ def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors have the sizes and field offsets of the C structs."""
     src = tmp_path / "sz.c"
     fields = {"dp_probe_spec": ["colors_dev", "seed", "dilute"], "dp_operator": ["m2", "links"],
-              "dp_solve_opts": ["reliable_delta", "profile"], "dp_solve_stats": ["max_true_resid", "stencil_bytes", "seconds"],
+              "dp_solve_opts": ["reliable_delta", "profile"], "dp_solve_stats": ["max_true_resid", "stencil_bytes", "seconds", "stencil_bytes_all"],
               "dp_trace_result": ["per_rhs", "solve"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dp.h"', "int main(void) {"]
     for st, fs in fields.items():
