@@ -190,8 +190,9 @@ typedef struct {
                                resolves about 3 digits: smaller values cost extra
                                iterations, larger ones extra FP64 updates */
     int32_t use_graph;      /* 1: replay the iteration loop from a captured hipGraph */
-    int32_t profile;        /* 1: time stencil kernel launches with HIP events (every 8th
-                               below 256 MB of algorithmic traffic per launch, else all) */
+    int32_t profile;        /* 1: time stencil kernel launches with HIP events (single
+                               instance: every 8th when a launch moves less than 256 MB of
+                               algorithmic traffic, else all; many instances: all) */
 } dp_solve_opts;
 
 typedef struct {
@@ -203,8 +204,7 @@ typedef struct {
     int32_t reliable_updates;/* FP64 reliable updates performed (all blocks) */
     double max_true_resid;   /* max over right-hand sides of |b - A x| / |b| (FP64) */
     int32_t rhs_block;       /* W used */
-    int32_t stencil_launches;/* profile = 1: stencil kernel launches timed (every 8th below
-                                256 MB of algorithmic traffic per launch, else all) */
+    int32_t stencil_launches;/* profile = 1: stencil kernel launches timed (see profile) */
     double stencil_ms;       /* profile = 1: summed duration of those launches */
     double stencil_bytes;    /* profile = 1: their algorithmic bytes, per lattice site of a
                                 launch 2*W*V + 4*L (read p and write q for the W right-hand

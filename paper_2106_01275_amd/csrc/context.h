@@ -126,13 +126,11 @@ dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);
 // the launch attaches to the kernel's own start and stop (finish_profile()
 // later adds their interval and the launch's algorithmic bytes to the stats),
 // otherwise with null events
+// `stride`: only every stride-th launch carries the events (two events per
+// launch cost host time that a short, launch-bound solve pays in full; a
+// regular sample of equal launches gives the same average).
 template <typename F>
-dp_status timed_launch(dp_ctx *ctx, bool profile, double bytes, F launch) {
-    // launches of less than 256 MB of algorithmic traffic: every 8th carries
-    // the events (two events per launch cost host time that a short,
-    // launch-bound solve pays in full; the sampled launches give the same
-    // average); longer launches are all timed
-    const unsigned stride = bytes < 256e6 ? 8 : 1;
+dp_status timed_launch(dp_ctx *ctx, bool profile, double bytes, F launch, unsigned stride = 1) {
     if (profile) ctx->ev_bytes_all += bytes;
     if (!profile || (ctx->ev_seq++ % stride) != 0) {
         launch(hipEvent_t(nullptr), hipEvent_t(nullptr));

@@ -258,13 +258,16 @@ double stencil_alg_bytes(const Lat &lat, int nc, int W, int prec, bool links) {
 }
 
 static dp_status timed_stencil(dp_ctx *ctx, const SolveCfg &cfg, const Launch &L, const StencilArgs &a) {
-    return timed_launch(ctx, cfg.profile != 0, stencil_alg_bytes(L.lat, L.nc, L.W, cfg.inner, a.links),
+    // the launches of one block are equal: below 256 MB of algorithmic
+    // traffic per launch, time every 8th
+    const double bytes = stencil_alg_bytes(L.lat, L.nc, L.W, cfg.inner, a.links);
+    return timed_launch(ctx, cfg.profile != 0, bytes,
                         [&](hipEvent_t e0, hipEvent_t e1) {
                             StencilArgs ta = a;
                             ta.ev0 = e0;
                             ta.ev1 = e1;
                             launch_stencil(L, cfg.inner, ta);
-                        });
+                        }, bytes < 256e6 ? 8u : 1u);
 }
 
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
