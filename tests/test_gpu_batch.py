@@ -122,7 +122,8 @@ def test_uneven_batch_workload_64(ctx):
         ps_.append(w.p)
         Us.append(U)
         cols.append((col, n))
-    res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-8, inner="bf16", rhs_block=32, reliable_delta=0.1))
+    # the benchmark's configuration: W = 32 (414 jobs over 256 slots), the library's BF16 delta
+    res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-8, inner="bf16", rhs_block=32))
     for r in res:
         assert r["solve"]["nconverged"] == r["solve"]["nrhs"] and r["solve"]["max_true_resid"] <= 1e-8
     order = np.argsort([w.volume for w in batch])
