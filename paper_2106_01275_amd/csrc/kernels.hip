@@ -799,8 +799,8 @@ __device__ __forceinline__ void ld_hop(const LS *__restrict__ U8, int site, int 
 // tile's sites are staged in LDS once and shared by the W lanes.  MODE 2
 // (W >= 64): a wavefront covers one site, so the site index is uniform and
 // the links and neighbour indices come through scalar loads; no LDS and no
-// barriers.  MODE 3 (16 <= W < 64 with even x0-slabs) is MODE 1 with two
-// sites per thread (k_stencil_pair_body).  In every mode the vector loads of the site and its eight
+// barriers.  MODES 3 and 4 (16 <= W < 64 with even x0-slabs) are MODE 1
+// with two or four neighbouring sites per thread (k_stencil_group_body).  In every mode the vector loads of the site and its eight
 // neighbours are issued before any arithmetic, so they are in flight
 // together.
 template <typename S, typename LS, int NC, bool LINKS, int MODE>
@@ -877,49 +877,72 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
     block_partials<1>(bk, acc, W, logW, rd, sm);
 }
 
-// MODE 3: MODE 1 with two x0-adjacent sites per thread.  When every XCD's
-// slab has an even number of x0-slices, the slab walk puts the two slices of
-// a pair at consecutive items, so a thread takes items 2i and 2i + 1: sites
-// s and s + V3, each the other's x0 neighbour.  16 site loads instead of 18
-// per pair (16^4, FP32, W = 32: 41.6 instead of 45.1 us).
-template <typename S, typename LS, int NC, bool LINKS>
-__device__ __forceinline__ void k_stencil_pair_body(const Blk &bk, Launch L, typename St<S>::R diag,
-                                                    const S *__restrict__ pin, S *__restrict__ q,
-                                                    const LS *__restrict__ U, const int *__restrict__ nbr, int cg,
-                                                    Red rd) {
+// MODES 3 and 4: MODE 1 with G sites per thread that are each other's
+// neighbours, so the shared neighbours are loaded once.  When every XCD's
+// slab has an even number of x0-slices, the slab walk (x0 fastest) puts the
+// x0-slices of a pair at consecutive items: with G = 2 a thread takes items
+// 2i, 2i + 1, sites s and s + V3 (x0 neighbours): 16 site loads per pair
+// instead of 18.  With two slices per slab and an even D3, items 4i .. 4i + 3
+// are s, s + V3, s + 1, s + V3 + 1 (x0 and x3 neighbours; 4i / 2 is even,
+// so x3 + 1 does not wrap): 28 loads per quad instead of 36.  16^4, FP32,
+// W = 32: 45.1 us (G = 1), 41.6 (G = 2), 40.6 (G = 4).
+template <int G>
+__device__ __forceinline__ int group_nb(int h, int dir) {
+    // the group member that is neighbour dir of member h, or -1
+    if (G == 2) return (h == 0 && dir == 0) ? 1 : (h == 1 && dir == 4) ? 0 : -1;
+    switch (h * 8 + dir) {
+        case 0 * 8 + 0: return 1;
+        case 0 * 8 + 3: return 2;
+        case 1 * 8 + 4: return 0;
+        case 1 * 8 + 3: return 3;
+        case 2 * 8 + 0: return 3;
+        case 2 * 8 + 7: return 0;
+        case 3 * 8 + 4: return 2;
+        case 3 * 8 + 7: return 1;
+        default: return -1;
+    }
+}
+
+template <typename S, typename LS, int NC, bool LINKS, int G>
+__device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, typename St<S>::R diag,
+                                                     const S *__restrict__ pin, S *__restrict__ q,
+                                                     const LS *__restrict__ U, const int *__restrict__ nbr, int cg,
+                                                     Red rd) {
     using R = typename St<S>::R;
-    constexpr int kMaxItems = 2 * (kBlock / 16);
+    constexpr int kMaxItems = G == 2 ? 2 * (kBlock / 16) : 4 * (kBlock / 32);
     __shared__ R su[kMaxItems * 8 * NC * NC * 2];
     __shared__ int snb[kMaxItems * 8];
     __shared__ double sm[kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = tid >> logW;
-    const int items_per_tile = 2 * (kBlock >> logW);
+    const int items_per_tile = G * (kBlock >> logW);
     double acc_pq = 0.0;
     const SiteWalk wk = site_walk(L.lat, bk);
     for (int t = wk.first; t * items_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * items_per_tile;
         stage_hops<LS, R, NC, LINKS>(su, snb, wk, item0, items_per_tile, U, nbr);
-        if (item0 + 2 * sl >= wk.items) continue;
-        const int s0 = walk_site(wk, item0 + 2 * sl), s1 = s0 + wk.V3;
-        R v0r[NC], v0i[NC], v1r[NC], v1i[NC];
-        ld_site<S, NC>(pin, s0, logW, j, v0r, v0i);
-        ld_site<S, NC>(pin, s1, logW, j, v1r, v1i);
+        if (item0 + G * sl >= wk.items) continue;
+        const int s0 = walk_site(wk, item0 + G * sl);
+        R vor[G][NC], voi[G][NC];  // the members' own vectors
+#pragma unroll
+        for (int h = 0; h < G; ++h)
+            ld_site<S, NC>(pin, s0 + (h & 1) * wk.V3 + (h >> 1), logW, j, vor[h], voi[h]);
         R pqs = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int ls = 2 * sl + h;
-            const int site = h ? s1 : s0;
+        for (int h = 0; h < G; ++h) {
+            const int ls = G * sl + h;
+            const int site = s0 + (h & 1) * wk.V3 + (h >> 1);
             R vr[8][NC], vi[8][NC];
 #pragma unroll
             for (int dir = 0; dir < 8; ++dir) {
-                if (h == 0 && dir == 0) {
+                const int m = group_nb<G>(h, dir);
+                if (m >= 0) {
 #pragma unroll
-                    for (int b = 0; b < NC; ++b) { vr[dir][b] = v1r[b]; vi[dir][b] = v1i[b]; }
-                } else if (h == 1 && dir == 4) {
-#pragma unroll
-                    for (int b = 0; b < NC; ++b) { vr[dir][b] = v0r[b]; vi[dir][b] = v0i[b]; }
+                    for (int b = 0; b < NC; ++b) {
+                        vr[dir][b] = vor[m][b];
+                        vi[dir][b] = voi[m][b];
+                    }
                 } else {
                     ld_site<S, NC>(pin, snb[ls * 8 + dir], logW, j, vr[dir], vi[dir]);
                 }
@@ -927,14 +950,17 @@ __device__ __forceinline__ void k_stencil_pair_body(const Blk &bk, Launch L, typ
             R ar[NC], ai[NC];
 #pragma unroll
             for (int a = 0; a < NC; ++a) {
-                ar[a] = diag * (h ? v1r[a] : v0r[a]);
-                ai[a] = diag * (h ? v1i[a] : v0i[a]);
+                ar[a] = diag * vor[h][a];
+                ai[a] = diag * voi[h][a];
             }
 #pragma unroll
             for (int dir = 0; dir < 8; ++dir) {
                 if (!LINKS) {
 #pragma unroll
-                    for (int a = 0; a < NC; ++a) { ar[a] -= vr[dir][a]; ai[a] -= vi[dir][a]; }
+                    for (int a = 0; a < NC; ++a) {
+                        ar[a] -= vr[dir][a];
+                        ai[a] -= vi[dir][a];
+                    }
                     continue;
                 }
                 R u[2 * NC * NC];
@@ -949,7 +975,7 @@ __device__ __forceinline__ void k_stencil_pair_body(const Blk &bk, Launch L, typ
 #pragma unroll
             for (int a = 0; a < NC; ++a) {
                 St<S>::st(qrow, (unsigned)((a << logW) + j), ar[a], ai[a]);
-                pqs = fmaR(h ? v1r[a] : v0r[a], ar[a], fmaR(h ? v1i[a] : v0i[a], ai[a], pqs));
+                pqs = fmaR(vor[h][a], ar[a], fmaR(voi[h][a], ai[a], pqs));
             }
         }
         acc_pq += (double)pqs;
@@ -963,8 +989,8 @@ template <typename S, typename LS, int NC, bool LINKS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ pin,
                                                     S *__restrict__ q, const LS *__restrict__ U,
                                                     const int *__restrict__ nbr, int cg, Red rd) {
-    if constexpr (MODE == 3)
-        k_stencil_pair_body<S, LS, NC, LINKS>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
+    if constexpr (MODE == 3 || MODE == 4)
+        k_stencil_group_body<S, LS, NC, LINKS, MODE == 3 ? 2 : 4>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
     else
         k_stencil_body<S, LS, NC, LINKS, MODE>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
 }
@@ -1694,11 +1720,15 @@ static void stencil_nc(const Launch &L, const StencilArgs &a) {
                               (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd);                                 \
     else                                                                                                \
         k_stencil<S, LS, NC, LINKS, M><<<grid, blk, 0, L.stream>>>(L, (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd)
-    // pairs: x0-slabs of an even number of slices (the slab walk of site_walk)
-    const bool pairs = !std::is_same<S, bf16x2>::value && L.nblk >= 8 && L.nblk % 8 == 0 &&
-                       L.lat.D[0] % 16 == 0;
+    // groups: x0-slabs of an even number of slices (the slab walk of
+    // site_walk); quads: slabs of two slices, D3 even, W >= 32 (LDS)
+    const bool slabs = !std::is_same<S, bf16x2>::value && L.nblk >= 8 && L.nblk % 8 == 0;
+    const bool pairs = slabs && L.lat.D[0] % 16 == 0;
+    const bool quads = slabs && L.lat.D[0] == 16 && L.lat.D[3] % 2 == 0 && L.W >= 32;
     if (L.W >= 64)
         DP_ST(2);
+    else if (quads)
+        DP_ST(4);
     else if (L.W >= 16 && pairs)
         DP_ST(3);
     else if (L.W >= 16)
