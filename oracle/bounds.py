@@ -7,7 +7,7 @@ Everything here is plain Python over explicit point sets:
     and Thm. oddC (eqs. cond:2, cond:3) on Z^d, by enumeration;
   * col_lower_bound is eq. (pBounds) (Sec. 3.2), with |C(d, alpha, beta)|
     counted from the set definition (not from the recursive listing, whose
-    d == 1 branch omits the 2p term; see DESIGN.md readings);
+    d == 1 branch omits the 2p term and gives 9 instead of 37 for (2, 4));
   * p0_lower_bound is eq. (7) for p = 0;
   * tile_shape is the tile policy of Sec. 3.5.
 """

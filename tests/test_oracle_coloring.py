@@ -293,7 +293,8 @@ def test_tile_policy_table():
 # cells of Table ActualCols whose colour count the oracle's greedy colouring
 # reproduces exactly under the reading (index order with dimension 0 slowest,
 # red-black = even coordinate sum first, BEST = fewer colours, ties natural);
-# the k <= 4 cells (p=1,k=3), (p=1,k=4), (p=2,k=4) differ, see the design doc.
+# the k <= 4 cells (p=1,k=3): 56 vs 32, (p=1,k=4): 56 vs 64 and (p=2,k=4): 88 vs 92
+# differ (the printed counts depend on an index order the paper does not state).
 REPRODUCED = [(p, k) for k in (1, 2, 3) for p in range(9) if (p, k) != (1, 3)] + \
              [(0, 4), (3, 4), (4, 4), (8, 4)]
 
