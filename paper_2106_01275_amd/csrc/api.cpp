@@ -416,21 +416,39 @@ static void combine(const dp_probe_spec &ps, const std::vector<double> &tj, dp_t
 
 // The probes of ps solved once; every solution contracted with each of the
 // ndisp displacements (any sign).  outs[n] gets the estimate for disp[n].
-// Pinned staging of one call's per-block results: every block's state (for
+// Pinned staging of a call's per-block results: every block's states (for
 // its statistics) and its contractions are copied there in stream order and
-// read once after the call's final synchronisation, so consecutive blocks
-// follow each other on the device without a host round trip.
+// read after a synchronisation once per kChunk blocks (and at the end), so
+// consecutive blocks follow each other on the device without a host round
+// trip while the staging stays small.
 struct Staging {
+    static constexpr long long kChunk = 256;
     char *base = nullptr;
-    size_t sb = 0;
-    long long nblocks = 0;
-    dp_status init(dp_ctx *ctx, long long nblk, size_t result_doubles) {
+    size_t sb = 0, per_block = 0;
+    int states = 1;
+    long long chunk = 1;
+    std::vector<BlockStats> bss;  // host-side counts (reliable updates) of the chunk's solves
+    dp_status init(dp_ctx *ctx, long long nblocks, int states_per_block, size_t result_doubles_per_block) {
         sb = (state_bytes() + 255) / 256 * 256;
-        nblocks = nblk;
-        return ctx->host_pinned((size_t)nblk * sb + result_doubles * sizeof(double), (void **)&base);
+        states = states_per_block;
+        per_block = result_doubles_per_block;
+        chunk = std::max(1LL, std::min(nblocks, kChunk));
+        bss.assign((size_t)chunk * states, BlockStats());
+        return ctx->host_pinned((size_t)chunk * (states * sb + per_block * sizeof(double)), (void **)&base);
     }
-    void *state(long long k) const { return base + (size_t)k * sb; }
-    double *results() const { return (double *)(base + (size_t)nblocks * sb); }
+    void *state(long long k, int i = 0) const { return base + ((size_t)(k % chunk) * states + i) * sb; }
+    BlockStats &stats(long long k, int i, int nvalid) {
+        BlockStats &b = bss[(size_t)(k % chunk) * states + i];
+        if (nvalid >= 0) {
+            b = BlockStats();
+            b.nvalid = nvalid;
+        }
+        return b;
+    }
+    double *result(long long k) const {
+        return (double *)(base + (size_t)chunk * states * sb) + (size_t)(k % chunk) * per_block;
+    }
+    bool drain_after(long long k, long long nblocks) const { return k % chunk == chunk - 1 || k == nblocks - 1; }
 };
 
 static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const int32_t *disp, int ndisp,
@@ -452,28 +470,33 @@ static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const 
     s.rhs_block = W;
     const long long nblocks = (nrhs + W - 1) / W;
     Staging stg;
-    DP_TRY(stg.init(ctx, nblocks, (size_t)ndisp * 2 * nrhs));
-    std::vector<BlockStats> bss(nblocks);
+    DP_TRY(stg.init(ctx, nblocks, 1, (size_t)ndisp * 2 * W));
+    std::vector<std::vector<double>> tj(ndisp, std::vector<double>(2 * nrhs, 0.0));
+    long long k0 = 0;  // first block not yet drained
     for (long long k = 0; k < nblocks; ++k) {
         const long long r0 = k * W, nv = std::min<long long>(W, nrhs - r0);
-        bss[k].nvalid = (int)nv;
+        BlockStats &bs = stg.stats(k, 0, (int)nv);
         InitProbe init{&L, cfg.inner, make_gen(ps, r0, nv, 0), &rd, &cs, ctx};
         double *x64 = (double *)ctx->at(kSlotX64);
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bss[k], &s, stg.state(k)));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s, stg.state(k)));
         for (int n = 0; n < ndisp; ++n) {
             // each contraction reads x only at the probe's sites shifted by disp[n]
             launch_displaced_dot(L, make_gen(ps, r0, nv, 0), disp[n], x64, rd, cs);
             DP_HIP(hipGetLastError());
-            DP_HIP(hipMemcpyAsync(stg.results() + (size_t)n * 2 * nrhs + 2 * r0, cs.tj, 2 * nv * sizeof(double),
+            DP_HIP(hipMemcpyAsync(stg.result(k) + (size_t)n * 2 * W, cs.tj, 2 * nv * sizeof(double),
                                   hipMemcpyDeviceToHost, stream));
         }
+        if (stg.drain_after(k, nblocks)) {
+            DP_HIP(hipStreamSynchronize(stream));
+            for (; k0 <= k; ++k0) {
+                const long long b0 = k0 * W, bn = std::min<long long>(W, nrhs - b0);
+                block_stats(stg.state(k0), stg.stats(k0, 0, -1), &s);
+                for (int n = 0; n < ndisp; ++n)
+                    std::memcpy(tj[n].data() + 2 * b0, stg.result(k0) + (size_t)n * 2 * W, 2 * bn * sizeof(double));
+            }
+        }
     }
-    DP_HIP(hipStreamSynchronize(stream));
     DP_TRY(finish_profile(ctx, &s));
-    for (long long k = 0; k < nblocks; ++k) block_stats(stg.state(k), bss[k], &s);
-    std::vector<std::vector<double>> tj(ndisp);
-    for (int n = 0; n < ndisp; ++n)
-        tj[n].assign(stg.results() + (size_t)n * 2 * nrhs, stg.results() + (size_t)(n + 1) * 2 * nrhs);
     s.seconds = now_s() - t0;
     for (int n = 0; n < ndisp; ++n) {
         combine(ps, tj[n], outs[n]);
@@ -623,28 +646,35 @@ dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *opd, int32_t p, const dp
     s.rhs_block = W;
     const long long nblocks = (nrhs + W - 1) / W;
     Staging stg;
-    DP_TRY(stg.init(ctx, 2 * nblocks, 4 * (size_t)nrhs));
-    double *tjh = stg.results(), *lxh = stg.results() + 2 * nrhs;
-    std::vector<BlockStats> bss(2 * nblocks);
+    DP_TRY(stg.init(ctx, nblocks, 2, 4 * (size_t)W));
+    std::vector<double> tj(2 * nrhs, 0.0), lx(2 * nrhs, 0.0);
+    long long k0 = 0;  // first block not yet drained
     for (long long k = 0; k < nblocks; ++k) {
         const long long r0 = k * W, nv = std::min<long long>(W, nrhs - r0);
-        bss[2 * k].nvalid = bss[2 * k + 1].nvalid = (int)nv;
+        BlockStats &bs1 = stg.stats(k, 0, (int)nv), &bs2 = stg.stats(k, 1, (int)nv);
         InitProbe ix{&L, cfg.inner, make_gen(*ps, r0, nv, 0), &rd, &cs, ctx};
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, xsol, ix, bss[2 * k], &s, stg.state(2 * k)));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, xsol, ix, bs1, &s, stg.state(k, 0)));
         launch_displaced_dot(L, make_gen(*ps, r0, nv, 0), p, xsol, rd, cs);
-        DP_HIP(hipMemcpyAsync(tjh + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        DP_HIP(hipMemcpyAsync(stg.result(k), cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
         InitProbe il{&L, cfg.inner, make_gen(*ps, r0, nv, p), &rd, &cs, ctx};
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, lsol, il, bss[2 * k + 1], &s, stg.state(2 * k + 1)));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, lsol, il, bs2, &s, stg.state(k, 1)));
         launch_dot(L, lsol, xsol, rd, cs);
-        DP_HIP(hipMemcpyAsync(lxh + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        DP_HIP(hipMemcpyAsync(stg.result(k) + 2 * W, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost,
+                              stream));
         if (dT_dU || dT_dUbar)
             launch_force(L, xsol, lsol, op.nbr, norm, r0 == 0, (double *)dT_dU, (double *)dT_dUbar);
         DP_HIP(hipGetLastError());
+        if (stg.drain_after(k, nblocks)) {
+            DP_HIP(hipStreamSynchronize(stream));
+            for (; k0 <= k; ++k0) {
+                const long long b0 = k0 * W, bn = std::min<long long>(W, nrhs - b0);
+                for (int i = 0; i < 2; ++i) block_stats(stg.state(k0, i), stg.stats(k0, i, -1), &s);
+                std::memcpy(tj.data() + 2 * b0, stg.result(k0), 2 * bn * sizeof(double));
+                std::memcpy(lx.data() + 2 * b0, stg.result(k0) + 2 * W, 2 * bn * sizeof(double));
+            }
+        }
     }
-    DP_HIP(hipStreamSynchronize(stream));
     DP_TRY(finish_profile(ctx, &s));
-    for (long long k = 0; k < 2 * nblocks; ++k) block_stats(stg.state(k), bss[k], &s);
-    std::vector<double> tj(tjh, tjh + 2 * nrhs), lx(lxh, lxh + 2 * nrhs);
     double Tr = 0, Ti = 0, gr = 0, gi = 0;
     for (long long j = 0; j < nrhs; ++j) {
         Tr += tj[2 * j];
@@ -799,25 +829,30 @@ dp_status dp_trace_deflated(dp_ctx *ctx, const dp_operator *opd, const dp_deflat
     s.rhs_block = W;
     const long long nblocks = (nrhs + W - 1) / W;
     Staging stg;
-    DP_TRY(stg.init(ctx, nblocks, 2 * (size_t)nrhs));
-    std::vector<BlockStats> bss(nblocks);
+    DP_TRY(stg.init(ctx, nblocks, 1, 2 * (size_t)W));
+    std::vector<double> tj(2 * nrhs, 0.0);
     dp_status proj = DP_OK;
+    long long k0 = 0;  // first block not yet drained
     for (long long k = 0; k < nblocks; ++k) {
         const long long r0 = k * W, nv = std::min<long long>(W, nrhs - r0);
-        bss[k].nvalid = (int)nv;
+        BlockStats &bs = stg.stats(k, 0, (int)nv);
         InitDeflated init{&L, cfg.inner, make_gen(*ps, r0, nv, 0), &rd, &cs, ctx, d, &proj};
         double *x64 = (double *)ctx->at(kSlotX64);
-        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bss[k], &s, stg.state(k)));
+        DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s, stg.state(k)));
         DP_TRY(proj);
         launch_displaced_dot(L, make_gen(*ps, r0, nv, 0), p, x64, rd, cs);
         DP_HIP(hipGetLastError());
-        DP_HIP(hipMemcpyAsync(stg.results() + 2 * r0, cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost,
-                              stream));
+        DP_HIP(hipMemcpyAsync(stg.result(k), cs.tj, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, stream));
+        if (stg.drain_after(k, nblocks)) {
+            DP_HIP(hipStreamSynchronize(stream));
+            for (; k0 <= k; ++k0) {
+                const long long b0 = k0 * W, bn = std::min<long long>(W, nrhs - b0);
+                block_stats(stg.state(k0), stg.stats(k0, 0, -1), &s);
+                std::memcpy(tj.data() + 2 * b0, stg.result(k0), 2 * bn * sizeof(double));
+            }
+        }
     }
-    DP_HIP(hipStreamSynchronize(stream));
     DP_TRY(finish_profile(ctx, &s));
-    for (long long k = 0; k < nblocks; ++k) block_stats(stg.state(k), bss[k], &s);
-    std::vector<double> tj(stg.results(), stg.results() + 2 * nrhs);
     s.seconds = now_s() - t0;
     combine(*ps, tj, *out);
     out->tr[0] += td[0];
