@@ -284,6 +284,22 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
     __shared__ double sm[NV * kWaves];
     const int tid = threadIdx.x;
     const double *src = rd.part1 + (size_t)lane * rd.nblk * NV;
+    const int j = lane;
+    // the lane's state that the epilogue reads, loaded before the partials
+    // so that the two loads' latencies overlap (only this workgroup's
+    // thread 0 reads or writes lane j's state)
+    constexpr bool kState = EPI == kEpiAlpha || EPI == kEpiBeta || EPI == kEpiRU;
+    double st_rr = 0.0, st_prev = 0.0, st_ref = 0.0, st_bb = 0.0;
+    int st_active = 0, st_flags = 0, st_iters = 0;
+    if (kState && tid == 0) {
+        st_rr = cs.rr[j];
+        st_prev = cs.rr_prev[j];
+        st_ref = cs.rr_ref[j];
+        st_bb = cs.bb[j];
+        st_active = cs.active[j];
+        st_flags = cs.flags[j];
+        st_iters = cs.iters[j];
+    }
     // thread tid adds partials tid, tid + kBlock, ... (four loads in flight),
     // then a fixed butterfly in each wavefront and the wavefronts in order:
     // the same summation order on every call
@@ -318,7 +334,6 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
         tot[v] = 0.0;
         for (int w = 0; w < kWaves; ++w) tot[v] += sm[v * kWaves + w];
     }
-    const int j = lane;
     const double t = tot[0];
     if (EPI == kEpiInit) {
         cs.bb[j] = t;
@@ -332,53 +347,53 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
         cs.active[j] = t > 0.0;
         cs.flags[j] = t > 0.0 ? 0 : kFlagConverged;
     } else if (EPI == kEpiAlpha) {
-        if (cs.active[j] && !(cs.flags[j] & kFlagHold)) {
+        double alpha = 0.0;
+        if (st_active && !(st_flags & kFlagHold)) {
             if (!(t > 0.0) || !isfinite(t)) {
-                cs.alpha[j] = 0.0;
                 if (cs.exact) {
-                    cs.flags[j] |= kFlagBreakdown;
+                    cs.flags[j] = st_flags | kFlagBreakdown;
                     cs.active[j] = 0;
                 } else {
-                    cs.flags[j] |= kFlagRestart | (cs.hold ? kFlagHold : 0);
+                    cs.flags[j] = st_flags | kFlagRestart | (cs.hold ? kFlagHold : 0);
                 }
             } else {
-                cs.alpha[j] = cs.rr[j] / t;
+                alpha = st_rr / t;
             }
-        } else {
-            cs.alpha[j] = 0.0;
         }
+        cs.alpha[j] = alpha;
     } else if (EPI == kEpiBeta) {
-        if (cs.active[j] && !(cs.flags[j] & kFlagHold)) {
-            cs.iters[j] += 1;
-            cs.rr_prev[j] = cs.rr[j];
-            cs.beta[j] = t / cs.rr[j];
+        if (st_active && !(st_flags & kFlagHold)) {
+            cs.iters[j] = st_iters + 1;
+            cs.rr_prev[j] = st_rr;
+            cs.beta[j] = t / st_rr;
             cs.rr[j] = t;
             if (cs.exact) {
-                if (t <= cs.tol2 * cs.bb[j]) {
+                if (t <= cs.tol2 * st_bb) {
                     cs.active[j] = 0;
-                    cs.flags[j] |= kFlagConverged;
+                    cs.flags[j] = st_flags | kFlagConverged;
                 }
-            } else if (cs.hold && !(t >= cs.delta2 * cs.rr_ref[j])) {
-                cs.flags[j] |= kFlagHold;  // due a reliable update (or not finite)
+            } else if (cs.hold && !(t >= cs.delta2 * st_ref)) {
+                cs.flags[j] = st_flags | kFlagHold;  // due a reliable update (or not finite)
             }
-        } else if (!cs.active[j]) {
+        } else if (!st_active) {
             cs.beta[j] = 0.0;
         }
     } else if (EPI == kEpiRU || EPI == kEpiStats) {
         cs.true_rr[j] = t;
         cs.alpha[j] = 0.0;  // the fold before applied the deferred solution update
-        if (EPI == kEpiRU && cs.active[j]) {
+        if (EPI == kEpiRU && st_active) {
             // restart the direction (beta = 0) after a low-precision
             // breakdown or when the true residual grew since the last update
-            const bool restart = (cs.flags[j] & kFlagRestart) || !(t <= cs.rr_ref[j]);
-            cs.beta[j] = restart ? 0.0 : t / cs.rr_prev[j];
-            cs.flags[j] &= ~(kFlagRestart | kFlagHold);
+            const bool restart = (st_flags & kFlagRestart) || !(t <= st_ref);
+            cs.beta[j] = restart ? 0.0 : t / st_prev;
+            int flags = st_flags & ~(kFlagRestart | kFlagHold);
             cs.rr[j] = t;
             cs.rr_ref[j] = t;
-            if (t <= cs.tol2 * cs.bb[j]) {
+            if (t <= cs.tol2 * st_bb) {
                 cs.active[j] = 0;
-                cs.flags[j] |= kFlagConverged;
+                flags |= kFlagConverged;
             }
+            cs.flags[j] = flags;
         }
     } else {
         cs.tj[2 * j] = tot[0];
