@@ -343,7 +343,8 @@ dp_status dp_deflation_info(const dp_deflation *d, double *evals, double *resid,
                             int32_t *subspace);
 
 /*   out    device complex128 [nvec][N][nc], caller-owned, written (the Ritz
- *          vectors in the ABI layout). */
+ *          vectors in the ABI layout).
+ * DP_EINVAL when d lives on another device than ctx. */
 dp_status dp_deflation_vectors(dp_ctx *ctx, const dp_deflation *d, void *out, hipStream_t stream);
 
 /*
@@ -353,7 +354,10 @@ dp_status dp_deflation_vectors(dp_ctx *ctx, const dp_deflation *d, void *out, hi
  *     T_s = tr_defl + norm * sum_{j in sample s} t_j,   T = mean over samples.
  *   tr_defl  host double[2] (may be NULL): Tr(P A^{-1} Q), written.
  * out.per_sample holds the T_s (each an unbiased estimate of the whole
- * trace), out.per_rhs the t_j. Single instance, p >= 0. */
+ * trace), out.per_rhs the t_j. Single instance, p >= 0.  DP_EINVAL when d
+ * was built for an operator of other dims, nc, m2 or link presence (its
+ * link values are not compared: passing other links gives a wrong split),
+ * or lives on another device than ctx. */
 dp_status dp_trace_deflated(dp_ctx *ctx, const dp_operator *op, const dp_deflation *d, int32_t p,
                             const dp_probe_spec *ps, const dp_solve_opts *o, dp_trace_result *out,
                             double tr_defl[2], hipStream_t stream);

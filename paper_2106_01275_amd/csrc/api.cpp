@@ -776,6 +776,10 @@ dp_status dp_deflation_vectors(dp_ctx *ctx, const dp_deflation *d, void *out, hi
         ctx->err = "deflation_vectors: bad arguments";
         return DP_EINVAL;
     }
+    if (d->device != ctx->device) {
+        ctx->err = "deflation_vectors: the deflation lives on another device than the context";
+        return DP_EINVAL;
+    }
     return deflation_vectors(ctx, *d, (double *)out, stream);
 }
 
@@ -800,6 +804,10 @@ dp_status dp_trace_deflated(dp_ctx *ctx, const dp_operator *opd, const dp_deflat
     for (int k = 0; k < 4; ++k) same = same && opd->dims[k] == d->lat.D[k];
     if (!same) {
         ctx->err = "trace_deflated: the deflation was built for another operator";
+        return DP_EINVAL;
+    }
+    if (d->device != ctx->device) {
+        ctx->err = "trace_deflated: the deflation lives on another device than the context";
         return DP_EINVAL;
     }
     const double t0 = now_s();
