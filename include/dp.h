@@ -182,7 +182,8 @@ typedef struct {
     int32_t inner;          /* DP_PREC_*: storage of the inner CG vectors and links;
                                F32 and BF16 accumulate in FP32 and are refined by
                                FP64 reliable updates */
-    int32_t rhs_block;      /* right-hand sides solved together (W); 0 = autotune */
+    int32_t rhs_block;      /* right-hand sides solved together (W): 0 = autotune,
+                               else a power of two <= 256 (DP_EINVAL otherwise) */
     double reliable_delta;  /* mixed precision: replace the residual by the FP64
                                true residual once it dropped by this factor; a lane
                                that reaches it waits for that update before it moves

@@ -529,8 +529,8 @@ static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, 
 
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
                        hipStream_t s, int &W, const std::vector<std::pair<long long, long long>> *work) {
-    if (requested > 0) {
-        if (requested > kMaxW || (requested & (requested - 1))) {
+    if (requested != 0) {
+        if (requested < 0 || requested > kMaxW || (requested & (requested - 1))) {
             ctx->err = "rhs_block must be a power of two <= 256";
             return DP_EINVAL;
         }

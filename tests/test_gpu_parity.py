@@ -94,7 +94,8 @@ def test_apply_matches_oracle(ctx, prec, rtol, dims, nc, links, nrhs):
 
 
 @pytest.mark.parametrize("dims,nc,nrhs,block", [((4, 4, 4, 4), 3, 5, 0), ((6, 4, 5, 3), 3, 33, 16),
-                                                ((4, 4, 4, 4), 1, 1, 1), ((3, 5, 4, 4), 3, 70, 64)])
+                                                ((4, 4, 4, 4), 1, 1, 1), ((3, 5, 4, 4), 3, 70, 64),
+                                                ((8, 8, 8, 8), 3, 300, 256)])
 def test_solve_batch_fp64_matches_oracle(ctx, dims, nc, nrhs, block):
     _say("solve f64", dims, nc, nrhs, block)
     N = int(np.prod(dims))
@@ -110,7 +111,8 @@ def test_solve_batch_fp64_matches_oracle(ctx, dims, nc, nrhs, block):
     assert abs(st["max_iters"] - it.max()) <= 2
 
 
-@pytest.mark.parametrize("inner,block", [("f32", 32), ("f32", 64), ("bf16", 64), ("f32", 128)])
+@pytest.mark.parametrize("inner,block", [("f32", 32), ("f32", 64), ("bf16", 64), ("f32", 128), ("f32", 256),
+                                         ("bf16", 256)])
 def test_solve_batch_mixed_matches_oracle(ctx, inner, block):
     _say("solve mixed", inner, block)
     dims, nc, nrhs = (6, 4, 5, 4), 3, 70
@@ -153,9 +155,10 @@ def test_solve_failure_statuses(ctx):
     with pytest.raises(dp.DPError) as e:
         ctx.solve_batch([bad], [B], ctx.opts(tol=1e-12))
     assert e.value.status == dp.EBREAKDOWN
-    with pytest.raises(dp.DPError) as e:
-        ctx.solve_batch([op], [B], ctx.opts(tol=1e-12, rhs_block=3))
-    assert e.value.status == dp.EINVAL
+    for w in (3, 512, -4):  # not a power of two, above the largest width 256, negative
+        with pytest.raises(dp.DPError) as e:
+            ctx.solve_batch([op], [B], ctx.opts(tol=1e-12, rhs_block=w))
+        assert e.value.status == dp.EINVAL
     with pytest.raises(dp.DPError) as e:
         ctx.solve_batch([ctx.operator((4, 4, 0, 4), 1, 0.5, None)], [B], ctx.opts(tol=1e-12))
     assert e.value.status == dp.EINVAL
