@@ -260,9 +260,9 @@ def run_gauge16(a, torch, dp, workloads):
 def run_uneven(a, torch, dp, workloads):
     inst = workloads.uneven_batch()
     inner = a.inner or "bf16"
-    # W = 32: measured best for this batch (W = 16/32/64/128: 133/123/141/159 ms per step); the
-    # autotuner's single-instance timing prefers 128
-    W_req = 32 if a.rhs_block is None else a.rhs_block
+    # the width from the autotuner (rhs_block 0): 32 for this batch, the measured best
+    # (W = 16/32/64/128: 133/123/141/159 ms per step)
+    W_req = 0 if a.rhs_block is None else a.rhs_block
     steps = a.steps or 3
     c = dp.context(0)
     t0 = time.time()

@@ -118,7 +118,8 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
 size_t state_bytes();
 void block_stats(const void *state, BlockStats &bs, dp_solve_stats *acc);
 // For a batch, `work` lists (right-hand sides, sites) of every instance: the
-// cost of a width then counts the padded lanes of each instance's last job.
+// width then comes from the traffic per lane-site of a CG iteration times the
+// padded lanes of each instance's last block (no timing).
 dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long long nrhs, int requested,
                        hipStream_t s, int &W, const std::vector<std::pair<long long, long long>> *work = nullptr);
 dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st);

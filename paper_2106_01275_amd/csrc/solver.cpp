@@ -541,10 +541,45 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
         W = 1;
         return DP_OK;
     }
+    if (work) {
+        // Many instances in one launch: the slots keep thousands of lanes in
+        // flight at every width, so a width costs what its CG iteration moves
+        // per lane-site, 10 vector passes plus the eight hop links of a site
+        // shared by the W lanes, times the padding of every instance's last
+        // block (sum ceil(n_i/W) W N_i / sum n_i N_i).  Timing one instance
+        // alone instead rewards wide blocks that fill the GPU by themselves
+        // (64 uneven lattices: this ranks W = 16/32/64/128 as the measured
+        // 133/123/141/159 ms per step; the timed single instance picked 128).
+        // Widths below 16 (per-lane link loads) only when no instance has
+        // more right-hand sides.
+        const double c = (double)prec_bytes(cfg.inner);
+        double useful = 0;
+        long long most = 1;
+        for (auto &nw : *work) {
+            useful += (double)nw.first * nw.second;
+            most = std::max(most, nw.first);
+        }
+        int wmax = 1;
+        while (wmax < most && wmax < 128) wmax *= 2;
+        double best = 1e300;
+        int best_w = wmax;
+        for (int w = std::min(16, wmax); w <= wmax; w *= 2) {
+            double padded = 0;
+            for (auto &nw : *work) padded += (double)((nw.first + w - 1) / w) * w * nw.second;
+            const double per_site = 10.0 * op.nc * c + (op.links ? 8.0 * op.nc * op.nc * c / w : 0.0);
+            const double cost = (useful > 0 ? padded / useful : 1.0) * per_site;
+            if (cost < best * (1 - 1e-9)) {
+                best = cost;
+                best_w = w;
+            }
+        }
+        W = best_w;
+        return DP_OK;
+    }
     load_tune_file(ctx);
     const std::string key = tune_key(op, cfg, nrhs);
     auto it = ctx->tuned_w.find(key);
-    if (!work && it != ctx->tuned_w.end()) {
+    if (it != ctx->tuned_w.end()) {
         W = it->second;
         return DP_OK;
     }
@@ -556,31 +591,16 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
         if (w > 8 && w / 2 >= nrhs) break;
         if (bytes_per_w * w > ((size_t)32 << 30)) break;
         float ms = 0;
-        const std::string tkey = key + " W=" + std::to_string(w) + " ns";
-        auto t = ctx->tuned_w.find(tkey);
-        if (work && t != ctx->tuned_w.end()) {
-            ms = (float)(t->second * 1e-6);
-        } else {
-            DP_TRY(time_width(ctx, op, cfg, w, s, ms));
-            if (work) ctx->tuned_w[tkey] = (int)std::min(2e9, ms * 1e6);
-            timed = true;
-        }
-        double cost = ms / (double)std::min<long long>(w, nrhs);
-        if (work) {
-            double padded = 0, useful = 0;
-            for (auto &nw : *work) {
-                padded += (double)((nw.first + w - 1) / w) * w * nw.second;
-                useful += (double)nw.first * nw.second;
-            }
-            cost = ms / (double)w * (useful > 0 ? padded / useful : 1.0);
-        }
+        DP_TRY(time_width(ctx, op, cfg, w, s, ms));
+        timed = true;
+        const double cost = ms / (double)std::min<long long>(w, nrhs);
         if (cost < best) {
             best = cost;
             best_w = w;
         }
     }
     W = best_w;
-    if (!work) ctx->tuned_w[key] = W;
+    ctx->tuned_w[key] = W;
     if (timed) save_tune_file(ctx);
     return DP_OK;
 }

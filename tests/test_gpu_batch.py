@@ -132,3 +132,33 @@ def test_uneven_batch_workload_64(ctx):
         col, n = cols[i]
         o = oracle.trace(w.dims, 3, w.m2, Us[i], w.p, col, n, i, 0, 1, oracle.Z2_COMPLEX, True, tol=1e-11)
         assert abs(res[i]["T"] - o["T"]) < 1e-5 * abs(o["T"]), (i, res[i]["T"], o["T"])
+
+
+def test_autotuned_batch_width(ctx):
+    """rhs_block = 0 on a batch: the width minimises the traffic of a CG
+    iteration per useful lane-site, 10 vector passes plus the eight hop links
+    of a site shared by the W lanes, times the padding of every instance's
+    last block, over W = 16..128 (not above the next power of two of the
+    largest right-hand-side count).  The estimates equal those at that width
+    given explicitly."""
+    _say("batch autotuned width")
+    ops, pss, ps_, Us, cols = _instances(ctx, SMALL)
+    res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-10, inner="bf16", rhs_block=0))
+    W = res[0]["solve"]["rhs_block"]
+    work = [(3 * n, int(np.prod(inst[0]))) for inst, (_, n, _) in zip(SMALL, cols)]
+    useful = sum(r * s for r, s in work)
+    most = max(r for r, _ in work)
+    wmax = 1
+    while wmax < most and wmax < 128:
+        wmax *= 2
+    costs = {}
+    w = min(16, wmax)
+    while w <= wmax:
+        padded = sum(-(-r // w) * w * s for r, s in work)
+        costs[w] = padded / useful * (10 * 3 * 4 + 8 * 9 * 4 / w)
+        w *= 2
+    assert W == min(costs, key=lambda k: (costs[k], k)), (W, costs)
+    assert all(r["solve"]["rhs_block"] == W for r in res)
+    fixed = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-10, inner="bf16", rhs_block=W))
+    for a, b in zip(res, fixed):
+        assert a["T"] == b["T"]
