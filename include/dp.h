@@ -182,8 +182,12 @@ typedef struct {
     int32_t inner;          /* DP_PREC_*: storage of the inner CG vectors and links;
                                F32 and BF16 accumulate in FP32 and are refined by
                                FP64 reliable updates */
-    int32_t rhs_block;      /* right-hand sides solved together (W): 0 = autotune,
-                               else a power of two <= 256 (DP_EINVAL otherwise) */
+    int32_t rhs_block;      /* right-hand sides solved together (W): 0 = autotune
+                               (one instance: a few timed CG iterations per width,
+                               cached, DP_TUNE_CACHE names a file; several: the
+                               least traffic per useful lane-site, padding of each
+                               instance's last block included), else a power of
+                               two <= 256 (DP_EINVAL otherwise) */
     double reliable_delta;  /* mixed precision: replace the residual by the FP64
                                true residual once it dropped by this factor; a lane
                                that reaches it waits for that update before it moves
