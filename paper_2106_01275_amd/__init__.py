@@ -254,10 +254,15 @@ class Context:
     def _err(self, st, result=None):
         raise DPError(st, lib().dp_last_error(self.h).decode(), result)
 
-    def _cdev(self, t, dtype):
+    def _cdev(self, t, dtype, numel=None):
+        # the kernels trust the sizes: check them here, on the host
         torch = self.torch
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
             raise TypeError(f"expected a contiguous {dtype} tensor on the GPU")
+        if (t.device.index or 0) != self.device:
+            raise ValueError(f"tensor on cuda:{t.device.index}, context on cuda:{self.device}")
+        if numel is not None and t.numel() != numel:
+            raise ValueError(f"expected {numel} elements, got {t.numel()} (shape {tuple(t.shape)})")
         return ctypes.c_void_p(t.data_ptr())
 
     def operator(self, dims, nc, m2, links=None):
@@ -266,7 +271,8 @@ class Context:
         op.dims[:] = _dims4(dims)
         op.nc = nc
         op.m2 = float(m2)
-        op.links = None if links is None else self._cdev(links, self.torch.complex128).value
+        N = int(np.prod(list(op.dims)))
+        op.links = None if links is None else self._cdev(links, self.torch.complex128, 4 * N * nc * nc).value
         op._keep = links
         return op
 
@@ -274,7 +280,7 @@ class Context:
         ps = ProbeSpec()
         ps.dims[:] = _dims4(dims)
         ps.nc = nc
-        ps.colors_dev = self._cdev(colors_dev, self.torch.int32).value
+        ps.colors_dev = self._cdev(colors_dev, self.torch.int32, int(np.prod(list(ps.dims)))).value
         ps.ncolors = int(ncolors)
         ps.seed = int(seed)
         ps.sample0 = int(sample0)
@@ -302,8 +308,8 @@ class Context:
         N = int(np.prod(list(ps.dims)))
         if out is None:
             out = torch.empty((nrhs, N, ps.nc), dtype=torch.complex128, device=f"cuda:{self.device}")
-        st = lib().dp_make_probes(self.h, ctypes.byref(ps), rhs0, nrhs, self._cdev(out, torch.complex128),
-                                  self._stream())
+        st = lib().dp_make_probes(self.h, ctypes.byref(ps), rhs0, nrhs,
+                                  self._cdev(out, torch.complex128, nrhs * N * ps.nc), self._stream())
         if st != OK:
             self._err(st)
         return out
@@ -315,8 +321,13 @@ class Context:
         if xs is None:
             xs = [torch.empty_like(b) for b in bs]
         arr_ops = (Operator * n)(*ops)
-        pb = (ctypes.c_void_p * n)(*[self._cdev(b, torch.complex128).value for b in bs])
-        px = (ctypes.c_void_p * n)(*[self._cdev(x, torch.complex128).value for x in xs])
+        if len(bs) != n or len(xs) != n:
+            raise ValueError("one right-hand-side and one solution tensor per operator")
+        # (an operator with a dimension < 1 is left to the library, which rejects it)
+        sizes = [b.shape[0] * int(np.prod(list(op.dims))) * op.nc if min(op.dims) >= 1 else None
+                 for b, op in zip(bs, ops)]
+        pb = (ctypes.c_void_p * n)(*[self._cdev(b, torch.complex128, m).value for b, m in zip(bs, sizes)])
+        px = (ctypes.c_void_p * n)(*[self._cdev(x, torch.complex128, m).value for x, m in zip(xs, sizes)])
         nr = (ctypes.c_int64 * n)(*[b.shape[0] for b in bs])
         stats = (SolveStats * n)()
         st = lib().dp_solve_batch(self.h, n, arr_ops, pb, px, nr, ctypes.byref(opts), stats, self._stream())
@@ -406,7 +417,7 @@ class Context:
         h = ctypes.c_void_p()
         st = lib().dp_deflation_create(self.h, ctypes.byref(op), int(nvec), ctypes.byref(eo), ctypes.byref(h),
                                        self._stream())
-        d = Deflation(self, h, int(nvec)) if h.value else None
+        d = Deflation(self, h, int(nvec), tuple(op.dims), int(op.nc)) if h.value else None
         if st != OK and (check or st != ENOCONV or d is None):
             if d is not None:
                 d.close()
@@ -435,8 +446,9 @@ class Context:
     def apply(self, op, v, prec="f64"):
         torch = self.torch
         y = torch.empty_like(v)
-        st = lib().dp_apply(self.h, ctypes.byref(op), PREC[prec], self._cdev(v, torch.complex128),
-                            self._cdev(y, torch.complex128), v.shape[0], self._stream())
+        m = v.shape[0] * int(np.prod(list(op.dims))) * op.nc
+        st = lib().dp_apply(self.h, ctypes.byref(op), PREC[prec], self._cdev(v, torch.complex128, m),
+                            self._cdev(y, torch.complex128, m), v.shape[0], self._stream())
         if st != OK:
             self._err(st)
         return y
@@ -445,16 +457,20 @@ class Context:
 class Deflation:
     """Deflation vectors of one operator, owned by the library (device memory)."""
 
-    def __init__(self, ctx, h, nvec):
-        self.ctx, self.h, self.nvec = ctx, h, nvec
+    def __init__(self, ctx, h, nvec, dims, nc):
+        self.ctx, self.h, self.nvec, self.dims, self.nc = ctx, h, nvec, tuple(int(v) for v in dims), nc
         ev, rs = np.zeros(nvec), np.zeros(nvec)
         outer, sub = ctypes.c_int32(), ctypes.c_int32()
         lib().dp_deflation_info(h, ev.ctypes.data, rs.ctypes.data, ctypes.byref(outer), ctypes.byref(sub))
         self.evals, self.resid, self.outer, self.subspace = ev, rs, int(outer.value), int(sub.value)
 
-    def vectors(self, dims, nc):
-        """The Ritz vectors, complex128 cuda tensor [nvec, N, nc]."""
+    def vectors(self, dims=None, nc=None):
+        """The Ritz vectors, complex128 cuda tensor [nvec, N, nc] (dims and nc
+        are those of the operator; if given they must match)."""
         torch = self.ctx.torch
+        if (dims is not None and tuple(_dims4(dims)) != self.dims) or (nc is not None and nc != self.nc):
+            raise ValueError(f"the deflation is for dims {self.dims}, nc {self.nc}")
+        dims, nc = self.dims, self.nc
         N = int(np.prod(list(dims)))
         out = torch.empty((self.nvec, N, nc), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
         st = lib().dp_deflation_vectors(self.ctx.h, self.h, self.ctx._cdev(out, torch.complex128),

@@ -164,6 +164,21 @@ def test_solve_failure_statuses(ctx):
     assert e.value.status == dp.EINVAL
 
 
+def test_binding_rejects_bad_sizes(ctx):
+    """The kernels trust the sizes they are given: the binding checks every
+    tensor's element count (and device) on the host before any call."""
+    dims, c128 = (4, 4, 4, 4), torch.complex128
+    with pytest.raises(ValueError):
+        ctx.operator(dims, 3, 0.5, torch.zeros((4, 255, 3, 3), dtype=c128, device="cuda"))
+    op = ctx.operator(dims, 1, 0.5, None)
+    with pytest.raises(ValueError):
+        ctx.solve_batch([op], [torch.zeros((2, 255, 1), dtype=c128, device="cuda")], ctx.opts(tol=1e-10))
+    with pytest.raises(ValueError):
+        ctx.probe_spec(dims, 1, torch.zeros(255, dtype=torch.int32, device="cuda"), 1, 0, 0, 1, "z2_complex", False)
+    with pytest.raises(ValueError):
+        ctx.apply(op, torch.zeros((1, 256, 3), dtype=c128, device="cuda"))
+
+
 # ------------------------------------------------------------------ traces
 
 
