@@ -277,6 +277,30 @@ dp_status dp_trace_multi(dp_ctx *ctx, const dp_operator *op, const int32_t *disp
                          hipStream_t stream);
 
 /*
+ * Every level of a nested (hierarchical) colouring from the solves of the
+ * finest one (Sec. 2.3): with one noise vector z0 for all levels the probe of
+ * a class is the sum of the probes of its sub-classes, so by linearity
+ *     T_l = sum_j v_{parent_l(j)}^H P x_j,   x_j = A^{-1} v_j,
+ * the sum over the finest probes v_j of each solution contracted with the
+ * probe of its parent class on level l.  Equal, up to the solver tolerance,
+ * to dp_trace_estimate on level l's colouring with the same seed and
+ * samples, for the price of one set of solves.
+ *   ps              the finest level (its colouring and noise).
+ *   coarse_colors   host array of ncoarse device int32[N] colourings, each
+ *                   nested with the fine one (every fine class inside one
+ *                   coarse class), coarse_ncolors their colour counts.
+ *   out             host dp_trace_result[ncoarse + 1], written: out[0] the
+ *                   finest level (as dp_trace_estimate), out[1 + l] level l;
+ *                   per_rhs of a coarse level holds the per-solution terms
+ *                   v_{parent_l(j)}^H P x_j.
+ * DP_EINVAL when a coarse colouring is not nested in the fine one or a colour
+ * is outside [0, ncolors) (checked on the device before any solve).
+ * Single instance; the other conventions are those of dp_trace_estimate. */
+dp_status dp_trace_levels(dp_ctx *ctx, const dp_operator *op, int32_t p, const dp_probe_spec *ps,
+                          int32_t ncoarse, const int32_t *const *coarse_colors, const int32_t *coarse_ncolors,
+                          const dp_solve_opts *o, dp_trace_result *out, hipStream_t stream);
+
+/*
  * Adjoint gradient of the probed estimate T (same probes as dp_trace_estimate).
  * With x_j = A^{-1} v_j and lambda_j = A^{-1} P^T v_j ((P^T v)(y) = v(y - p e0)),
  * recomputed here (no Krylov history is kept):

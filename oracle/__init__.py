@@ -291,6 +291,38 @@ def trace_grad(dims, nc, m2, links, p, colors, ncolors, seed, sample0, nsamples,
     return complex(out[0], out[1]), complex(g[0], g[1]), dU, dUb
 
 
+def trace_levels(dims, nc, m2, links, p, colors, ncolors, seed, sample0, nsamples, kind, dilute, tol=1e-12):
+    """Every level of a nested colouring from the solves of the finest one
+    (Sec. 2.3).  With one noise vector per sample for all levels, the probe of
+    a class is the sum of the probes of its sub-classes; by linearity the
+    level-l estimate is then the sum over the finest probes v_j of
+    v_{parent_l(j)}^H P A^{-1} v_j.  colors [L][N] are the levels, coarse to
+    fine (the last one is solved), ncolors their colour counts.  Returns one
+    dict per level (in the order given) with T, the per-sample values T_s and
+    the per-solution terms t_j."""
+    colors = [np.asarray(c, dtype=np.int32) for c in colors]
+    fine, nfine = colors[-1], int(ncolors[-1])
+    ndil = nc if dilute else 1
+    V = probes(dims, nc, fine, nfine, seed, sample0, nsamples, kind, dilute)
+    X, _, _ = cg_many(dims, nc, m2, links, V, tol=tol)
+    out = []
+    for col in colors:
+        parent = {}
+        for x in range(len(fine)):
+            parent[int(fine[x])] = int(col[x])
+        tj = np.zeros(len(V), dtype=np.complex128)
+        j = 0
+        for s in range(sample0, sample0 + nsamples):
+            for c in range(nfine):
+                for a in range(ndil):
+                    vp = probe(dims, nc, col, seed, s, parent[c], a, dilute, kind) if c in parent else 0 * V[j]
+                    tj[j] = np.vdot(vp, shift(dims, X[j], p))
+                    j += 1
+        Ts = noise_norm(kind) * tj.reshape(nsamples, -1).sum(axis=1)
+        out.append({"T": complex(Ts.mean()), "per_sample": Ts, "tj": tj})
+    return out
+
+
 def noise_norm(kind: int) -> float:
     return 0.5 if kind == Z2_COMPLEX else 1.0
 

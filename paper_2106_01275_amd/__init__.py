@@ -81,7 +81,8 @@ class EigOpts(ctypes.Structure):
 
 EXPORTS = ["dp_create", "dp_destroy", "dp_last_error", "dp_build_coloring", "dp_build_coloring_multi",
            "dp_tile_shape", "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
-           "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply", "dp_deflation_create",
+           "dp_trace_estimate", "dp_trace_multi", "dp_trace_levels", "dp_trace_grad", "dp_apply",
+           "dp_deflation_create",
            "dp_deflation_info", "dp_deflation_vectors", "dp_trace_deflated", "dp_deflation_destroy"]
 
 _lib = None
@@ -112,6 +113,8 @@ def lib():
                                         ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp]
         L.dp_trace_multi.argtypes = [vp, ctypes.POINTER(Operator), vp, i32, ctypes.POINTER(ProbeSpec),
                                      ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp]
+        L.dp_trace_levels.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(ProbeSpec), i32, vp, vp,
+                                      ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp]
         L.dp_trace_grad.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(ProbeSpec),
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp, vp, vp, vp]
         L.dp_apply.argtypes = [vp, ctypes.POINTER(Operator), i32, vp, vp, i64, vp]
@@ -125,7 +128,7 @@ def lib():
         L.dp_deflation_destroy.restype = None
         for name in ("dp_create", "dp_build_coloring", "dp_build_coloring_multi", "dp_tile_shape",
                      "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
-                     "dp_trace_estimate", "dp_trace_multi", "dp_trace_grad", "dp_apply",
+                     "dp_trace_estimate", "dp_trace_multi", "dp_trace_levels", "dp_trace_grad", "dp_apply",
                      "dp_deflation_create", "dp_deflation_info", "dp_deflation_vectors", "dp_trace_deflated"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
@@ -382,6 +385,34 @@ class Context:
         out = [{"p": int(disps[i]), "T": complex(res[i].tr[0], res[i].tr[1]), "stderr": res[i].stderr_,
                 "per_sample": bufs[i][0].view(np.complex128).copy(), "tj": bufs[i][1].view(np.complex128).copy(),
                 "solve": res[i].solve.asdict()} for i in range(n)]
+        if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
+            self._err(st, out)
+        return out
+
+    def trace_levels(self, op, ps, p, coarse, opts, check=True):
+        """Every level of a nested colouring from the solves of the finest one
+        (ps).  coarse: list of (colours, ncolours) of the coarser levels,
+        colours an int32 cuda tensor [N] each.  Returns a list of dicts, the
+        finest level first, then the coarse levels in the order given."""
+        N = int(np.prod(list(ps.dims)))
+        n = len(coarse)
+        keep = [self._cdev(c, self.torch.int32, N) for c, _ in coarse]
+        arr_c = (ctypes.c_void_p * max(n, 1))(*[k.value for k in keep])
+        arr_n = (ctypes.c_int32 * max(n, 1))(*[int(m) for _, m in coarse])
+        res = (TraceResult * (n + 1))()
+        ndil = ps.nc if ps.dilute else 1
+        nrhs = ps.nsamples * ps.ncolors * ndil
+        bufs = []
+        for i in range(n + 1):
+            per_s, per_r = np.zeros(2 * ps.nsamples), np.zeros(2 * nrhs)
+            bufs.append((per_s, per_r))
+            res[i].per_sample = per_s.ctypes.data
+            res[i].per_rhs = per_r.ctypes.data
+        st = lib().dp_trace_levels(self.h, ctypes.byref(op), int(p), ctypes.byref(ps), n, arr_c, arr_n,
+                                   ctypes.byref(opts), res, self._stream())
+        out = [{"T": complex(res[i].tr[0], res[i].tr[1]), "stderr": res[i].stderr_,
+                "per_sample": bufs[i][0].view(np.complex128).copy(), "tj": bufs[i][1].view(np.complex128).copy(),
+                "solve": res[i].solve.asdict()} for i in range(n + 1)]
         if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
             self._err(st, out)
         return out

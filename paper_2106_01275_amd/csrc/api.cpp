@@ -451,9 +451,13 @@ struct Staging {
     bool drain_after(long long k, long long nblocks) const { return k % chunk == chunk - 1 || k == nblocks - 1; }
 };
 
+// colors[n], cmaps[n] (optional, per contraction): contract each solution
+// with the probe of colour cmap[c] of the colouring colors[n] instead of its
+// own (the parent class on a coarser nested level).
 static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const int32_t *disp, int ndisp,
                                      const dp_probe_spec &ps, const dp_solve_opts *o, const SolveCfg &cfg,
-                                     dp_trace_result *outs, hipStream_t stream) {
+                                     dp_trace_result *outs, hipStream_t stream,
+                                     const int32_t *const *colors = nullptr, const int *const *cmaps = nullptr) {
     const double t0 = now_s();
     DP_TRY(check_spec(ctx, ps, &opd));
     OpPrep op;
@@ -481,7 +485,10 @@ static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const 
         DP_TRY(solve_block(ctx, op, cfg, L, rd, cs, x64, init, bs, &s, stg.state(k)));
         for (int n = 0; n < ndisp; ++n) {
             // each contraction reads x only at the probe's sites shifted by disp[n]
-            launch_displaced_dot(L, make_gen(ps, r0, nv, 0), disp[n], x64, rd, cs);
+            ProbeGen g = make_gen(ps, r0, nv, 0);
+            if (colors && colors[n]) g.colors = colors[n];
+            if (cmaps) g.cmap = cmaps[n];
+            launch_displaced_dot(L, g, disp[n], x64, rd, cs);
             DP_HIP(hipGetLastError());
             DP_HIP(hipMemcpyAsync(stg.result(k) + (size_t)n * 2 * W, cs.tj, 2 * nv * sizeof(double),
                                   hipMemcpyDeviceToHost, stream));
@@ -605,6 +612,61 @@ dp_status dp_trace_multi(dp_ctx *ctx, const dp_operator *op, const int32_t *disp
     dp_status st = trace_displacements(ctx, *op, disp, ndisp, *ps, o, cfg, out, ws_.s);
     if (st == DP_ENOCONV) ctx->err = "trace_multi: some right-hand sides did not converge";
     if (st == DP_EBREAKDOWN) ctx->err = "trace_multi: CG breakdown";
+    return st;
+}
+
+dp_status dp_trace_levels(dp_ctx *ctx, const dp_operator *op, int32_t p, const dp_probe_spec *ps, int32_t ncoarse,
+                          const int32_t *const *coarse_colors, const int32_t *coarse_ncolors, const dp_solve_opts *o,
+                          dp_trace_result *out, hipStream_t stream) {
+    DP_TRY(check_ctx(ctx));
+    if (!op || !ps || !out || p < 0 || ncoarse < 0 || (ncoarse > 0 && (!coarse_colors || !coarse_ncolors))) {
+        ctx->err = "trace_levels: bad arguments";
+        return DP_EINVAL;
+    }
+    for (int l = 0; l < ncoarse; ++l)
+        if (!coarse_colors[l] || coarse_ncolors[l] < 1) {
+            ctx->err = "trace_levels: a coarse colouring is missing or has no colours";
+            return DP_EINVAL;
+        }
+    SolveCfg cfg;
+    DP_TRY(solve_cfg(ctx, o, cfg));
+    DP_TRY(check_spec(ctx, *ps, op));
+    WorkStream ws_;
+    DP_TRY(ws_.enter(ctx, stream, cfg.use_graph));
+    struct Leave {
+        WorkStream &w;
+        ~Leave() { (void)w.leave(); }
+    } leave_{ws_};
+    const int N = ps->dims[0] * ps->dims[1] * ps->dims[2] * ps->dims[3];
+    const size_t nmap = (size_t)ncoarse * ps->ncolors;
+    std::vector<const int32_t *> cols(ncoarse + 1, nullptr);
+    std::vector<const int *> maps(ncoarse + 1, nullptr);
+    if (ncoarse > 0) {
+        // fine colour -> parent colour on each coarse level, checked nested
+        DP_TRY(ctx->ensure(kSlotCmap, (nmap + ncoarse) * sizeof(int)));
+        int *cm = (int *)ctx->at(kSlotCmap), *bad = cm + nmap;
+        for (int l = 0; l < ncoarse; ++l)
+            launch_level_map(N, ps->colors_dev, ps->ncolors, coarse_colors[l], coarse_ncolors[l],
+                             cm + (size_t)l * ps->ncolors, bad + l, ws_.s);
+        DP_HIP(hipGetLastError());
+        std::vector<int> hbad(ncoarse, 0);
+        DP_HIP(hipMemcpyAsync(hbad.data(), bad, ncoarse * sizeof(int), hipMemcpyDeviceToHost, ws_.s));
+        DP_HIP(hipStreamSynchronize(ws_.s));
+        for (int l = 0; l < ncoarse; ++l) {
+            if (hbad[l]) {
+                ctx->err = "trace_levels: coarse colouring " + std::to_string(l) +
+                           " is not nested in the fine one, or a colour is out of range";
+                return DP_EINVAL;
+            }
+            cols[l + 1] = coarse_colors[l];
+            maps[l + 1] = cm + (size_t)l * ps->ncolors;
+        }
+    }
+    std::vector<int32_t> disp(ncoarse + 1, p);
+    dp_status st = trace_displacements(ctx, *op, disp.data(), ncoarse + 1, *ps, o, cfg, out, ws_.s, cols.data(),
+                                       maps.data());
+    if (st == DP_ENOCONV) ctx->err = "trace_levels: some right-hand sides did not converge";
+    if (st == DP_EBREAKDOWN) ctx->err = "trace_levels: CG breakdown";
     return st;
 }
 

@@ -28,7 +28,7 @@ namespace dp {
 
 enum Slot {
     kSlotNbr, kSlotU64, kSlotU8, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotXLo,
-    kSlotPart1, kSlotState, kSlotColors, kSlotVec, kNumSlots
+    kSlotPart1, kSlotState, kSlotColors, kSlotVec, kSlotCmap, kNumSlots
 };
 
 // A prepared operator: neighbour table and links in the internal layout.

@@ -70,6 +70,9 @@ struct ProbeGen {
     long long rhs0;      // enumeration index of lane 0
     long long nvalid;    // lanes [0, nvalid) carry probes
     int shift;           // 0: v_j; p: (P^T v_j)(y) = v_j(y - p e0)
+    const int *cmap;     // displaced dot only: non-null, lane j (colour c_j) is contracted with
+                         // the probe of colour cmap[c_j] of the colouring `colors` (its parent
+                         // class on a coarser nested level); null, with its own probe
 };
 
 enum Prec { kF64 = 0, kF32 = 1, kBF16 = 2 };
@@ -157,6 +160,11 @@ void launch_fold(const Launch &L, int prec, double *x64, void *xlo, const void *
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
                        const double *x64, const void *U64, const int *nbr, void *r, int ru_mode,
                        const Red &rd, const CgState &cs, const ProbeGen *gen = nullptr);
+// cmap[c] = the coarse colour of the sites of fine colour c (-1 for a colour
+// no site has); *bad set to 1 when a colour is out of range or two sites of
+// one fine colour have different coarse colours (not nested).
+void launch_level_map(int N, const int *fine, int nfine, const int *coarse, int ncoarse, int *cmap, int *bad,
+                      hipStream_t s);
 void launch_displaced_dot(const Launch &L, const ProbeGen &g, int p, const double *x64, const Red &rd,
                           const CgState &cs);
 void launch_dot(const Launch &L, const double *a64, const double *b64, const Red &rd,

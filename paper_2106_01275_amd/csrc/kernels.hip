@@ -1280,7 +1280,8 @@ __device__ __forceinline__ void k_displaced_dot_body(const Blk &bk, Launch L, Pr
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
     if (j < g.nvalid) {
-        const ProbeLane pl = probe_lane(g, nc, g.rhs0 + j);
+        ProbeLane pl = probe_lane(g, nc, g.rhs0 + j);
+        if (g.cmap) pl.c = g.cmap[pl.c];  // the parent class's probe: same noise, coarse colour
         for (int t = t0; t < t1; ++t) {
             const int site = t * sites_per_tile + sl;
             if (site >= L.lat.N || g.colors[site] != pl.c) continue;
@@ -1296,6 +1297,33 @@ __device__ __forceinline__ void k_displaced_dot_body(const Blk &bk, Launch L, Pr
         }
     }
     block_partials<2>(bk, acc, W, logW, rd, sm);
+}
+
+// Map of a nested colouring's fine colours to coarse ones (three passes:
+// clear, scatter, check; every colour is range-checked before it indexes).
+__global__ void k_level_map_clear(int *cmap, int nfine, int *bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nfine) cmap[i] = -1;
+    if (i == 0) *bad = 0;
+}
+
+__global__ void k_level_map_scatter(int N, const int *fine, int nfine, const int *coarse, int ncoarse, int *cmap,
+                                    int *bad) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    const int c = fine[x], cc = coarse[x];
+    if (c < 0 || c >= nfine || cc < 0 || cc >= ncoarse) {
+        *bad = 1;
+        return;
+    }
+    cmap[c] = cc;  // equal values from every site of a nested colouring
+}
+
+__global__ void k_level_map_check(int N, const int *fine, int nfine, const int *coarse, const int *cmap, int *bad) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    const int c = fine[x];
+    if (c >= 0 && c < nfine && cmap[c] != coarse[x]) *bad = 1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_displaced_dot(Launch L, ProbeGen g, int p,
@@ -1871,6 +1899,13 @@ void launch_true_resid(const Launch &L, int prec, bool links, double diag, const
         k_finish<1, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
     else
         k_finish<1, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_level_map(int N, const int *fine, int nfine, const int *coarse, int ncoarse, int *cmap, int *bad,
+                      hipStream_t s) {
+    k_level_map_clear<<<blocks_for(nfine), kBlock, 0, s>>>(cmap, nfine, bad);
+    k_level_map_scatter<<<blocks_for(N), kBlock, 0, s>>>(N, fine, nfine, coarse, ncoarse, cmap, bad);
+    k_level_map_check<<<blocks_for(N), kBlock, 0, s>>>(N, fine, nfine, coarse, cmap, bad);
 }
 
 void launch_displaced_dot(const Launch &L, const ProbeGen &g, int p, const double *x64, const Red &rd,
