@@ -228,6 +228,17 @@ def run_gauge16(a, torch, dp, workloads):
         extra["multi_displacement"] = {"displacements": list(range(9)), "seconds": tm,
                                        "seconds_one_displacement": sec_per_sample,
                                        "T": [[r_["T"].real, r_["T"].imag] for r_ in rm]}
+        if level == len(w.ks) - 1 and level > 0:
+            # every coarser nested level from the finest level's solves (one sample)
+            coarse = [(torch.from_numpy(np.ascontiguousarray(cols[i])).cuda(), int(ncols[i])) for i in range(level)]
+            torch.cuda.synchronize()
+            tn = time.perf_counter()
+            rn = c.trace_levels(op, ps, p, coarse, c.opts(tol=w.tol, inner=inner, rhs_block=W))
+            torch.cuda.synchronize()
+            tn = time.perf_counter() - tn
+            extra["levels_from_finest"] = {"levels": [f"k={k}" for k in w.ks[:level]] + [f"k={w.ks[level]}"],
+                                           "seconds": tn, "seconds_finest_alone": sec_per_sample,
+                                           "T": [[r_["T"].real, r_["T"].imag] for r_ in rn[1:] + rn[:1]]}
         # plain single-RHS FP64 GPU solver on a few of the same right-hand sides
         nplain = 8
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, 0, 1, "z2_complex", True)
