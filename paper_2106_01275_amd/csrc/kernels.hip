@@ -1005,12 +1005,71 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
     block_partials<1>(bk, acc, W, logW, rd, sm);
 }
 
+// MODE 5 (W = 1): one right-hand side leaves a launch with one thread per
+// site too few threads to fill the GPU (an 8^4 lattice: 16 workgroups), so
+// a site takes 32 threads: thread (h, a) = (lane / 4, lane % 4) forms row a
+// of hop h's product U v (rows a >= nc idle), the eight hops of a row are
+// summed by a butterfly over lanes 4, 8 and 16 apart, and hop 0's threads
+// write q.  Eight sites per workgroup pass.
+template <typename S, typename LS, int NC, bool LINKS>
+__device__ __forceinline__ void k_stencil_split_body(const Blk &bk, Launch L, typename St<S>::R diag,
+                                                     const S *__restrict__ pin, S *__restrict__ q,
+                                                     const LS *__restrict__ U, const int *__restrict__ nbr, int cg,
+                                                     Red rd) {
+    using R = typename St<S>::R;
+    __shared__ double sm[kBlock];
+    const int tid = threadIdx.x, lane = tid & 31, h = lane >> 2, a = lane & 3;
+    const int ngroups = (L.lat.N + 7) / 8;
+    double acc_pq = 0.0;
+    for (int g = bk.b; g < ngroups; g += bk.nb) {
+        const int site = g * 8 + (tid >> 5);
+        const bool live = site < L.lat.N;
+        R sr = 0, si = 0;
+        if (live && a < NC) {
+            const int y = nbr[site * 8 + h];
+            if (LINKS) {
+                // row a of U_mu(x) (h < 4) or of U_mu(x - mu)^H (h >= 4)
+                const LS *u = U + ((size_t)site * 8 + h) * NC * NC;
+#pragma unroll
+                for (int b = 0; b < NC; ++b) {
+                    typename St<LS>::R ur, ui;
+                    St<LS>::ld(u, h < 4 ? a * NC + b : b * NC + a, ur, ui);
+                    if (h >= 4) ui = -ui;
+                    R vr, vi;
+                    St<S>::ld(pin, (size_t)y * NC + b, vr, vi);
+                    sr = fmaR((R)ur, vr, fmaR(-(R)ui, vi, sr));
+                    si = fmaR((R)ur, vi, fmaR((R)ui, vr, si));
+                }
+            } else {
+                St<S>::ld(pin, (size_t)y * NC + a, sr, si);
+            }
+        }
+#pragma unroll
+        for (int off = 4; off < 32; off <<= 1) {
+            sr += __shfl_xor(sr, off, 64);
+            si += __shfl_xor(si, off, 64);
+        }
+        if (live && h == 0 && a < NC) {
+            R pr, pi;
+            St<S>::ld(pin, (size_t)site * NC + a, pr, pi);
+            const R qr = fmaR(diag, pr, -sr), qi = fmaR(diag, pi, -si);
+            St<S>::st(q, (size_t)site * NC + a, qr, qi);
+            acc_pq += (double)fmaR(pr, qr, pi * qi);
+        }
+    }
+    if (!cg) return;
+    double acc[1] = {acc_pq};
+    block_partials<1>(bk, acc, 1, 0, rd, sm);
+}
+
 template <typename S, typename LS, int NC, bool LINKS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ pin,
                                                     S *__restrict__ q, const LS *__restrict__ U,
                                                     const int *__restrict__ nbr, int cg, Red rd) {
     if constexpr (MODE == 3 || MODE == 4)
         k_stencil_group_body<S, LS, NC, LINKS, MODE == 3 ? 2 : 4>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
+    else if constexpr (MODE == 5)
+        k_stencil_split_body<S, LS, NC, LINKS>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
     else
         k_stencil_body<S, LS, NC, LINKS, MODE>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
 }
@@ -1817,7 +1876,9 @@ static void stencil_nc(const Launch &L, const StencilArgs &a) {
     const bool slabs = !std::is_same<S, bf16x2>::value && L.nblk >= 8 && L.nblk % 8 == 0;
     const bool pairs = slabs && L.lat.D[0] % 16 == 0;
     const bool quads = slabs && L.lat.D[0] == 16 && L.lat.D[3] % 2 == 0 && L.W >= 32;
-    if (L.W >= 64)
+    if (L.W == 1 && !std::is_same<S, bf16x2>::value)
+        DP_ST(5);
+    else if (L.W >= 64)
         DP_ST(2);
     else if (quads)
         DP_ST(4);

@@ -197,7 +197,10 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     L.W = W;
     L.logW = logW;
     L.ntiles = (op.lat.N + (kBlock >> logW) - 1) / (kBlock >> logW);
-    L.nblk = grid_blocks(L.ntiles);
+    // one right-hand side: the stencil splits a site over 32 threads, eight
+    // sites per workgroup, so the launch takes up to N / 8 workgroups (the
+    // other kernels leave the extra ones idle)
+    L.nblk = grid_blocks(W == 1 ? std::max(L.ntiles, (op.lat.N + 7) / 8) : L.ntiles);
     L.stream = s;
     const size_t vec = (size_t)op.lat.N * op.nc * W;
     const size_t lo = vec * prec_bytes(cfg.inner);
