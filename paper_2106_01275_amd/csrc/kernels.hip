@@ -815,7 +815,8 @@ __device__ __forceinline__ void ld_hop(const LS *__restrict__ U8, int site, int 
 // per lane when `cg` is set (the first kernel of a CG iteration).
 //
 // MODE 0 (W < 16): every lane loads its site's links itself (the lanes of a
-// site read the same addresses).  MODE 1 (16 <= W < 64): the links of the
+// site read the same addresses); for W = 1 (FP64, FP32) MODE 5 instead
+// splits a site over 32 threads (k_stencil_split_body).  MODE 1 (16 <= W < 64): the links of the
 // tile's sites are staged in LDS once and shared by the W lanes.  MODE 2
 // (W >= 64): a wavefront covers one site, so the site index is uniform and
 // the links and neighbour indices come through scalar loads; no LDS and no
