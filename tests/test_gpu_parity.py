@@ -76,7 +76,10 @@ def test_make_probes_bit_exact(ctx, dims, nc, noise, dilute, p, k):
                                                 # slabs, even D3, W = 32), x0 pairs (even slabs)
                                                 ((16, 4, 4, 4), 3, True, 32), ((16, 4, 4, 4), 1, False, 32),
                                                 ((32, 4, 2, 2), 3, True, 32), ((16, 2, 4, 3), 3, True, 16),
-                                                ((16, 4, 2, 3), 3, True, 32)])
+                                                ((16, 4, 2, 3), 3, True, 32),
+                                                # one right-hand side: a site split over 32 threads
+                                                ((4, 4, 4, 4), 1, False, 1), ((6, 4, 5, 3), 3, False, 1),
+                                                ((5, 3, 4, 3), 1, True, 1), ((2, 2, 2, 2), 3, True, 1)])
 def test_apply_matches_oracle(ctx, prec, rtol, dims, nc, links, nrhs):
     _say("apply", prec, dims, nc, links, nrhs)
     N = int(np.prod(dims))
