@@ -49,7 +49,7 @@ enum {
     DP_EHIP = 3,          /* a HIP runtime call failed */
     DP_ENOCONV = 4,       /* max_iter reached; outputs are written, stats say which */
     DP_EBREAKDOWN = 5,    /* CG breakdown: p^H A p <= 0 or not finite */
-    DP_EUNSUPPORTED = 6   /* valid request this build does not support */
+    DP_EUNSUPPORTED = 6   /* valid request the library does not support */
 };
 
 /* visitation order of the greedy colouring (Sec. 3.1) */
