@@ -1983,8 +1983,107 @@ void launch_dot(const Launch &L, const double *a64, const double *b64, const Red
 
 void launch_ctrl(const CgState &cs, int W, hipStream_t s) { k_ctrl<<<1, 64, 0, s>>>(cs, W); }
 
+// The same force for W >= 8, W threads per (site, mu) pair: thread j loads
+// lane j of the four rows the pair needs (coalesced, each once per pair) and
+// forms its lane's 4 nc^2 doubles (padded to 8 * 5 = 40 for nc = 3); the
+// lanes are summed by a reduce-scatter inside the wavefront (three halvings:
+// a lane keeps one half of its values and adds its partner's copy of that
+// half, so the shuffles move 20 + 10 + 5 values instead of 3 x 40), a
+// butterfly on the remaining five, and through LDS across the wavefronts of
+// a pair (W > 64); all in a fixed order.
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_force_lanes(Launch L, const double2 *__restrict__ x64,
+                                                        const double2 *__restrict__ l64, const int *__restrict__ nbr,
+                                                        double scale, int first, double *__restrict__ dU,
+                                                        double *__restrict__ dUbar) {
+    constexpr int NV = 4 * NC * NC;         // dU re, dU im, dUbar re, dUbar im per (a, b)
+    constexpr int NP = (NV + 7) / 8 * 8;    // padded so that three halvings divide it
+    __shared__ double red[kBlock / 8][NP];  // one row per pair (W < 64) or per wavefront (W >= 64)
+    const int W = L.W, logW = L.logW, tid = threadIdx.x;
+    const int j = tid & (W - 1), pl = tid >> logW;
+    const long long pair = (long long)blockIdx.x * (kBlock >> logW) + pl;
+    const bool live = pair < (long long)L.lat.N * 4;
+    const int site = live ? (int)(pair >> 2) : 0, mu = (int)(pair & 3);
+    double v[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) v[k] = 0.0;
+    if (live) {
+        const int y = nbr[site * 8 + mu];
+        double2 la[NC], xa[NC], xb[NC], lb[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            la[c] = l64[((size_t)(site * NC + c) << logW) + j];
+            xa[c] = x64[((size_t)(site * NC + c) << logW) + j];
+            xb[c] = x64[((size_t)(y * NC + c) << logW) + j];
+            lb[c] = l64[((size_t)(y * NC + c) << logW) + j];
+        }
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                const int k = 4 * (a * NC + b);
+                v[k] = la[a].x * xb[b].x + la[a].y * xb[b].y;  // conj(l) x
+                v[k + 1] = la[a].x * xb[b].y - la[a].y * xb[b].x;
+                v[k + 2] = xa[a].x * lb[b].x + xa[a].y * lb[b].y;  // x conj(l)
+                v[k + 3] = xa[a].y * lb[b].x - xa[a].x * lb[b].y;
+            }
+    }
+    // reduce-scatter over the span = min(W, 64) lanes of a group (W >= 8:
+    // three halvings fit), then a butterfly over the rest of the span
+    const int span = W < 64 ? W : 64, lane = tid & 63;
+    int base = 0;  // first value this lane holds after the halvings
+#pragma unroll
+    for (int step = 0; step < 3; ++step) {
+        const int off = span >> (step + 1);
+        const int half = NP >> (step + 1);
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const double keep = upper ? v[k + half] : v[k];
+            const double give = upper ? v[k] : v[k + half];
+            v[k] = keep + __shfl_xor(give, off, 64);
+        }
+        base += upper ? half : 0;
+    }
+    constexpr int NR = NP / 8;  // values per lane after the halvings
+    for (int off = span >> 4; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    // lanes with the low bits of the span clear hold the sums of their values
+    const int row = W < 64 ? pl : (tid >> 6);
+    if ((lane & ((span >> 3) - 1)) == 0)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) red[row][base + k] = v[k];
+    __syncthreads();
+    if (!live) return;
+    const int nw = W < 64 ? 1 : W >> 6, r0 = W < 64 ? pl : (pl * W) >> 6;
+    for (int k = j; k < NV; k += W) {
+        double t = red[r0][k];
+        for (int w = 1; w < nw; ++w) t += red[r0 + w][k];
+        const int ab = k >> 2, comp = k & 3;
+        const size_t o = 2 * (((size_t)mu * L.lat.N + site) * NC * NC + ab) + (comp & 1);
+        double *out = comp < 2 ? dU : dUbar;
+        if (!out) continue;
+        t *= scale;
+        out[o] = first ? t : out[o] + t;
+    }
+}
+
 void launch_force(const Launch &L, const double *x64, const double *l64, const int *nbr, double scale, int first,
                   double *dU, double *dUbar) {
+    if (L.W >= 8) {
+        // W threads per (site, mu) pair
+        const long long nthreads = (long long)L.lat.N * 4 * L.W;
+        if (L.nc == 3)
+            k_force_lanes<3><<<blocks_for(nthreads), kBlock, 0, L.stream>>>(L, (const double2 *)x64,
+                                                                           (const double2 *)l64, nbr, scale, first,
+                                                                           dU, dUbar);
+        else
+            k_force_lanes<1><<<blocks_for(nthreads), kBlock, 0, L.stream>>>(L, (const double2 *)x64,
+                                                                           (const double2 *)l64, nbr, scale, first,
+                                                                           dU, dUbar);
+        return;
+    }
     const long long n = (long long)L.lat.N * 4 * L.nc * L.nc;
     k_force<<<blocks_for(n), kBlock, 0, L.stream>>>(L, (const double2 *)x64, (const double2 *)l64, nbr, scale,
                                                     first, (double2 *)dU, (double2 *)dUbar);

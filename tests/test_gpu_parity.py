@@ -303,6 +303,30 @@ def test_trace_grad_matches_oracle(ctx, dims, inner):
     assert np.abs(dUb.cpu().numpy() - dUbo).max() < tol * s
 
 
+@pytest.mark.parametrize("nc", [3, 1])
+def test_trace_grad_every_width(ctx, nc):
+    """The force kernels at every kind of width: one thread per entry (W = 1,
+    4), lanes summed inside a wavefront (W = 8, 32, 64) and across wavefronts
+    (W = 128, 256), each against the oracle's gradient (FP64, 1e-9); the
+    6x4x4x4 distance-2 colouring (6 colours, two samples) gives 36 (nc = 3)
+    or 12 right-hand sides, so most widths end in a ragged or mostly empty
+    block."""
+    dims = (6, 4, 4, 4)
+    _say("grad widths", nc)
+    U = workloads.random_links(dims, 0.5, 4, nc)
+    col, n, colg, ps = _probe_setup(ctx, dims, nc, 1, 2, "natural", 19, 0, 2, "z2_complex", True)
+    op = ctx.operator(dims, nc, 0.25, cuda(U))
+    To, go, dUo, dUbo = oracle.trace_grad(dims, nc, 0.25, U, 1, col, n, 19, 0, 2, oracle.Z2_COMPLEX, True,
+                                          tol=1e-13)
+    s = np.abs(dUo).max()
+    for W in (1, 4, 8, 32, 64, 128, 256):
+        T, g, dU, dUb, st = ctx.trace_grad(op, ps, 1, ctx.opts(tol=1e-12, inner="f64", rhs_block=W))
+        assert st["rhs_block"] == W
+        assert abs(g - go) < 1e-9 * abs(go), W
+        assert np.abs(dU.cpu().numpy() - dUo).max() < 1e-9 * s, W
+        assert np.abs(dUb.cpu().numpy() - dUbo).max() < 1e-9 * s, W
+
+
 def test_grad_free_field_closed_form(ctx):
     """All-distinct colouring on the 4^4 free field: dT/dm2 equals the
     closed-form derivative -sum_k cos(k0 p)/lambda(k)^2."""
