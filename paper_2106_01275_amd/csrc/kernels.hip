@@ -906,10 +906,14 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
 // instead of 18.  With two slices per slab and an even D3, items 4i .. 4i + 3
 // are s, s + V3, s + 1, s + V3 + 1 (x0 and x3 neighbours; 4i / 2 is even,
 // so x3 + 1 does not wrap): 28 loads per quad instead of 36.  16^4, FP32,
-// W = 32: 45.1 us (G = 1), 41.6 (G = 2), 40.6 (G = 4).
-template <int G>
+// W = 32: 45.1 us (G = 1), 41.6 (G = 2), 40.6 (G = 4).  With a multiple of
+// four slices per slab (MODE 6, LINE), items 4i .. 4i + 3 are four
+// consecutive x0-slices of one (x1, x2, x3): s + h V3, 30 loads per four
+// sites instead of 32 with pairs.
+template <int G, bool LINE>
 __device__ __forceinline__ int group_nb(int h, int dir) {
     // the group member that is neighbour dir of member h, or -1
+    if (LINE) return (dir == 0 && h < G - 1) ? h + 1 : (dir == 4 && h > 0) ? h - 1 : -1;
     if (G == 2) return (h == 0 && dir == 0) ? 1 : (h == 1 && dir == 4) ? 0 : -1;
     switch (h * 8 + dir) {
         case 0 * 8 + 0: return 1;
@@ -924,7 +928,7 @@ __device__ __forceinline__ int group_nb(int h, int dir) {
     }
 }
 
-template <typename S, typename LS, int NC, bool LINKS, int G>
+template <typename S, typename LS, int NC, bool LINKS, int G, bool LINE = false>
 __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, typename St<S>::R diag,
                                                      const S *__restrict__ pin, S *__restrict__ q,
                                                      const LS *__restrict__ U, const int *__restrict__ nbr, int cg,
@@ -948,16 +952,16 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
         R vor[G][NC], voi[G][NC];  // the members' own vectors
 #pragma unroll
         for (int h = 0; h < G; ++h)
-            ld_site<S, NC>(pin, s0 + (h & 1) * wk.V3 + (h >> 1), logW, j, vor[h], voi[h]);
+            ld_site<S, NC>(pin, s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1)), logW, j, vor[h], voi[h]);
         R pqs = 0;
 #pragma unroll
         for (int h = 0; h < G; ++h) {
             const int ls = G * sl + h;
-            const int site = s0 + (h & 1) * wk.V3 + (h >> 1);
+            const int site = s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1));
             R vr[8][NC], vi[8][NC];
 #pragma unroll
             for (int dir = 0; dir < 8; ++dir) {
-                const int m = group_nb<G>(h, dir);
+                const int m = group_nb<G, LINE>(h, dir);
                 if (m >= 0) {
 #pragma unroll
                     for (int b = 0; b < NC; ++b) {
@@ -1069,6 +1073,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
                                                     const int *__restrict__ nbr, int cg, Red rd) {
     if constexpr (MODE == 3 || MODE == 4)
         k_stencil_group_body<S, LS, NC, LINKS, MODE == 3 ? 2 : 4>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
+    else if constexpr (MODE == 6)
+        k_stencil_group_body<S, LS, NC, LINKS, 4, true>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
     else if constexpr (MODE == 5)
         k_stencil_split_body<S, LS, NC, LINKS>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
     else
@@ -1877,12 +1883,15 @@ static void stencil_nc(const Launch &L, const StencilArgs &a) {
     const bool slabs = !std::is_same<S, bf16x2>::value && L.nblk >= 8 && L.nblk % 8 == 0;
     const bool pairs = slabs && L.lat.D[0] % 16 == 0;
     const bool quads = slabs && L.lat.D[0] == 16 && L.lat.D[3] % 2 == 0 && L.W >= 32;
+    const bool lines = slabs && L.lat.D[0] % 32 == 0 && L.W >= 32;  // slabs of 4k slices
     if (L.W == 1 && !std::is_same<S, bf16x2>::value)
         DP_ST(5);
     else if (L.W >= 64)
         DP_ST(2);
     else if (quads)
         DP_ST(4);
+    else if (lines)
+        DP_ST(6);
     else if (L.W >= 16 && pairs)
         DP_ST(3);
     else if (L.W >= 16)
