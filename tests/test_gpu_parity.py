@@ -73,7 +73,8 @@ def test_make_probes_bit_exact(ctx, dims, nc, noise, dilute, p, k):
                                                 ((3, 4, 4, 5), 3, True, 100), ((5, 4, 3, 4), 1, True, 20),
                                                 ((2, 2, 2, 2), 3, False, 5),
                                                 # grouped-site stencils: x0 x x3 quads (two-slice
-                                                # slabs, even D3, W = 32), x0 pairs (even slabs)
+                                                # slabs, even D3, W = 32), x0 lines of four (slabs of
+                                                # 4k slices: 32 x ...), x0 pairs (other even slabs)
                                                 ((16, 4, 4, 4), 3, True, 32), ((16, 4, 4, 4), 1, False, 32),
                                                 ((32, 4, 2, 2), 3, True, 32), ((16, 2, 4, 3), 3, True, 16),
                                                 ((16, 4, 2, 3), 3, True, 32),
