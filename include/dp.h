@@ -225,7 +225,9 @@ typedef struct {
 
 /*
  * Solves A_i x = b for every right-hand side of every instance with CG
- * (Hestenes-Stiefel, x0 = 0).
+ * (Hestenes-Stiefel, x0 = 0).  These solves, one per probing vector, are
+ * what the paper names the bulk of the cost of the estimator (Sec. 2.1):
+ * every probe of eqs. (3)-(4) costs one of them.
  *   ninst  number of instances (>= 1).
  *   ops    host dp_operator[ninst].
  *   b      host array [ninst] of device complex128 [nrhs[i]][N_i][nc_i].
@@ -302,6 +304,10 @@ dp_status dp_trace_levels(dp_ctx *ctx, const dp_operator *op, int32_t p, const d
 
 /*
  * Adjoint gradient of the probed estimate T (same probes as dp_trace_estimate).
+ * The paper has no gradient: this call is an addition to its method, derived
+ * from dT = -lambda^H dA x for each probe (A Hermitian), and its results are
+ * checked against central finite differences of T and, for the free field,
+ * against the derivative of the Fourier closed form of Tr(P A^{-1}).
  * With x_j = A^{-1} v_j and lambda_j = A^{-1} P^T v_j ((P^T v)(y) = v(y - p e0)),
  * recomputed here (no Krylov history is kept):
  *     dT/dm2              = -(norm/s) sum_j lambda_j^H x_j

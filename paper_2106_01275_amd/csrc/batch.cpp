@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "context.h"
@@ -352,7 +353,9 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         for (int k = 0; k < nslots; ++k)
             if (hsd[k].flags & kSlotIter) steps = std::min(steps, std::max(1, cfg.max_iter - slot_it[k]));
         if (cfg.use_graph && !cfg.profile) {
-            auto g = ctx->graphs.find(steps);
+            // B is fixed for the call, and the graphs are dropped before and after it
+            const std::string key = "batch " + std::to_string(steps);
+            auto g = ctx->graphs.find(key);
             if (g == ctx->graphs.end()) {
                 hipGraph_t graph = nullptr;
                 hipGraphExec_t exec = nullptr;
@@ -362,7 +365,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
                 const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 DP_HIP(ie);
-                g = ctx->graphs.emplace(steps, exec).first;
+                g = ctx->graphs.emplace(key, exec).first;
             }
             DP_HIP(hipGraphLaunch(g->second, s));
         } else {

@@ -72,7 +72,7 @@ struct dp_ctx {
     int check_every = 8;
     hipStream_t gstream = nullptr;            // library stream for graph capture
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    std::map<int, hipGraphExec_t> graphs;     // iteration groups by length (one solve)
+    std::map<std::string, hipGraphExec_t> graphs;  // iteration groups by length and kernel arguments
     // device buffers of the multi-instance engine, kept for the next call
     // (hipMalloc / hipFree synchronise the device and cost far more than a
     // small batch's solves)
@@ -104,6 +104,11 @@ struct SolveCfg {
 };
 
 dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep &out, hipStream_t s);
+// workgroups of a single-instance launch at width W
+int launch_blocks(const Lat &lat, int W);
+// bytes of workspace slot `slot` that prepare_operator and make_launch need
+// for this operator, inner precision and width (0: the slot is not used)
+size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W);
 dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launch &L, Red &rd, CgState &cs,
                       const SolveCfg &cfg);
 // Runs CG on the block initialised by `init` (a callable launching the init

@@ -13,8 +13,11 @@
 // workgroup, and chunks are assigned so that each XCD owns a contiguous part
 // of the lattice (its L2 then serves the x1/x2/x3 neighbour re-reads).
 //
-// Reductions (dot products per right-hand side) accumulate in FP64: every
-// workgroup writes its partial sums, and a finishing kernel with one
+// Reductions (dot products per right-hand side) accumulate in FP64 across
+// sites and workgroups; with FP32 or BF16 storage a thread first sums the
+// few products of one site (its colours and hops) in FP32, or up to 24
+// elements in the vector kernels, before adding them to its FP64 total.
+// Every workgroup writes its partial sums, and a finishing kernel with one
 // workgroup per right-hand side adds them in a fixed order (deterministic)
 // and runs the CG scalar epilogue (alpha, beta, convergence flags) on the
 // device, so the host only reads a control word now and then.  The kernel

@@ -143,6 +143,34 @@ dp_status WorkStream::leave() {
 
 static size_t prec_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
 
+int launch_blocks(const Lat &lat, int W) {
+    int logW = 0;
+    while ((1 << logW) < W) ++logW;
+    const int ntiles = (lat.N + (kBlock >> logW) - 1) / (kBlock >> logW);
+    // one right-hand side: the stencil splits a site over 32 threads, eight
+    // sites per workgroup, so the launch takes up to N / 8 workgroups (the
+    // other kernels leave the extra ones idle)
+    return grid_blocks(W == 1 ? std::max(ntiles, (lat.N + 7) / 8) : ntiles);
+}
+
+size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W) {
+    const size_t N = (size_t)lat.N, vec = N * nc * W, lo = vec * prec_bytes(inner);
+    switch (slot) {
+        case kSlotNbr: return N * 8 * sizeof(int);
+        case kSlotU64: return links ? N * 4 * nc * nc * 16 : 0;
+        case kSlotU8: return links ? 2 * N * 4 * nc * nc * prec_bytes(inner) : 0;
+        case kSlotB64:
+        case kSlotX64: return vec * 16;
+        case kSlotR:
+        case kSlotP:
+        case kSlotQ: return lo;
+        case kSlotXLo: return inner != kF64 ? lo : 0;
+        case kSlotPart1: return (size_t)launch_blocks(lat, W) * W * 2 * sizeof(double);
+        case kSlotState: return state_bytes();
+        default: return 0;
+    }
+}
+
 dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep &out, hipStream_t s) {
     for (int d = 0; d < 4; ++d)
         if (op.dims[d] < 1) {
@@ -172,15 +200,15 @@ dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep
     out.m2 = op.m2;
     out.links = op.links != nullptr;
     out.inner = inner;
-    DP_TRY(ctx->ensure(kSlotNbr, (size_t)N * 8 * sizeof(int)));
+    auto sz = [&](int slot) { return slot_size(slot, out.lat, op.nc, out.links, inner, 1); };
+    DP_TRY(ctx->ensure(kSlotNbr, sz(kSlotNbr)));
     build_neighbours(out.lat, (int *)ctx->at(kSlotNbr), s);
     out.nbr = (const int *)ctx->at(kSlotNbr);
     if (out.links) {
-        const size_t nl = (size_t)N * 4 * op.nc * op.nc;
-        DP_TRY(ctx->ensure(kSlotU64, nl * 16));
+        DP_TRY(ctx->ensure(kSlotU64, sz(kSlotU64)));
         convert_links(kF64, out.lat, op.nc, op.links, ctx->at(kSlotU64), s);
         out.U64 = ctx->at(kSlotU64);
-        DP_TRY(ctx->ensure(kSlotU8, 2 * nl * prec_bytes(inner)));
+        DP_TRY(ctx->ensure(kSlotU8, sz(kSlotU8)));
         gather_links(inner, out.lat, op.nc, op.links, out.nbr, ctx->at(kSlotU8), s);
         out.U8 = ctx->at(kSlotU8);
     }
@@ -197,24 +225,15 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     L.W = W;
     L.logW = logW;
     L.ntiles = (op.lat.N + (kBlock >> logW) - 1) / (kBlock >> logW);
-    // one right-hand side: the stencil splits a site over 32 threads, eight
-    // sites per workgroup, so the launch takes up to N / 8 workgroups (the
-    // other kernels leave the extra ones idle)
-    L.nblk = grid_blocks(W == 1 ? std::max(L.ntiles, (op.lat.N + 7) / 8) : L.ntiles);
+    L.nblk = launch_blocks(op.lat, W);
     L.stream = s;
-    const size_t vec = (size_t)op.lat.N * op.nc * W;
-    const size_t lo = vec * prec_bytes(cfg.inner);
-    DP_TRY(ctx->ensure(kSlotB64, vec * 16));
-    DP_TRY(ctx->ensure(kSlotX64, vec * 16));
-    DP_TRY(ctx->ensure(kSlotR, lo));
-    DP_TRY(ctx->ensure(kSlotP, lo));
-    DP_TRY(ctx->ensure(kSlotQ, lo));
-    if (cfg.inner != kF64) DP_TRY(ctx->ensure(kSlotXLo, lo));
-    DP_TRY(ctx->ensure(kSlotPart1, (size_t)L.nblk * W * 2 * sizeof(double)));
+    for (int slot : {kSlotB64, kSlotX64, kSlotR, kSlotP, kSlotQ, kSlotXLo, kSlotPart1, kSlotState}) {
+        const size_t b = slot_size(slot, op.lat, op.nc, op.links, cfg.inner, W);
+        if (b) DP_TRY(ctx->ensure(slot, b));
+    }
     rd.part1 = (double *)ctx->at(kSlotPart1);
     rd.nblk = L.nblk;
-    const size_t nd = 9 * kMaxW + 8, ni = 3 * kMaxW + 8;
-    DP_TRY(ctx->ensure(kSlotState, nd * sizeof(double) + ni * sizeof(int)));
+    const size_t nd = 9 * kMaxW + 8;
     double *d = (double *)ctx->at(kSlotState);
     cs.rr = d;
     cs.rr_prev = d + kMaxW;
@@ -316,6 +335,48 @@ void block_stats(const void *state, BlockStats &bs, dp_solve_stats *acc) {
     }
 }
 
+// Every argument a captured iteration group passes to its kernels, as a
+// lookup key of the graph cache.
+static std::string graph_key(int steps, int inner, const Launch &L, const StencilArgs &a, const void *r,
+                             const void *xlo) {
+    std::string k;
+    auto put = [&k](const void *v, size_t n) { k.append((const char *)v, n); };
+    auto val = [&put](auto v) { put(&v, sizeof v); };
+    val(steps);
+    val(inner);
+    for (int d = 0; d < 4; ++d) val(L.lat.D[d]);
+    val(L.lat.N);
+    val(L.nc);
+    val(L.W);
+    val(L.logW);
+    val(L.nblk);
+    val(L.ntiles);
+    val((const void *)L.stream);
+    val(a.links);
+    val(a.diag);
+    val(a.pin);
+    val(a.q);
+    val(a.U);
+    val((const void *)a.nbr);
+    val(a.cg);
+    val((const void *)a.rd.part1);
+    val(a.rd.nblk);
+    const CgState &c = a.cs;
+    for (const void *ptr : {(const void *)c.rr, (const void *)c.rr_prev, (const void *)c.rr_ref,
+                            (const void *)c.bb, (const void *)c.alpha, (const void *)c.beta,
+                            (const void *)c.true_rr, (const void *)c.tj, (const void *)c.active,
+                            (const void *)c.iters, (const void *)c.flags, (const void *)c.ctrl,
+                            (const void *)c.ctrld})
+        val(ptr);
+    val(c.tol2);
+    val(c.delta2);
+    val(c.exact);
+    val(c.hold);
+    val(r);
+    val(xlo);
+    return k;
+}
+
 template <typename Init>
 dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
                       const CgState &cs, double *x64, Init init, BlockStats &bs, dp_solve_stats *acc,
@@ -352,9 +413,15 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     while (nactive > 0 && it < cfg.max_iter) {
         const int steps = std::min(steps_next, cfg.max_iter - it);
         if (cfg.use_graph && pending && !cfg.profile) {
-            // the group [update2, stencil, update1] x steps replayed from a graph
-            auto g = ctx->graphs.find(steps);
+            // the group [update2, stencil, update1] x steps replayed from a
+            // graph; a graph holds the kernel arguments it was captured with,
+            // so it is looked up by all of them (two solves of one call, say
+            // the forward and adjoint solves of a gradient, or instances of
+            // different shapes, never share a graph)
+            const std::string key = graph_key(steps, cfg.inner, L, a, r, xlo);
+            auto g = ctx->graphs.find(key);
             if (g == ctx->graphs.end()) {
+                if (ctx->graphs.size() >= 64) ctx->drop_graphs();
                 hipGraph_t graph = nullptr;
                 hipGraphExec_t exec = nullptr;
                 DP_HIP(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal));
@@ -367,7 +434,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
                 const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 DP_HIP(ie);
-                g = ctx->graphs.emplace(steps, exec).first;
+                g = ctx->graphs.emplace(key, exec).first;
             }
             DP_HIP(hipGraphLaunch(g->second, L.stream));
         } else {
@@ -430,17 +497,16 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     return DP_OK;
 }
 
-// Autotuner of the right-hand-side block width W: for each candidate W
-// (powers of two from 8 to 128, not above the next power of two of nrhs,
-// within a memory budget) a block of dense random right-hand sides runs
-// 2 + 6 CG iterations of the real kernels; the 6 are timed with HIP events
-// and the cost per useful right-hand side and iteration,
-// time / min(W, nrhs), decides.  For a batch of instances the cost is
-// time / W times the padded share of the work, sum ceil(n_i / W) W N_i over
-// sum n_i N_i (n_i right-hand sides on N_i sites).  Choices (single
-// instance) and timings in nanoseconds (batches) are cached per (N, nc,
+// Autotuner of the right-hand-side block width W (one instance): for each
+// candidate W (powers of two from 8 to 128, not above the next power of two
+// of nrhs, within a memory budget) a block of dense random right-hand sides
+// runs 2 + 6 CG iterations of the real kernels; the 6 are timed with HIP
+// events and the cost per useful right-hand side and iteration,
+// time / min(W, nrhs), decides.  The choices are cached per (N, nc,
 // precision, links, next power of two of nrhs) in the context, and in the
-// JSON file named by DP_TUNE_CACHE when that variable is set.
+// JSON file named by DP_TUNE_CACHE when that variable is set.  A batch of
+// instances is not timed: its width comes from a traffic model (see
+// choose_width).
 static std::string tune_key(const OpPrep &op, const SolveCfg &cfg, long long nrhs) {
     long long b = 1;
     while (b < nrhs && b < kMaxW) b *= 2;

@@ -41,6 +41,18 @@ def test_mix64_is_a_bijection_on_a_sample_and_fixes_zero():
     assert len(vals) == 4999
 
 
+def test_mix64_is_the_splitmix64_output_function():
+    """The noise hash is SplitMix64's output function (Steele, Lea and
+    Flood, OOPSLA 2014): the generator seeded with 0 adds the golden-ratio
+    increment 0x9E3779B97F4A7C15 to its state and outputs mix64(state); its
+    published first outputs are reproduced exactly."""
+    gamma = 0x9E3779B97F4A7C15
+    published = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC,
+                 0x1B39896A51A8749B]
+    for i, want in enumerate(published, start=1):
+        assert oracle.mix64((gamma * i) % 2 ** 64) == want
+
+
 @pytest.mark.parametrize("kind", [oracle.REAL_Z2, oracle.Z2_COMPLEX, oracle.Z4])
 def test_noise_statistics(kind):
     """Rademacher / Z4 noise (Sec. 2): mean 0, E|z|^2 = 1 after the
