@@ -322,6 +322,35 @@ dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *op, int32_t p, const dp_
                         void *dT_dU, void *dT_dUbar, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * single-instance solve of dp_solve_batch (same kernels, same results) with
+ * every workspace buffer in one static device array of
+ * DP_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on holds
+ * until the process ends.  The call allocates nothing: no hipMalloc, no
+ * hipFree, no pool, graph or event.
+ *   op     host dp_operator (one instance).
+ *   b      device complex128 [nrhs][N][nc], caller-owned, read.
+ *   x      device complex128 [nrhs][N][nc], caller-owned, written.
+ *   o      as dp_solve_batch, except that use_graph and profile must be 0
+ *          (DP_EINVAL otherwise) and rhs_block = 0 takes the widest power of
+ *          two <= 32 (and <= the next power of two of nrhs) whose workspace
+ *          fits, without timing; an explicit rhs_block must fit.
+ *   st     host dp_solve_stats, written (may be NULL).
+ * DP_EINVAL, with the bytes needed in the message, when the workspace of the
+ * lattice at that width exceeds the array.  The workspace is, per site,
+ * 32 (neighbours) + [links] 4 nc^2 (16 + 2 s) + W nc (32 + 3 s (+ s mixed))
+ * bytes, s = 16 / 8 / 4 for F64 / F32 / BF16, plus 16 W per workgroup and
+ * 22 KB of per-lane state: e.g. an 8^4 x 3 lattice with links at F32,
+ * W = 32 takes about 30 MB.  Every call on one GPU uses that GPU's single
+ * array (each call writes every part of it it reads, so no earlier contents
+ * matter): calls that overlap on one GPU, from two host threads or two
+ * contexts, race and must not be made. */
+#define DP_NOALLOC_SCRATCH_BYTES (64ull << 20)
+dp_status dp_solve_noalloc(dp_ctx *ctx, const dp_operator *op, const void *b, void *x, int64_t nrhs,
+                           const dp_solve_opts *o, dp_solve_stats *st, hipStream_t stream);
+
+/*
  * y = A v for nrhs vectors with the stencil kernel of the given storage
  * precision (DP_PREC_*): inputs are rounded to that precision, the result is
  * returned in complex128.  v, y: device complex128 [nrhs][N][nc].

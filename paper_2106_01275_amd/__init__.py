@@ -82,7 +82,7 @@ class EigOpts(ctypes.Structure):
 EXPORTS = ["dp_create", "dp_destroy", "dp_last_error", "dp_build_coloring", "dp_build_coloring_multi",
            "dp_tile_shape", "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
            "dp_trace_estimate", "dp_trace_multi", "dp_trace_levels", "dp_trace_grad", "dp_apply",
-           "dp_deflation_create",
+           "dp_solve_noalloc", "dp_deflation_create",
            "dp_deflation_info", "dp_deflation_vectors", "dp_trace_deflated", "dp_deflation_destroy"]
 
 _lib = None
@@ -118,6 +118,8 @@ def lib():
         L.dp_trace_grad.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(ProbeSpec),
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(TraceResult), vp, vp, vp, vp]
         L.dp_apply.argtypes = [vp, ctypes.POINTER(Operator), i32, vp, vp, i64, vp]
+        L.dp_solve_noalloc.argtypes = [vp, ctypes.POINTER(Operator), vp, vp, i64, ctypes.POINTER(SolveOpts),
+                                       ctypes.POINTER(SolveStats), vp]
         L.dp_deflation_create.argtypes = [vp, ctypes.POINTER(Operator), i32, ctypes.POINTER(EigOpts),
                                           ctypes.POINTER(vp), vp]
         L.dp_deflation_info.argtypes = [vp, vp, vp, vp, vp]
@@ -129,7 +131,7 @@ def lib():
         for name in ("dp_create", "dp_build_coloring", "dp_build_coloring_multi", "dp_tile_shape",
                      "dp_build_coloring_tiled", "dp_clearance", "dp_make_probes", "dp_solve_batch",
                      "dp_trace_estimate", "dp_trace_multi", "dp_trace_levels", "dp_trace_grad", "dp_apply",
-                     "dp_deflation_create", "dp_deflation_info", "dp_deflation_vectors", "dp_trace_deflated"):
+                     "dp_solve_noalloc", "dp_deflation_create", "dp_deflation_info", "dp_deflation_vectors", "dp_trace_deflated"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -473,6 +475,22 @@ class Context:
         if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
             self._err(st, out)
         return out
+
+    def solve_noalloc(self, op, b, opts, x=None, check=True):
+        """One instance, b: complex128 [nrhs, N, nc]; the library allocates
+        nothing (its workspace is a static device array)."""
+        torch = self.torch
+        if x is None:
+            x = torch.empty_like(b)
+        m = b.shape[0] * int(np.prod(list(op.dims))) * op.nc if min(op.dims) >= 1 else None
+        stats = SolveStats()
+        st = lib().dp_solve_noalloc(self.h, ctypes.byref(op), self._cdev(b, torch.complex128, m),
+                                    self._cdev(x, torch.complex128, m), b.shape[0], ctypes.byref(opts),
+                                    ctypes.byref(stats), self._stream())
+        res = (x, stats.asdict())
+        if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
+            self._err(st, res)
+        return res
 
     def apply(self, op, v, prec="f64"):
         torch = self.torch

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "solver.cpp", "api.cpp", "coloring.cpp", "batch.cpp", "deflation.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "solver.cpp", "api.cpp", "coloring.cpp", "batch.cpp", "deflation.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

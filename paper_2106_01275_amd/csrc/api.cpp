@@ -161,6 +161,7 @@ dp_status dp_create(dp_ctx **out, int32_t hip_device) {
         g_err = "dp_create: hipSetDevice failed";
         return DP_EHIP;
     }
+    if (noalloc_attach(hip_device, g_err) != DP_OK) return DP_EHIP;
     dp_ctx *ctx = new (std::nothrow) dp_ctx();
     if (!ctx) {
         g_err = "dp_create: out of host memory";

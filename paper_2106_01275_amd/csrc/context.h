@@ -81,6 +81,10 @@ struct dp_ctx {
     size_t pinned_bytes = 0;
     dp_status host_pinned(size_t bytes, void **out);  // at least `bytes`, kept for later calls
 
+    // set while a call runs on the static scratch array (dp_solve_noalloc):
+    // ensure() and pool_get() then fail instead of allocating or freeing
+    bool no_alloc = false;
+
     void drop_graphs();
     // smallest pooled buffer of at least `bytes`, else a new one; *got = its size
     dp_status pool_get(size_t bytes, void **out, size_t *got);
@@ -104,6 +108,9 @@ struct SolveCfg {
 };
 
 dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep &out, hipStream_t s);
+// Looks up (once per device, with `device` current) the device address of
+// the static scratch array of dp_solve_noalloc.
+dp_status noalloc_attach(int device, std::string &err);
 // workgroups of a single-instance launch at width W
 int launch_blocks(const Lat &lat, int W);
 // bytes of workspace slot `slot` that prepare_operator and make_launch need

@@ -31,6 +31,11 @@
 dp_status dp_ctx::ensure(int s, size_t bytes, bool zero) {
     if (bytes == 0) bytes = 256;
     if (slot_bytes[s] >= bytes) return DP_OK;
+    if (no_alloc) {
+        err = "internal: workspace slot " + std::to_string(s) + " needs " + std::to_string(bytes) +
+              " bytes beyond the static scratch layout";
+        return DP_ENOMEM;
+    }
     dp_ctx *ctx = this;
     if (slot[s]) DP_HIP(hipFree(slot[s]));
     slot[s] = nullptr;
@@ -48,6 +53,10 @@ dp_status dp_ctx::ensure(int s, size_t bytes, bool zero) {
 
 dp_status dp_ctx::pool_get(size_t bytes, void **out, size_t *got) {
     if (bytes == 0) bytes = 256;
+    if (no_alloc) {
+        err = "internal: pooled buffer requested by a call that may not allocate";
+        return DP_ENOMEM;
+    }
     size_t best = pool.size();
     for (size_t i = 0; i < pool.size(); ++i)
         if (pool[i].second >= bytes && (best == pool.size() || pool[i].second < pool[best].second)) best = i;
