@@ -361,8 +361,8 @@ dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, con
         DP_TRY(choose_width(ctx, op, cfg, nrhs[i], o->rhs_block, stream, W));
         s.rhs_block = W;
         Launch L;
-        Red rd;
-        CgState cs;
+        Red rd{};
+        CgState cs{};
         DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
         for (long long r0 = 0; r0 < nrhs[i]; r0 += W) {
             const long long nv = std::min<long long>(W, nrhs[i] - r0);
@@ -468,8 +468,8 @@ static dp_status trace_displacements(dp_ctx *ctx, const dp_operator &opd, const 
     int W = 1;
     DP_TRY(choose_width(ctx, op, cfg, nrhs, o->rhs_block, stream, W));
     Launch L;
-    Red rd;
-    CgState cs;
+    Red rd{};
+    CgState cs{};
     DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
     dp_solve_stats s{};
     s.rhs_block = W;
@@ -698,8 +698,8 @@ dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *opd, int32_t p, const dp
     int W = 1;
     DP_TRY(choose_width(ctx, op, cfg, nrhs, o->rhs_block, stream, W));
     Launch L;
-    Red rd;
-    CgState cs;
+    Red rd{};
+    CgState cs{};
     DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
     DP_TRY(ctx->ensure(kSlotX64b, (size_t)op.lat.N * op.nc * W * 16));
     double *xsol = (double *)ctx->at(kSlotX64b);
@@ -774,8 +774,8 @@ dp_status dp_apply(dp_ctx *ctx, const dp_operator *opd, int32_t prec, const void
     int W = 1;
     while (W < nrhs && W < 64) W *= 2;
     Launch L;
-    Red rd;
-    CgState cs;
+    Red rd{};
+    CgState cs{};
     DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
     for (long long r0 = 0; r0 < nrhs; r0 += W) {
         const long long nv = std::min<long long>(W, nrhs - r0);
@@ -893,8 +893,8 @@ dp_status dp_trace_deflated(dp_ctx *ctx, const dp_operator *opd, const dp_deflat
     int W = 1;
     DP_TRY(choose_width(ctx, op, cfg, nrhs, o->rhs_block, stream, W));
     Launch L;
-    Red rd;
-    CgState cs;
+    Red rd{};
+    CgState cs{};
     DP_TRY(make_launch(ctx, op, W, stream, L, rd, cs, cfg));
     dp_solve_stats s{};
     s.rhs_block = W;

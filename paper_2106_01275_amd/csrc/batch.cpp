@@ -102,7 +102,8 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     // memory budget
     const size_t vec = (size_t)maxN * nc * W;
     const size_t lo = vec * prec_bytes(cfg.inner);
-    const size_t part_bytes = (size_t)W * kSlotMaxBlk * 2 * sizeof(double);
+    // partial sums: the stencil's four per lane and workgroup, then |r|^2 and Re q^H p
+    const size_t part_bytes = (size_t)W * kSlotMaxBlk * 6 * sizeof(double);
     const size_t slot_bytes = vec * 32 + lo * (mixed ? 4 : 3) + part_bytes;
     int slot_cap = std::min(kMaxSlots, std::max(64, 8192 / W));
     slot_cap = (int)std::min<size_t>(slot_cap, std::max<size_t>(1, kSlotBudget / slot_bytes));
@@ -147,10 +148,11 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         else
             d.xlo = d.x64;
         DP_TRY(mem.alloc(ctx, (void **)&d.rd.part1, part_bytes));
+        d.rd.part2 = d.rd.part1 + (size_t)W * kSlotMaxBlk * 4;
         double *st = (double *)(st_all + st_stride * k);
         CgState &cs = d.cs;
         cs.rr = st;
-        cs.rr_prev = st + kMaxW;
+        cs.qp = st + kMaxW;
         cs.rr_ref = st + 2 * kMaxW;
         cs.bb = st + 3 * kMaxW;
         cs.alpha = st + 4 * kMaxW;
@@ -166,6 +168,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         cs.tol2 = cfg.tol * cfg.tol;
         cs.delta2 = cfg.delta * cfg.delta;
         cs.hold = cfg.inner == kBF16;
+        cs.rq_direct = cfg.inner == kBF16;
         cs.exact = !mixed;
     }
     std::vector<int> slot_of((size_t)gblk, nslots);
@@ -261,10 +264,16 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         for (int w = b0; w < gblk; ++w) slot_of[w] = nslots;
         return true;
     };
+    // The |r|^2 partial sums of a slot's last vector update, which the next
+    // CG iteration adds up, are laid out by its number of workgroups: when
+    // the sharing changes they are rebuilt from the lane totals (cs.rr, set
+    // by the check that preceded every change).
     auto upload = [&]() -> dp_status {
-        if (balance())
+        const bool reshared = balance();
+        if (reshared)
             DP_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int) * slot_of.size(), hipMemcpyHostToDevice, s));
         DP_HIP(hipMemcpyAsync(d_sd, hsd.data(), sizeof(SlotDesc) * (nslots + 1), hipMemcpyHostToDevice, s));
+        if (reshared) launch_b_reseed(B);
         return DP_OK;
     };
     // initialise the slots flagged kSlotInit, then make them iterate
@@ -360,7 +369,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
                 hipGraph_t graph = nullptr;
                 hipGraphExec_t exec = nullptr;
                 DP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                for (int c = 0; c < steps; ++c) launch_b_iteration(B, true);
+                for (int c = 0; c < steps; ++c) launch_b_iteration(B);
                 DP_HIP(hipStreamEndCapture(s, &graph));
                 const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
@@ -369,15 +378,13 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             }
             DP_HIP(hipGraphLaunch(g->second, s));
         } else {
-            // update2 on a freshly initialised slot is harmless: alpha = beta = 0 and p = r = b
             double bytes = 0;
             for (int k = 0; k < nslots; ++k)
                 if (hsd[k].flags & kSlotIter) bytes += stencil_alg_bytes(hsd[k].L.lat, nc, W, cfg.inner, B.links);
             for (int c = 0; c < steps; ++c) {
-                launch_b_update2(B);
                 DP_TRY(timed_launch(ctx, cfg.profile != 0, bytes,
                                     [&](hipEvent_t e0, hipEvent_t e1) { launch_b_stencil(B, e0, e1); }));
-                launch_b_update1(B);
+                launch_b_update(B);
             }
         }
         DP_HIP(hipGetLastError());

@@ -175,8 +175,9 @@ dp_status deflation_build(dp_ctx *ctx, const dp_operator &opd, int nvec, const d
     cs.tj = D.scratch;
     cs.true_rr = D.scratch + 2 * W;
     cs.alpha = D.scratch + 3 * W;
-    Red rd;
+    Red rd{};
     rd.part1 = D.scratch + 4 * W;
+    rd.part2 = nullptr;  // (no CG here)
     rd.nblk = L.nblk;
 
     // spectral bounds: A = (m2 + 8) - H with |H| <= max over sites of the
@@ -343,8 +344,9 @@ dp_status deflation_trace_part(dp_ctx *ctx, const dp_deflation &d, int p, hipStr
     cs.tj = d.scratch;
     cs.true_rr = d.scratch + 2 * d.W;
     cs.alpha = d.scratch + 3 * d.W;
-    Red rd;
+    Red rd{};
     rd.part1 = d.scratch + 4 * d.W;
+    rd.part2 = nullptr;  // (no CG here)
     rd.nblk = L.nblk;
     launch_dot_shift(L, d.V, d.V, p, rd, cs);
     std::vector<double> tj(2 * d.W);

@@ -29,15 +29,21 @@ dp_status clearance(const int32_t dims[4], const int32_t *colors, int32_t p, int
 constexpr int kBlock = 256;      // threads per workgroup of every lattice kernel
 constexpr int kMaxW = 256;       // largest right-hand-side block width
 
-// Per-workgroup partial sums of a reduction, [W][nblk][NV].
+// Per-workgroup partial sums of the reductions.  part1 [W][nblk][NV] (NV <=
+// 4): the stencil's p^H q, r^H q, |q|^2, r^H p of a CG iteration (r^H q and
+// r^H p with BF16 storage only), and the other dot products; part2 [W][nblk][2]: |r|^2 and
+// Re q^H p of the residual and direction that the last vector update,
+// initialisation or reliable update wrote (q = A p of the direction before;
+// the next finishing kernel of the CG iteration adds them up).
 struct Red {
     double *part1;
+    double *part2;
     int nblk;
 };
 
 // Per-right-hand-side CG state of one block of W right-hand sides (device).
 struct CgState {
-    double *rr, *rr_prev, *rr_ref, *bb, *alpha, *beta, *true_rr;
+    double *rr, *qp, *rr_ref, *bb, *alpha, *beta, *true_rr;  // qp: Re q^H p total of part2
     double *tj;          // [W][2] contraction results / dot products
     int *active, *iters, *flags;
     int *ctrl;           // [0] active, [1] candidates, [2] need reliable update, [3] breakdowns
@@ -45,6 +51,9 @@ struct CgState {
     double tol2, delta2;
     int exact;           // 1: FP64 inner solve (no reliable updates)
     int hold;            // 1: lanes due a reliable update wait for it (BF16 storage)
+    int rq_direct;       // 1 exactly for BF16 storage, whose stencil sums r^H q and
+                         //    r^H p itself; 0: the finishing kernel forms r^H q from
+                         //    p^H q and Re q^H p
 };
 
 // kFlagRestart (mixed precision): p^H A p <= 0 in low precision; the next
@@ -115,10 +124,12 @@ struct BatchLaunch {
     hipStream_t stream;
 };
 void launch_b_init(const BatchLaunch &B, int mixed);
-void launch_b_iteration(const BatchLaunch &B, bool update2);
-void launch_b_update2(const BatchLaunch &B);
+void launch_b_iteration(const BatchLaunch &B);
+// the stencil with its three dot products (ev0/ev1: its own start and stop)
 void launch_b_stencil(const BatchLaunch &B, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_b_update1(const BatchLaunch &B);  // with the alpha and beta epilogues
+void launch_b_update(const BatchLaunch &B);  // the finishing kernel, then the vector update
+// iterating slots: |r|^2 partials rebuilt from cs.rr (after a new sharing of the workgroups)
+void launch_b_reseed(const BatchLaunch &B);
 void launch_b_ru(const BatchLaunch &B, int final_stats);
 void launch_b_dot(const BatchLaunch &B);
 void launch_b_ctrl(const BatchLaunch &B);
@@ -137,11 +148,14 @@ void launch_init_probe(const Launch &L, int prec, const ProbeGen &g, double *b64
 void launch_init_abi(const Launch &L, int prec, const double *babi, long long rhs0, long long nvalid,
                      double *b64, void *r, void *p, void *xlo, double *x64, int mixed, const Red &rd,
                      const CgState &cs);
-// Arguments of the stencil launch: q = A pin, with p^H q and alpha when cg.
+// Arguments of the stencil launch: q = A pin; with cg (a CG iteration) also
+// p^H q and |q|^2 per lane (BF16 storage: r^H q and r^H p too, rin = r), then
+// the finishing kernel that forms alpha, the new |r|^2 and beta.
 struct StencilArgs {
     bool links = false;
     double diag = 0;
     const void *pin = nullptr;
+    const void *rin = nullptr;
     void *q = nullptr;
     const void *U = nullptr;     // hop links [N][8][nc][nc] (gather_links)
     const int *nbr = nullptr;
@@ -151,15 +165,20 @@ struct StencilArgs {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // if set: the stencil kernel's own start and stop times
 };
 void launch_stencil(const Launch &L, int prec, const StencilArgs &a);
-void launch_update1(const Launch &L, int prec, void *r, const void *q, const Red &rd, const CgState &cs);
-// x += alpha p (deferred), p = r + beta p
-void launch_update2(const Launch &L, int prec, const void *r, void *p, void *x, const CgState &cs);
-// x64 += xlo + alpha p, xlo = 0 (xlo null: FP64, x64 += alpha p)
-void launch_fold(const Launch &L, int prec, double *x64, void *xlo, const void *p, const CgState &cs);
-// gen set: b is regenerated from those probes instead of read from b64
+// The vector update of a CG iteration: x += alpha p, r -= alpha q,
+// p = r + beta p, and |r|^2 per lane into rd.part2
+void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const void *q, const Red &rd,
+                   const CgState &cs);
+// x64 += xlo, xlo = 0 (mixed precision)
+void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
+// FP64 true residual b - A x64 (gen set: b is regenerated from those probes
+// instead of read from b64).  ru_mode 1 (reliable update): r becomes it, p
+// is continued from it (FP32) or kept (BF16; restarted as r for lanes
+// flagged to restart), then the reliable-update epilogue; ru_mode 0: only
+// its norm, for the statistics.  q: A p_prev, read by the FP32 continuation.
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
-                       const double *x64, const void *U64, const int *nbr, void *r, int ru_mode,
-                       const Red &rd, const CgState &cs, const ProbeGen *gen = nullptr);
+                       const double *x64, const void *U64, const int *nbr, void *r, void *p, const void *q,
+                       int ru_mode, const Red &rd, const CgState &cs, const ProbeGen *gen = nullptr);
 // cmap[c] = the coarse colour of the sites of fine colour c (-1 for a colour
 // no site has); *bad set to 1 when a colour is out of range or two sites of
 // one fine colour have different coarse colours (not nested).
@@ -171,7 +190,9 @@ void launch_dot(const Launch &L, const double *a64, const double *b64, const Red
                 const CgState &cs);
 void launch_force(const Launch &L, const double *x64, const double *l64, const int *nbr, double scale,
                   int first, double *dU, double *dUbar);
-void launch_ctrl(const CgState &cs, int W, hipStream_t s);
+// |r|^2 of every lane from rd.part2 (and, FP64, its convergence), then the
+// control word
+void launch_ctrl(const Red &rd, const CgState &cs, int W, hipStream_t s);
 
 // Deflation (dense pieces over FP64 blocks [n rows][width], internal layout)
 // r = p = b read from b64 in place, xlo = 0, |b|^2 (the init of probes that

@@ -264,58 +264,62 @@ __device__ __forceinline__ void probe_value(const ProbeGen &g, unsigned long lon
 // ------------------------------------------------------------ reductions
 
 // Writes this workgroup's sums of NV values per lane to
-// part[(lane * nblk + b) * NV + v] (all threads call it once).
+// dst[(lane * nblk + b) * NV + v] (all threads call it once).
+// Lane j = tid % W: the threads of one lane inside a wavefront are summed by
+// a butterfly over the thread-index bits above log2 W, then the wavefronts
+// in order through LDS (sm: NV * kBlock doubles); a fixed order.
 template <int NV>
-__device__ void block_partials(const Blk &bk, const double (&val)[NV], int W, int logW, const Red &rd, double *sm) {
+__device__ void block_partials_to(const Blk &bk, const double (&val)[NV], int W, int logW, double *dst, int nblk,
+                                  double *sm) {
     const int tid = threadIdx.x;
-    const int spl = kBlock >> logW;  // threads per lane
+    double v_[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sm[v * kBlock + tid] = val[v];
+    for (int v = 0; v < NV; ++v) {
+        v_[v] = val[v];
+        for (int off = W; off < 64; off <<= 1) v_[v] += __shfl_xor(v_[v], off, 64);
+    }
+    // per wavefront, threads 0 .. min(W, 64) - 1 hold the sums of their lanes
+    const int per_wave = W < 64 ? W : 64;
+    const int lane_in_wave = tid & 63;
+    if (lane_in_wave < per_wave) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sm[v * kBlock + (tid >> 6) * per_wave + lane_in_wave] = v_[v];
+    }
     __syncthreads();
     if (tid < W) {
+        // lane tid's wavefront sums: W < 64: one per wavefront at
+        // w * W + tid; W >= 64: the wavefronts w with w * 64 + (tid % 64) = tid
+        // mod W, i.e. entries tid, tid + W, ... of the packed array
+        const int nsum = W < 64 ? kBlock / 64 : kBlock / W;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double s = 0.0;
-            for (int k = 0; k < spl; ++k) s += sm[v * kBlock + k * W + tid];
-            rd.part1[((size_t)tid * rd.nblk + bk.b) * NV + v] = s;
+            for (int k = 0; k < nsum; ++k) s += sm[v * kBlock + k * W + tid];
+            dst[((size_t)tid * nblk + bk.b) * NV + v] = s;
         }
     }
 }
 
-enum Epi { kEpiInit, kEpiAlpha, kEpiBeta, kEpiRU, kEpiStats, kEpiTj };
+// the same into rd.part1
+template <int NV>
+__device__ void block_partials(const Blk &bk, const double (&val)[NV], int W, int logW, const Red &rd, double *sm) {
+    block_partials_to<NV>(bk, val, W, logW, rd.part1, rd.nblk, sm);
+}
 
-// One workgroup per lane: total of the lane's partials (fixed order), then
-// the scalar epilogue of that lane.
-template <int NV, int EPI>
-__device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgState &cs) {
+// Total over the nblk partial sums of one lane, src = the lane's [nblk][NV]
+// block, in a fixed order (the same on every call): thread tid adds
+// partials tid, tid + kBlock, ... (four loads in flight), then a butterfly
+// in each wavefront and the wavefronts in order.  All threads call it; the
+// totals are valid in thread 0.  sm: NV * kBlock / 64 doubles.
+template <int NV>
+__device__ __forceinline__ void lane_total(const double *src, int nblk, double (&tot)[NV], double *sm) {
     constexpr int kWaves = kBlock / 64;
-    __shared__ double sm[NV * kWaves];
     const int tid = threadIdx.x;
-    const double *src = rd.part1 + (size_t)lane * rd.nblk * NV;
-    const int j = lane;
-    // the lane's state that the epilogue reads, loaded before the partials
-    // so that the two loads' latencies overlap (only this workgroup's
-    // thread 0 reads or writes lane j's state)
-    constexpr bool kState = EPI == kEpiAlpha || EPI == kEpiBeta || EPI == kEpiRU;
-    double st_rr = 0.0, st_prev = 0.0, st_ref = 0.0, st_bb = 0.0;
-    int st_active = 0, st_flags = 0, st_iters = 0;
-    if (kState && tid == 0) {
-        st_rr = cs.rr[j];
-        st_prev = cs.rr_prev[j];
-        st_ref = cs.rr_ref[j];
-        st_bb = cs.bb[j];
-        st_active = cs.active[j];
-        st_flags = cs.flags[j];
-        st_iters = cs.iters[j];
-    }
-    // thread tid adds partials tid, tid + kBlock, ... (four loads in flight),
-    // then a fixed butterfly in each wavefront and the wavefronts in order:
-    // the same summation order on every call
     double s[NV], s2[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) s[v] = s2[v] = 0.0;
     int b = tid;
-    for (; b + 3 * kBlock < rd.nblk; b += 4 * kBlock) {
+    for (; b + 3 * kBlock < nblk; b += 4 * kBlock) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double a0 = src[(size_t)b * NV + v], a1 = src[(size_t)(b + kBlock) * NV + v];
@@ -324,7 +328,7 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
             s2[v] += a2 + a3;
         }
     }
-    for (; b < rd.nblk; b += kBlock) {
+    for (; b < nblk; b += kBlock) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) s[v] += src[(size_t)b * NV + v];
     }
@@ -335,18 +339,54 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
         if ((tid & 63) == 0) sm[v * kWaves + tid / 64] = x;
     }
     __syncthreads();
-    if (tid != 0) return;
-    double tot[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         tot[v] = 0.0;
         for (int w = 0; w < kWaves; ++w) tot[v] += sm[v * kWaves + w];
     }
+}
+
+// Epilogues of the finishing kernels.  Those marked (part2, NV = 2) total
+// the |r|^2 and Re q^H p partials of the last vector update, initialisation
+// or reliable update; kEpiTj and kEpiStatsP1 total rd.part1.
+enum Epi { kEpiInit, kEpiCheck, kEpiRU, kEpiStats, kEpiStatsP1, kEpiTj };
+
+// One workgroup per lane: total of the lane's partials (fixed order), then
+// the scalar epilogue of that lane (thread 0; only this workgroup reads or
+// writes lane j's state).
+//   kEpiInit (part2)   |b|^2: the lane's CG state from scratch
+//   kEpiCheck (part2)  |r|^2 of the latest residual into rr; FP64: lanes
+//                      that meet tol stop (before a host check)
+//   kEpiRU (part2)     the FP64 true residual of a reliable update
+//   kEpiStats (part2), kEpiStatsP1 (part1)  a norm into true_rr only
+//   kEpiTj (part1, NV = 2)  a complex dot product into tj
+template <int NV, int EPI>
+__device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgState &cs) {
+    __shared__ double sm[NV * kBlock / 64];
+    const int tid = threadIdx.x;
+    constexpr bool kPart2 = EPI == kEpiInit || EPI == kEpiCheck || EPI == kEpiRU || EPI == kEpiStats;
+    static_assert(!kPart2 || NV == 2, "part2 holds two values per lane and workgroup");
+    const double *src = (kPart2 ? rd.part2 : rd.part1) + (size_t)lane * rd.nblk * NV;
+    const int j = lane;
+    // the lane's state that the epilogue reads, loaded before the partials
+    // so that the two loads' latencies overlap
+    constexpr bool kState = EPI == kEpiCheck || EPI == kEpiRU;
+    double st_ref = 0.0, st_bb = 0.0;
+    int st_active = 0, st_flags = 0;
+    if (kState && tid == 0) {
+        st_ref = cs.rr_ref[j];
+        st_bb = cs.bb[j];
+        st_active = cs.active[j];
+        st_flags = cs.flags[j];
+    }
+    double tot[NV];
+    lane_total<NV>(src, rd.nblk, tot, sm);
+    if (tid != 0) return;
     const double t = tot[0];
     if (EPI == kEpiInit) {
         cs.bb[j] = t;
         cs.rr[j] = t;
-        cs.rr_prev[j] = t;
+        cs.qp[j] = 0.0;
         cs.rr_ref[j] = t;
         cs.true_rr[j] = t;
         cs.alpha[j] = 0.0;
@@ -354,55 +394,32 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
         cs.iters[j] = 0;
         cs.active[j] = t > 0.0;
         cs.flags[j] = t > 0.0 ? 0 : kFlagConverged;
-    } else if (EPI == kEpiAlpha) {
-        double alpha = 0.0;
-        if (st_active && !(st_flags & kFlagHold)) {
-            if (!(t > 0.0) || !isfinite(t)) {
-                if (cs.exact) {
-                    cs.flags[j] = st_flags | kFlagBreakdown;
-                    cs.active[j] = 0;
-                } else {
-                    cs.flags[j] = st_flags | kFlagRestart | (cs.hold ? kFlagHold : 0);
-                }
-            } else {
-                alpha = st_rr / t;
-            }
+    } else if (EPI == kEpiCheck) {
+        cs.rr[j] = t;
+        cs.qp[j] = tot[NV - 1];
+        if (cs.exact && st_active && t <= cs.tol2 * st_bb) {
+            cs.active[j] = 0;
+            cs.flags[j] = st_flags | kFlagConverged;
         }
-        cs.alpha[j] = alpha;
-    } else if (EPI == kEpiBeta) {
-        if (st_active && !(st_flags & kFlagHold)) {
-            cs.iters[j] = st_iters + 1;
-            cs.rr_prev[j] = st_rr;
-            cs.beta[j] = t / st_rr;
-            cs.rr[j] = t;
-            if (cs.exact) {
-                if (t <= cs.tol2 * st_bb) {
-                    cs.active[j] = 0;
-                    cs.flags[j] = st_flags | kFlagConverged;
-                }
-            } else if (cs.hold && !(t >= cs.delta2 * st_ref)) {
-                cs.flags[j] = st_flags | kFlagHold;  // due a reliable update (or not finite)
-            }
-        } else if (!st_active) {
-            cs.beta[j] = 0.0;
-        }
-    } else if (EPI == kEpiRU || EPI == kEpiStats) {
+    } else if (EPI == kEpiRU) {
+        // the residual is the true one from here on (the direction was
+        // continued, kept or restarted by the kernel that wrote it)
         cs.true_rr[j] = t;
-        cs.alpha[j] = 0.0;  // the fold before applied the deferred solution update
-        if (EPI == kEpiRU && st_active) {
-            // restart the direction (beta = 0) after a low-precision
-            // breakdown or when the true residual grew since the last update
-            const bool restart = (st_flags & kFlagRestart) || !(t <= st_ref);
-            cs.beta[j] = restart ? 0.0 : t / st_prev;
+        if (st_active) {
             int flags = st_flags & ~(kFlagRestart | kFlagHold);
             cs.rr[j] = t;
+            cs.qp[j] = tot[NV - 1];
             cs.rr_ref[j] = t;
+            // a restarted direction is the residual itself (no previous one)
+            if (st_flags & kFlagRestart) cs.beta[j] = 0.0;
             if (t <= cs.tol2 * st_bb) {
                 cs.active[j] = 0;
                 flags |= kFlagConverged;
             }
             cs.flags[j] = flags;
         }
+    } else if (EPI == kEpiStats || EPI == kEpiStatsP1) {
+        cs.true_rr[j] = t;
     } else {
         cs.tj[2 * j] = tot[0];
         cs.tj[2 * j + 1] = NV > 1 ? tot[NV - 1] : 0.0;
@@ -413,6 +430,94 @@ template <int NV, int EPI>
 __global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
     k_finish_body<NV, EPI>(blockIdx.x, rd, cs);
 }
+
+// Finishing kernel of a CG iteration (single reduction), one workgroup per
+// lane.  From the stencil's partials, pq = Re p^H q and qq = |q|^2 (q = A p
+// as stored; with BF16 storage also rq = Re r^H q and rp = Re r^H p), and
+// from the last update's, rr = |r|^2 (the residual as stored) and
+// Re q_prev^H p:
+//   FP64: a lane with rr <= tol^2 |b|^2 stops (converged);
+//   BF16: a lane whose rr fell below delta^2 times its value at the last
+//         reliable update holds (does not move) until that update;
+//   alpha = rr / pq (BF16: rp / pq),
+//   |r - alpha q|^2 = rr - 2 alpha rq + alpha^2 qq   (the new residual's
+//         norm, known before the update that forms it; rq as below),
+//   beta = |r - alpha q|^2 / rr,
+// so that one kernel can then form x, r and p (the new |r|^2 is also summed
+// there, exactly, for the next iteration: the expansion's cancellation
+// never carries over from one iteration to the next).  pq <= 0: FP64 stops
+// the lane (breakdown); mixed precision flags it to restart its direction
+// at the next reliable update (FP32 takes a steepest-descent step
+// meanwhile, BF16 holds).
+__device__ __forceinline__ void k_finish_cg_body(int lane, const Red &rd, const CgState &cs) {
+    __shared__ double sm[6 * kBlock / 64];
+    const int tid = threadIdx.x, j = lane;
+    double st_ref = 0.0, st_bb = 0.0, st_beta = 0.0;
+    int st_active = 0, st_flags = 0, st_iters = 0;
+    if (tid == 0) {
+        st_ref = cs.rr_ref[j];
+        st_bb = cs.bb[j];
+        st_beta = cs.beta[j];
+        st_active = cs.active[j];
+        st_flags = cs.flags[j];
+        st_iters = cs.iters[j];
+    }
+    double d3[4], d2[2];
+    lane_total<4>(rd.part1 + (size_t)lane * rd.nblk * 4, rd.nblk, d3, sm);
+    lane_total<2>(rd.part2 + (size_t)lane * rd.nblk * 2, rd.nblk, d2, sm + 4 * kBlock / 64);
+    if (tid != 0) return;
+    const double rr = d2[0], pq = d3[0], qq = d3[2];
+    // r^H q: since the residual is r = p - beta p_prev (beta the one that
+    // formed p), r^H q = p^H q - beta p_prev^H A p, and p_prev^H A p =
+    // (A p_prev)^H p = q_prev^H p was summed by the update that formed p (A
+    // Hermitian; no conjugacy assumed).  A reliable update replaces r by the
+    // true residual and keeps p, so the relation then holds up to the drift
+    // of the recursive residual, which with FP32 storage is a few 1e-5 of
+    // |r| and with BF16 storage up to about a tenth: there (rq_direct) the
+    // stencil sums r^H q itself, and also r^H p, so that alpha is the exact
+    // line search along p, Re r^H p / p^H A p, instead of |r|^2 / p^H A p
+    // (equal while r^H p_prev = 0; after a replacement the first step
+    // restores that orthogonality).
+    const double rq = cs.rq_direct ? d3[1] : pq - st_beta * d2[1];
+    const double rp = cs.rq_direct ? d3[3] : rr;
+    int active = st_active, flags = st_flags, iters = st_iters;
+    // a held lane keeps its direction, and with it the beta that formed it
+    double alpha = 0.0, beta = st_beta;
+    if (active) {
+        if (cs.exact && rr <= cs.tol2 * st_bb) {
+            active = 0;
+            flags |= kFlagConverged;
+        } else if (cs.hold && !(rr >= cs.delta2 * st_ref)) {
+            flags |= kFlagHold;  // due a reliable update (or not finite)
+        }
+    }
+    if (!active) beta = 0.0;
+    if (active && !(flags & kFlagHold)) {
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            beta = 0.0;
+            if (cs.exact) {
+                flags |= kFlagBreakdown;
+                active = 0;
+            } else {
+                flags |= kFlagRestart | (cs.hold ? kFlagHold : 0);
+            }
+        } else {
+            alpha = rp / pq;
+            const double rn = rr - 2.0 * alpha * rq + alpha * alpha * qq;
+            beta = rn > 0.0 && isfinite(rn) ? rn / rr : 0.0;
+            ++iters;
+        }
+    }
+    cs.rr[j] = rr;
+    cs.qp[j] = d2[1];
+    cs.alpha[j] = alpha;
+    cs.beta[j] = beta;
+    cs.active[j] = active;
+    cs.flags[j] = flags;
+    cs.iters[j] = iters;
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_cg(Red rd, CgState cs) { k_finish_cg_body(blockIdx.x, rd, cs); }
 
 // Control word for the host: [0] active lanes, [1] active lanes whose
 // recursive residual meets tol, [2] active lanes due a reliable update,
@@ -520,13 +625,13 @@ __device__ __forceinline__ void k_init_body(const Blk &bk, Launch L, ProbeGen g,
                                                  long long rhs0, long long nvalid, double2 *__restrict__ b64,
                                                  S *__restrict__ r, S *__restrict__ p, S *__restrict__ xlo,
                                                  double2 *__restrict__ x64, int mixed, Red rd, CgState cs) {
-    __shared__ double sm[kBlock];
+    __shared__ double sm[2 * kBlock];
     const int tid = threadIdx.x, W = L.W, logW = L.logW;
     const int j = tid & (W - 1);
     const int nc = L.nc;
     const unsigned long long seedmix = SRC == 0 ? mix64(g.seed) : 0ull;
     const ProbeLane pl = SRC == 0 ? probe_lane(g, nc, g.rhs0 + j) : ProbeLane{};
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};  // |b|^2, and 0 for q^H p (no previous direction)
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
     for (int t = t0; t < t1; ++t) {
@@ -556,7 +661,7 @@ __device__ __forceinline__ void k_init_body(const Blk &bk, Launch L, ProbeGen g,
             acc[0] += re * re + im * im;
         }
     }
-    block_partials<1>(bk, acc, W, logW, rd, sm);
+    block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
 }
 
 template <typename S, int SRC>
@@ -568,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const dou
 }
 
 // q = A p for one block of right-hand sides; with CG, also p^H q per lane
-// and, in the finishing workgroup, alpha = rr / p^H q.
+// and the other dot products of a CG iteration (k_finish_cg).
 // STAGE: links of the tile's sites staged in LDS (W >= 16).
 // ------------------------------------------------------------ stencil helpers
 
@@ -694,18 +799,19 @@ __device__ __forceinline__ void stage_tile_bf16(uint32_t *su, int *snb, const Si
 // body below.
 template <int NC, bool LINKS, int MODE>
 __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, float diag, const bf16x2 *__restrict__ pin,
-                                                    bf16x2 *__restrict__ q, const bf16x2 *__restrict__ U,
-                                                    const int *__restrict__ nbr, int cg, Red rd) {
+                                                    const bf16x2 *__restrict__ rin, bf16x2 *__restrict__ q,
+                                                    const bf16x2 *__restrict__ U, const int *__restrict__ nbr, int cg,
+                                                    Red rd) {
     constexpr bool STAGE = MODE == 1 && LINKS;
     constexpr int kMaxSites = kBlock / 16;
     __shared__ uint32_t su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
     __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
-    __shared__ double sm[kBlock];
+    __shared__ double sm[4 * kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
-    double acc_pq = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const SiteWalk wk = site_walk(L.lat, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
@@ -725,6 +831,12 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             const bf16x2 *row = pin + ((size_t)(y[k] * NC) << logW);
 #pragma unroll
             for (int b = 0; b < NC; ++b) v[k][b] = row[(unsigned)((b << logW) + j)].v;
+        }
+        uint32_t rv[NC];  // the residual at the site (CG: r^H q and r^H p summed here)
+        if (cg) {
+            const bf16x2 *rrow = rin + ((size_t)(site * NC) << logW);
+#pragma unroll
+            for (int b = 0; b < NC; ++b) rv[b] = rrow[(unsigned)((b << logW) + j)].v;
         }
 #pragma unroll
         for (int k = 1; k < 9; ++k)
@@ -760,7 +872,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             }
         }
         bf16x2 *qrow = q + ((size_t)(site * NC) << logW);
-        float pqs = 0;
+        float pqs = 0, rqs = 0, qqs = 0, rps = 0;
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
             const float pr = __uint_as_float(v[0][a] << 16), pi = __uint_as_float(v[0][a] & 0xffff0000u);
@@ -768,13 +880,23 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             bf16x2 o;
             o.v = pack_bf16(ar, ai);
             qrow[(unsigned)((a << logW) + j)] = o;
-            pqs = fmaf(pr, ar, fmaf(pi, ai, pqs));
+            if (cg) {
+                // the dot products of the stored (rounded) q
+                const float qr = __uint_as_float(o.v << 16), qi = __uint_as_float(o.v & 0xffff0000u);
+                pqs = fmaf(pr, qr, fmaf(pi, qi, pqs));
+                qqs = fmaf(qr, qr, fmaf(qi, qi, qqs));
+                const float rr_ = __uint_as_float(rv[a] << 16), ri = __uint_as_float(rv[a] & 0xffff0000u);
+                rqs = fmaf(rr_, qr, fmaf(ri, qi, rqs));
+                rps = fmaf(rr_, pr, fmaf(ri, pi, rps));
+            }
         }
-        acc_pq += (double)pqs;
+        acc[0] += (double)pqs;
+        acc[1] += (double)rqs;
+        acc[2] += (double)qqs;
+        acc[3] += (double)rps;
     }
     if (!cg) return;
-    double acc[1] = {acc_pq};
-    block_partials<1>(bk, acc, W, logW, rd, sm);
+    block_partials<4>(bk, acc, W, logW, rd, sm);
 }
 
 // Stages the hop links of the tile's sites (one contiguous record of 8 links
@@ -829,10 +951,10 @@ __device__ __forceinline__ void ld_hop(const LS *__restrict__ U8, int site, int 
 // together.
 template <typename S, typename LS, int NC, bool LINKS, int MODE>
 __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename St<S>::R diag, const S *__restrict__ pin,
-                                                    S *__restrict__ q, const LS *__restrict__ U,
-                                                    const int *__restrict__ nbr, int cg, Red rd) {
+                                               const S *__restrict__ rin, S *__restrict__ q, const LS *__restrict__ U,
+                                               const int *__restrict__ nbr, int cg, Red rd) {
     if constexpr (std::is_same<S, bf16x2>::value) {
-        k_stencil_bf16_body<NC, LINKS, MODE>(bk, L, diag, pin, q, U, nbr, cg, rd);
+        k_stencil_bf16_body<NC, LINKS, MODE>(bk, L, diag, pin, rin, q, U, nbr, cg, rd);
         return;
     }
     using R = typename St<S>::R;
@@ -840,12 +962,12 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
     constexpr int kMaxSites = kBlock / 16;
     __shared__ R su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
     __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
-    __shared__ double sm[kBlock];
+    __shared__ double sm[4 * kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
-    double acc_pq = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const SiteWalk wk = site_walk(L.lat, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
@@ -888,17 +1010,20 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
                 mul_sub<R, NC, true>(u, vr[dir + 1], vi[dir + 1], ar, ai);
         }
         S *qrow = q + ((size_t)(site * NC) << logW);
-        R pqs = 0;
+        R pqs = 0, qqs = 0;
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
             St<S>::st(qrow, (unsigned)((a << logW) + j), ar[a], ai[a]);
-            pqs = fmaR(vr[0][a], ar[a], fmaR(vi[0][a], ai[a], pqs));
+            if (cg) {
+                pqs = fmaR(vr[0][a], ar[a], fmaR(vi[0][a], ai[a], pqs));
+                qqs = fmaR(ar[a], ar[a], fmaR(ai[a], ai[a], qqs));
+            }
         }
-        acc_pq += (double)pqs;
+        acc[0] += (double)pqs;
+        acc[2] += (double)qqs;
     }
     if (!cg) return;
-    double acc[1] = {acc_pq};
-    block_partials<1>(bk, acc, W, logW, rd, sm);
+    block_partials<4>(bk, acc, W, logW, rd, sm);
 }
 
 // MODES 3 and 4: MODE 1 with G sites per thread that are each other's
@@ -933,19 +1058,19 @@ __device__ __forceinline__ int group_nb(int h, int dir) {
 
 template <typename S, typename LS, int NC, bool LINKS, int G, bool LINE = false>
 __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, typename St<S>::R diag,
-                                                     const S *__restrict__ pin, S *__restrict__ q,
-                                                     const LS *__restrict__ U, const int *__restrict__ nbr, int cg,
-                                                     Red rd) {
+                                                     const S *__restrict__ pin, const S *__restrict__ rin,
+                                                     S *__restrict__ q, const LS *__restrict__ U,
+                                                     const int *__restrict__ nbr, int cg, Red rd) {
     using R = typename St<S>::R;
     constexpr int kMaxItems = G == 2 ? 2 * (kBlock / 16) : 4 * (kBlock / 32);
     __shared__ R su[kMaxItems * 8 * NC * NC * 2];
     __shared__ int snb[kMaxItems * 8];
-    __shared__ double sm[kBlock];
+    __shared__ double sm[4 * kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = tid >> logW;
     const int items_per_tile = G * (kBlock >> logW);
-    double acc_pq = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const SiteWalk wk = site_walk(L.lat, bk);
     for (int t = wk.first; t * items_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * items_per_tile;
@@ -956,7 +1081,7 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
 #pragma unroll
         for (int h = 0; h < G; ++h)
             ld_site<S, NC>(pin, s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1)), logW, j, vor[h], voi[h]);
-        R pqs = 0;
+        R pqs = 0, qqs = 0;
 #pragma unroll
         for (int h = 0; h < G; ++h) {
             const int ls = G * sl + h;
@@ -1003,14 +1128,17 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
 #pragma unroll
             for (int a = 0; a < NC; ++a) {
                 St<S>::st(qrow, (unsigned)((a << logW) + j), ar[a], ai[a]);
-                pqs = fmaR(vor[h][a], ar[a], fmaR(voi[h][a], ai[a], pqs));
+                if (cg) {
+                    pqs = fmaR(vor[h][a], ar[a], fmaR(voi[h][a], ai[a], pqs));
+                    qqs = fmaR(ar[a], ar[a], fmaR(ai[a], ai[a], qqs));
+                }
             }
         }
-        acc_pq += (double)pqs;
+        acc[0] += (double)pqs;
+        acc[2] += (double)qqs;
     }
     if (!cg) return;
-    double acc[1] = {acc_pq};
-    block_partials<1>(bk, acc, W, logW, rd, sm);
+    block_partials<4>(bk, acc, W, logW, rd, sm);
 }
 
 // MODE 5 (W = 1): one right-hand side leaves a launch with one thread per
@@ -1021,14 +1149,14 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
 // write q.  Eight sites per workgroup pass.
 template <typename S, typename LS, int NC, bool LINKS>
 __device__ __forceinline__ void k_stencil_split_body(const Blk &bk, Launch L, typename St<S>::R diag,
-                                                     const S *__restrict__ pin, S *__restrict__ q,
-                                                     const LS *__restrict__ U, const int *__restrict__ nbr, int cg,
-                                                     Red rd) {
+                                                     const S *__restrict__ pin, const S *__restrict__ rin,
+                                                     S *__restrict__ q, const LS *__restrict__ U,
+                                                     const int *__restrict__ nbr, int cg, Red rd) {
     using R = typename St<S>::R;
-    __shared__ double sm[kBlock];
+    __shared__ double sm[4 * kBlock];
     const int tid = threadIdx.x, lane = tid & 31, h = lane >> 2, a = lane & 3;
     const int ngroups = (L.lat.N + 7) / 8;
-    double acc_pq = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int g = bk.b; g < ngroups; g += bk.nb) {
         const int site = g * 8 + (tid >> 5);
         const bool live = site < L.lat.N;
@@ -1060,214 +1188,197 @@ __device__ __forceinline__ void k_stencil_split_body(const Blk &bk, Launch L, ty
         if (live && h == 0 && a < NC) {
             R pr, pi;
             St<S>::ld(pin, (size_t)site * NC + a, pr, pi);
-            const R qr = fmaR(diag, pr, -sr), qi = fmaR(diag, pi, -si);
+            R qr = fmaR(diag, pr, -sr), qi = fmaR(diag, pi, -si);
             St<S>::st(q, (size_t)site * NC + a, qr, qi);
-            acc_pq += (double)fmaR(pr, qr, pi * qi);
+            if (cg) {
+                acc[0] += (double)fmaR(pr, qr, pi * qi);
+                acc[2] += (double)fmaR(qr, qr, qi * qi);
+            }
         }
     }
     if (!cg) return;
-    double acc[1] = {acc_pq};
-    block_partials<1>(bk, acc, 1, 0, rd, sm);
+    block_partials<4>(bk, acc, 1, 0, rd, sm);
 }
 
 template <typename S, typename LS, int NC, bool LINKS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R diag, const S *__restrict__ pin,
-                                                    S *__restrict__ q, const LS *__restrict__ U,
-                                                    const int *__restrict__ nbr, int cg, Red rd) {
-    if constexpr (MODE == 3 || MODE == 4)
-        k_stencil_group_body<S, LS, NC, LINKS, MODE == 3 ? 2 : 4>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
-    else if constexpr (MODE == 6)
-        k_stencil_group_body<S, LS, NC, LINKS, 4, true>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
-    else if constexpr (MODE == 5)
-        k_stencil_split_body<S, LS, NC, LINKS>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
+                                                    const S *__restrict__ rin, S *__restrict__ q,
+                                                    const LS *__restrict__ U, const int *__restrict__ nbr, int cg,
+                                                    Red rd) {
+    // the bodies are inlined once with cg = 1 and once with cg = 0: with a
+    // run-time flag the compiler keeps the registers of both paths live
+    // (the BF16 body went from 69 to 187 registers)
+    auto body = [&](int cg_) {
+        if constexpr (MODE == 3 || MODE == 4)
+            k_stencil_group_body<S, LS, NC, LINKS, MODE == 3 ? 2 : 4>(own_blk(), L, diag, pin, rin, q, U, nbr, cg_,
+                                                                      rd);
+        else if constexpr (MODE == 6)
+            k_stencil_group_body<S, LS, NC, LINKS, 4, true>(own_blk(), L, diag, pin, rin, q, U, nbr, cg_, rd);
+        else if constexpr (MODE == 5)
+            k_stencil_split_body<S, LS, NC, LINKS>(own_blk(), L, diag, pin, rin, q, U, nbr, cg_, rd);
+        else
+            k_stencil_body<S, LS, NC, LINKS, MODE>(own_blk(), L, diag, pin, rin, q, U, nbr, cg_, rd);
+    };
+    if (cg)
+        body(1);
     else
-        k_stencil_body<S, LS, NC, LINKS, MODE>(own_blk(), L, diag, pin, q, U, nbr, cg, rd);
+        body(0);
 }
 
-// r -= alpha q and |r|^2 per lane (second kernel of a CG iteration).  The
-// solution update x += alpha p of the iteration is deferred to the next
-// update2 (or fold), which reads p anyway: 10 vector passes per iteration
-// instead of 11.
+// The vector update of a CG iteration (second kernel; alpha and beta from
+// the finishing kernel): x += alpha p, r -= alpha q, p = r + beta p, and
+// |r|^2 and Re q^H p of the new residual and direction as stored (the next
+// finishing kernel adds the partials up).  A held or stopped lane keeps its
+// direction (alpha = 0: x and r are unchanged too).
 template <typename S>
-__device__ __forceinline__ void k_update1_body(const Blk &bk, Launch L, S *__restrict__ r, const S *__restrict__ q,
-                                               Red rd, CgState cs) {
+__device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__restrict__ x, S *__restrict__ r,
+                                              S *__restrict__ p, const S *__restrict__ q, Red rd, CgState cs) {
     using R = typename St<S>::R;
-    __shared__ double sm[kBlock];
+    __shared__ double sm[2 * kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> logW;
     const R alpha = (R)cs.alpha[j];
-    double acc[1] = {0.0};
+    const R beta = (R)cs.beta[j];
+    const bool keep = (cs.flags[j] & kFlagHold) || !cs.active[j];
+    double acc[2] = {0.0, 0.0};
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
     // element e = ((site * nc + a) << logW) + j: lane j is tid & (W-1) for
     // every e = e0 + tid + k * kBlock since kBlock is a multiple of W
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
     const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
-    R part = 0;
+    R part = 0, partq = 0;
     int cnt = 0;
     size_t e = e0 + tid;
     // four elements per pass, all loads issued before the first use (more
     // loads in flight per wavefront); the same summation order as the
-    // element-by-element tail below
+    // element-by-element tail below; no branch inside (a kept direction is
+    // stored back unchanged: a loaded value is stored exactly)
     for (; e + 3 * kBlock < e1; e += 4 * kBlock) {
-        R rr_[4], ri[4], qr[4], qi[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            St<S>::ld(r, e + u * kBlock, rr_[u], ri[u]);
-            St<S>::ld(q, e + u * kBlock, qr[u], qi[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            rr_[u] = fmaR(-alpha, qr[u], rr_[u]);
-            ri[u] = fmaR(-alpha, qi[u], ri[u]);
-            St<S>::st(r, e + u * kBlock, rr_[u], ri[u]);
-            St<S>::round(rr_[u], ri[u]);
-            part = fmaR(rr_[u], rr_[u], fmaR(ri[u], ri[u], part));
-        }
-        if ((cnt += 4) == 24) {
-            acc[0] += (double)part;
-            part = 0;
-            cnt = 0;
-        }
-    }
-    for (; e < e1; e += kBlock) {
-        R rr_, ri, qr, qi;
-        St<S>::ld(r, e, rr_, ri);
-        St<S>::ld(q, e, qr, qi);
-        rr_ = fmaR(-alpha, qr, rr_);
-        ri = fmaR(-alpha, qi, ri);
-        St<S>::st(r, e, rr_, ri);
-        // the next iteration uses the stored (rounded) residual
-        St<S>::round(rr_, ri);
-        part = fmaR(rr_, rr_, fmaR(ri, ri, part));
-        if (++cnt == 24) {
-            acc[0] += (double)part;
-            part = 0;
-            cnt = 0;
-        }
-    }
-    acc[0] += (double)part;
-    block_partials<1>(bk, acc, W, logW, rd, sm);
-}
-
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_update1(Launch L, S *__restrict__ r, const S *__restrict__ q, Red rd,
-                                                    CgState cs) {
-    k_update1_body<S>(own_blk(), L, r, q, rd, cs);
-}
-
-// x += alpha p (the previous iteration's deferred solution update), then
-// p = r + beta p (third kernel of a CG iteration).  A held lane keeps its
-// direction (its deferred update still lands).
-template <typename S>
-__device__ __forceinline__ void k_update2_body(const Blk &bk, Launch L, const S *__restrict__ r, S *__restrict__ p,
-                                               S *__restrict__ x, CgState cs) {
-    using R = typename St<S>::R;
-    const int tid = threadIdx.x, W = L.W;
-    const int j = tid & (W - 1);
-    const int sites_per_tile = kBlock >> L.logW;
-    const R alpha = (R)cs.alpha[j];
-    const R beta = (R)cs.beta[j];
-    const bool keep = cs.flags[j] & kFlagHold;
-    int t0, t1;
-    tile_range(bk, L.ntiles, t0, t1);
-    const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
-    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
-    size_t e = e0 + tid;
-    // four elements per pass, all loads issued before the first use (more
-    // loads in flight per wavefront); no branch inside: a held lane stores
-    // its p back unchanged (a loaded value is stored exactly)
-    for (; e + 3 * kBlock < e1; e += 4 * kBlock) {
-        R rr_[4], ri[4], pr[4], pi[4], xr[4], xi[4];
+        R xr[4], xi[4], rr_[4], ri[4], pr[4], pi[4], qr[4], qi[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             St<S>::ld(p, e + u * kBlock, pr[u], pi[u]);
-            St<S>::ld(x, e + u * kBlock, xr[u], xi[u]);
+            St<S>::ld(q, e + u * kBlock, qr[u], qi[u]);
             St<S>::ld(r, e + u * kBlock, rr_[u], ri[u]);
+            St<S>::ld(x, e + u * kBlock, xr[u], xi[u]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             St<S>::st(x, e + u * kBlock, fmaR(alpha, pr[u], xr[u]), fmaR(alpha, pi[u], xi[u]));
-            St<S>::st(p, e + u * kBlock, keep ? pr[u] : fmaR(beta, pr[u], rr_[u]),
-                      keep ? pi[u] : fmaR(beta, pi[u], ri[u]));
+            rr_[u] = fmaR(-alpha, qr[u], rr_[u]);
+            ri[u] = fmaR(-alpha, qi[u], ri[u]);
+            St<S>::st(r, e + u * kBlock, rr_[u], ri[u]);
+            // the next iteration uses the stored (rounded) residual
+            St<S>::round(rr_[u], ri[u]);
+            R npr = keep ? pr[u] : fmaR(beta, pr[u], rr_[u]), npi = keep ? pi[u] : fmaR(beta, pi[u], ri[u]);
+            St<S>::st(p, e + u * kBlock, npr, npi);
+            St<S>::round(npr, npi);
+            part = fmaR(rr_[u], rr_[u], fmaR(ri[u], ri[u], part));
+            partq = fmaR(qr[u], npr, fmaR(qi[u], npi, partq));
+        }
+        if ((cnt += 4) == 24) {
+            acc[0] += (double)part;
+            acc[1] += (double)partq;
+            part = partq = 0;
+            cnt = 0;
         }
     }
     for (; e < e1; e += kBlock) {
-        R rr_, ri, pr, pi, xr, xi;
+        R xr, xi, rr_, ri, pr, pi, qr, qi;
         St<S>::ld(p, e, pr, pi);
+        St<S>::ld(q, e, qr, qi);
+        St<S>::ld(r, e, rr_, ri);
         St<S>::ld(x, e, xr, xi);
         St<S>::st(x, e, fmaR(alpha, pr, xr), fmaR(alpha, pi, xi));
-        if (keep) continue;
-        St<S>::ld(r, e, rr_, ri);
-        St<S>::st(p, e, fmaR(beta, pr, rr_), fmaR(beta, pi, ri));
+        rr_ = fmaR(-alpha, qr, rr_);
+        ri = fmaR(-alpha, qi, ri);
+        St<S>::st(r, e, rr_, ri);
+        St<S>::round(rr_, ri);
+        R npr = keep ? pr : fmaR(beta, pr, rr_), npi = keep ? pi : fmaR(beta, pi, ri);
+        St<S>::st(p, e, npr, npi);
+        St<S>::round(npr, npi);
+        part = fmaR(rr_, rr_, fmaR(ri, ri, part));
+        partq = fmaR(qr, npr, fmaR(qi, npi, partq));
+        if (++cnt == 24) {
+            acc[0] += (double)part;
+            acc[1] += (double)partq;
+            part = partq = 0;
+            cnt = 0;
+        }
     }
+    acc[0] += (double)part;
+    acc[1] += (double)partq;
+    // a kept direction keeps the Re q_prev^H p of the update that formed it
+    // (the q loaded here is A of the kept direction itself): its total comes
+    // back from cs.qp, once per lane
+    if (keep) acc[1] = (bk.b == 0 && tid < W) ? cs.qp[j] : 0.0;
+    block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_update2(Launch L, const S *__restrict__ r, S *__restrict__ p,
-                                                    S *__restrict__ x, CgState cs) {
-    k_update2_body<S>(own_blk(), L, r, p, x, cs);
+__global__ __launch_bounds__(kBlock) void k_update(Launch L, S *__restrict__ x, S *__restrict__ r,
+                                                   S *__restrict__ p, const S *__restrict__ q, Red rd, CgState cs) {
+    k_update_body<S>(own_blk(), L, x, r, p, q, rd, cs);
 }
 
-// Mixed precision (xlo set): x64 += xlo + alpha p, xlo = 0.  FP64 (xlo null,
-// x64 is the iterate): x64 += alpha p.  Either way the deferred solution
-// update lands; the epilogue that follows sets alpha to 0.
+// Mixed precision: x64 += xlo, xlo = 0 (the low-precision iterate folded
+// into the FP64 solution before a reliable update).
 template <typename S>
-__device__ __forceinline__ void k_fold_body(const Blk &bk, Launch L, double2 *__restrict__ x64, S *__restrict__ xlo,
-                                            const S *__restrict__ p, CgState cs) {
+__device__ __forceinline__ void k_fold_body(const Blk &bk, Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
     using R = typename St<S>::R;
     const int tid = threadIdx.x, W = L.W;
-    const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> L.logW;
-    const double alpha = cs.alpha[j];
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
     const size_t e0 = (size_t)t0 * sites_per_tile * L.nc * W;
     const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * L.nc * W;
     for (size_t e = e0 + tid; e < e1; e += kBlock) {
-        R pr, pi;
-        St<S>::ld(p, e, pr, pi);
+        R xr, xi;
+        St<S>::ld(xlo, e, xr, xi);
         double2 v = x64[e];
-        v.x = fma(alpha, (double)pr, v.x);
-        v.y = fma(alpha, (double)pi, v.y);
-        if (xlo) {
-            R xr, xi;
-            St<S>::ld(xlo, e, xr, xi);
-            v.x += (double)xr;
-            v.y += (double)xi;
-            St<S>::st(xlo, e, 0, 0);
-        }
+        v.x += (double)xr;
+        v.y += (double)xi;
+        St<S>::st(xlo, e, 0, 0);
         x64[e] = v;
     }
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo,
-                                                 const S *__restrict__ p, CgState cs) {
-    k_fold_body<S>(own_blk(), L, x64, xlo, p, cs);
+__global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__ x64, S *__restrict__ xlo) {
+    k_fold_body<S>(own_blk(), L, x64, xlo);
 }
 
-// FP64 true residual r = b - A x64 with FP64 links.  Stores r in the
-// storage precision and |r|^2 per lane.
+// FP64 true residual r_new = b - A x64 with FP64 links, |r_new|^2 per lane
+// into rd.part2.  ru (a reliable update): r_new replaces the residual in the
+// storage precision; a lane flagged to restart takes r_new as its direction.
+// The other directions: FP32 storage continues them as p + (r_new - r_old),
+// the direction the last update would have formed from r_new (so that
+// r = p - beta p_prev still holds exactly for the finishing kernel), and
+// sums Re q^H p of it (q = A p_prev, still in qin) beside |r_new|^2; BF16
+// storage keeps them (residual replacement; its finishing kernel takes the
+// exact line search along p) and writes the lane's total cs.qp back.
+// Otherwise (statistics) nothing is written but the norm.
 template <typename S, int NC, bool LINKS, int MODE>
 __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, double diag, const double2 *__restrict__ b64,
-                                                       const double2 *__restrict__ x64,
-                                                       const double2 *__restrict__ U, const int *__restrict__ nbr,
-                                                       S *__restrict__ rout, Red rd, CgState cs, ProbeGen g,
-                                                       int gen) {
+                                                  const double2 *__restrict__ x64, const double2 *__restrict__ U,
+                                                  const int *__restrict__ nbr, S *__restrict__ rout,
+                                                  S *__restrict__ pio, const S *__restrict__ qin, int ru, Red rd,
+                                                  CgState cs, ProbeGen g, int gen) {
     constexpr int kMaxSites = kBlock / 16;
     __shared__ double su[MODE == 1 && LINKS ? kMaxSites * 8 * NC * NC * 2 : 1];
     __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
-    __shared__ double sm[kBlock];
+    __shared__ double sm[2 * kBlock];
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     const SiteWalk wk = site_walk(L.lat, bk);
     const unsigned long long seedmix = gen ? mix64(g.seed) : 0ull;
     const ProbeLane pl = gen ? probe_lane(g, NC, g.rhs0 + j) : ProbeLane{};
+    const bool restart = ru && (cs.flags[j] & kFlagRestart);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         if (MODE == 1) stage_tile<double2, double, NC, LINKS>(su, snb, wk, t * sites_per_tile, sites_per_tile, U, nbr);
         if (t * sites_per_tile + sl >= wk.items) continue;
@@ -1319,22 +1430,49 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
             else
                 mul_sub<double, NC, true>(u, vr[dir + 1], vi[dir + 1], ar, ai);
         }
-        S *rrow = rout + ((size_t)(site * NC) << logW);
+        if (ru) {
+            using R = typename St<S>::R;
+            // (the neighbours' registers are free from here on)
+            __builtin_amdgcn_sched_barrier(0);
+            S *rrow = rout + ((size_t)(site * NC) << logW);
+            S *prow = pio + ((size_t)(site * NC) << logW);
+            const S *qrow = qin + ((size_t)(site * NC) << logW);
 #pragma unroll
-        for (int a = 0; a < NC; ++a) {
-            St<S>::st(rrow, ((size_t)a << logW) + j, (typename St<S>::R)(-ar[a]), (typename St<S>::R)(-ai[a]));
-            acc[0] += ar[a] * ar[a] + ai[a] * ai[a];
+            for (int a = 0; a < NC; ++a) {
+                const size_t i = ((size_t)a << logW) + j;
+                R nr = (R)(-ar[a]), ni = (R)(-ai[a]);
+                if (cs.rq_direct) {
+                    St<S>::st(rrow, i, nr, ni);
+                    if (restart) St<S>::st(prow, i, nr, ni);
+                } else {
+                    R ro_r, ro_i, po_r, po_i, qr, qi;
+                    St<S>::ld(rrow, i, ro_r, ro_i);
+                    St<S>::ld(prow, i, po_r, po_i);
+                    St<S>::ld(qrow, i, qr, qi);
+                    St<S>::st(rrow, i, nr, ni);
+                    St<S>::round(nr, ni);
+                    R npr = restart ? nr : po_r + (nr - ro_r), npi = restart ? ni : po_i + (ni - ro_i);
+                    St<S>::st(prow, i, npr, npi);
+                    St<S>::round(npr, npi);
+                    acc[1] += (double)(qr * npr + qi * npi);
+                }
+            }
         }
+#pragma unroll
+        for (int a = 0; a < NC; ++a) acc[0] += ar[a] * ar[a] + ai[a] * ai[a];
     }
-    block_partials<1>(bk, acc, W, logW, rd, sm);
+    if (ru && cs.rq_direct) acc[1] = (bk.b == 0 && tid < W) ? cs.qp[j] : 0.0;
+    block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
 }
 
 template <typename S, int NC, bool LINKS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
                                                        const double2 *__restrict__ x64,
                                                        const double2 *__restrict__ U, const int *__restrict__ nbr,
-                                                       S *__restrict__ rout, Red rd, CgState cs, ProbeGen g, int gen) {
-    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, U, nbr, rout, rd, cs, g, gen);
+                                                       S *__restrict__ rout, S *__restrict__ pio,
+                                                       const S *__restrict__ qin, int ru, Red rd, CgState cs,
+                                                       ProbeGen g, int gen) {
+    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, U, nbr, rout, pio, qin, ru, rd, cs, g, gen);
 }
 
 // t_j = sum_x sum_b conj(v_j(x,b)) x_j(x + p e0, b), probes regenerated.
@@ -1558,24 +1696,17 @@ __global__ __launch_bounds__(kBlock) void k_b_stencil(BatchLaunch B) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
-    k_stencil_body<S, LS, NC, LINKS, MODE>(bk, d->L, (typename St<S>::R)d->diag, (const S *)d->p, (S *)d->q,
-                                           (const LS *)d->U, d->nbr, 1, d->rd);
+    k_stencil_body<S, LS, NC, LINKS, MODE>(bk, d->L, (typename St<S>::R)d->diag, (const S *)d->p,
+                                           (const S *)d->r, (S *)d->q, (const LS *)d->U, d->nbr, 1, d->rd);
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_b_update1(BatchLaunch B) {
+__global__ __launch_bounds__(kBlock) void k_b_update(BatchLaunch B) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
-    k_update1_body<S>(bk, d->L, (S *)d->r, (const S *)d->q, d->rd, d->cs);
-}
-
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_b_update2(BatchLaunch B) {
-    Blk bk;
-    const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
-    if (!d) return;
-    k_update2_body<S>(bk, d->L, (const S *)d->r, (S *)d->p, (S *)d->xlo, d->cs);
+    // FP64: the iterate is x64 itself (xlo aliases it)
+    k_update_body<S>(bk, d->L, (S *)d->xlo, (S *)d->r, (S *)d->p, (const S *)d->q, d->rd, d->cs);
 }
 
 template <typename S>
@@ -1583,17 +1714,17 @@ __global__ __launch_bounds__(kBlock) void k_b_fold(BatchLaunch B, int phase) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, phase);
     if (!d) return;
-    // FP64: the iterate is x64 itself (xlo aliases it)
-    k_fold_body<S>(bk, d->L, (double2 *)d->x64, B.prec == kF64 ? nullptr : (S *)d->xlo, (const S *)d->p, d->cs);
+    k_fold_body<S>(bk, d->L, (double2 *)d->x64, (S *)d->xlo);
 }
 
 template <typename S, int NC, bool LINKS, int MODE>
-__global__ __launch_bounds__(kBlock) void k_b_true_resid(BatchLaunch B, int phase) {
+__global__ __launch_bounds__(kBlock) void k_b_true_resid(BatchLaunch B, int phase, int ru) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, phase);
     if (!d) return;
     k_true_resid_body<S, NC, LINKS, MODE>(bk, d->L, d->diag, (const double2 *)d->b64, (const double2 *)d->x64,
-                                          (const double2 *)d->U64, d->nbr, (S *)d->r, d->rd, d->cs, d->g, d->gen_b);
+                                          (const double2 *)d->U64, d->nbr, (S *)d->r, (S *)d->p, (const S *)d->q,
+                                          ru, d->rd, d->cs, d->g, d->gen_b);
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_dot(BatchLaunch B) {
@@ -1610,6 +1741,30 @@ __global__ __launch_bounds__(kBlock) void k_b_finish(BatchLaunch B, int phase) {
     const SlotDesc *d = B.sd + s;
     if (!(d->flags & phase)) return;
     k_finish_body<NV, EPI>(lane, d->rd, d->cs);
+}
+
+// After the workgroups were shared anew among the slots, the |r|^2 and
+// Re q^H p partials of an iterating slot (written by its last update with its
+// old number of workgroups) are replaced by the lane's totals, cs.rr and
+// cs.qp (which the check before the new sharing took from them): partial 0
+// holds them, the others 0.
+__global__ __launch_bounds__(kBlock) void k_b_reseed(BatchLaunch B) {
+    const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
+    const SlotDesc *d = B.sd + s;
+    if (!(d->flags & kSlotIter)) return;
+    const double rr = d->cs.rr[lane], qp = d->cs.qp[lane];
+    double *dst = d->rd.part2 + (size_t)lane * d->rd.nblk * 2;
+    for (int b = threadIdx.x; b < d->rd.nblk; b += kBlock) {
+        dst[2 * b] = b == 0 ? rr : 0.0;
+        dst[2 * b + 1] = b == 0 ? qp : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_finish_cg(BatchLaunch B) {
+    const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
+    const SlotDesc *d = B.sd + s;
+    if (!(d->flags & kSlotIter)) return;
+    k_finish_cg_body(lane, d->rd, d->cs);
 }
 
 __global__ void k_b_ctrl(BatchLaunch B) {
@@ -1855,7 +2010,7 @@ void launch_init_probe(const Launch &L, int prec, const ProbeGen &g, double *b64
                      k_init<S, 0><<<L.nblk, kBlock, 0, L.stream>>>(L, g, nullptr, 0, 0, (double2 *)b64, (S *)r,
                                                                    (S *)p, (S *)xlo, (double2 *)x64, mixed, rd,
                                                                    cs));
-    k_finish<1, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+    k_finish<2, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
 void launch_init_abi(const Launch &L, int prec, const double *babi, long long rhs0, long long nvalid, double *b64,
@@ -1865,22 +2020,22 @@ void launch_init_abi(const Launch &L, int prec, const double *babi, long long rh
                      k_init<S, 1><<<L.nblk, kBlock, 0, L.stream>>>(L, g, (const double2 *)babi, rhs0, nvalid,
                                                                    (double2 *)b64, (S *)r, (S *)p, (S *)xlo,
                                                                    (double2 *)x64, mixed, rd, cs));
-    k_finish<1, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+    k_finish<2, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
 template <typename S, typename LS, int NC, bool LINKS>
 static void stencil_nc(const Launch &L, const StencilArgs &a) {
     using R = typename St<S>::R;
     dim3 grid(L.nblk), blk(kBlock);
-    const S *pin = (const S *)a.pin;
+    const S *pin = (const S *)a.pin, *rin = (const S *)a.rin;
     S *q = (S *)a.q;
     const LS *U = (const LS *)a.U;
 #define DP_ST(M)                                                                                        \
     if (a.ev0)                                                                                          \
         hipExtLaunchKernelGGL(k_stencil<S, LS, NC, LINKS, M>, grid, blk, 0, L.stream, a.ev0, a.ev1, 0, L, \
-                              (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd);                                 \
+                              (R)a.diag, pin, rin, q, U, a.nbr, a.cg, a.rd);                            \
     else                                                                                                \
-        k_stencil<S, LS, NC, LINKS, M><<<grid, blk, 0, L.stream>>>(L, (R)a.diag, pin, q, U, a.nbr, a.cg, a.rd)
+        k_stencil<S, LS, NC, LINKS, M><<<grid, blk, 0, L.stream>>>(L, (R)a.diag, pin, rin, q, U, a.nbr, a.cg, a.rd)
     // groups: x0-slabs of an even number of slices (the slab walk of
     // site_walk); quads: slabs of two slices, D3 even, W >= 32 (LDS)
     const bool slabs = !std::is_same<S, bf16x2>::value && L.nblk >= 8 && L.nblk % 8 == 0;
@@ -1926,32 +2081,28 @@ void launch_stencil(const Launch &L, int prec, const StencilArgs &a) {
         stencil_t<float2, float2>(L, a);
     else
         stencil_t<bf16x2, bf16x2>(L, a);
-    if (a.cg) k_finish<1, kEpiAlpha><<<L.W, kBlock, 0, L.stream>>>(a.rd, a.cs);
+    if (a.cg) k_finish_cg<<<L.W, kBlock, 0, L.stream>>>(a.rd, a.cs);
 }
 
-void launch_update1(const Launch &L, int prec, void *r, const void *q, const Red &rd, const CgState &cs) {
-    DP_DISPATCH_PREC(prec, S, k_update1<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)r, (const S *)q, rd, cs));
-    k_finish<1, kEpiBeta><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
-}
-
-void launch_update2(const Launch &L, int prec, const void *r, void *p, void *x, const CgState &cs) {
+void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const void *q, const Red &rd,
+                   const CgState &cs) {
     DP_DISPATCH_PREC(prec, S,
-                     k_update2<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (const S *)r, (S *)p, (S *)x, cs));
+                     k_update<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)x, (S *)r, (S *)p, (const S *)q, rd, cs));
 }
 
-void launch_fold(const Launch &L, int prec, double *x64, void *xlo, const void *p, const CgState &cs) {
-    DP_DISPATCH_PREC(prec, S,
-                     k_fold<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (double2 *)x64, (S *)xlo, (const S *)p, cs));
+void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {
+    DP_DISPATCH_PREC(prec, S, k_fold<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (double2 *)x64, (S *)xlo));
 }
 
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64, const double *x64,
-                       const void *U64, const int *nbr, void *r, int ru_mode, const Red &rd, const CgState &cs,
-                       const ProbeGen *gen) {
+                       const void *U64, const int *nbr, void *r, void *p, const void *q, int ru_mode,
+                       const Red &rd, const CgState &cs, const ProbeGen *gen) {
     const ProbeGen g = gen ? *gen : ProbeGen{};
     const int use_gen = gen ? 1 : 0;
     const double2 *b = (const double2 *)b64, *x = (const double2 *)x64, *u = (const double2 *)U64;
 #define DP_TR(NC_, LK_, M_)                                                                                  \
-    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, rd, cs, g, use_gen)
+    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, (S *)p,     \
+                                                                   (const S *)q, ru_mode, rd, cs, g, use_gen)
     DP_DISPATCH_PREC(prec, S, {
         const int m = L.W >= 64 ? 2 : (L.W >= 16 ? 1 : 0);
         if (L.nc == 3) {
@@ -1970,9 +2121,9 @@ void launch_true_resid(const Launch &L, int prec, bool links, double diag, const
     });
 #undef DP_TR
     if (ru_mode)
-        k_finish<1, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+        k_finish<2, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
     else
-        k_finish<1, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+        k_finish<2, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
 void launch_level_map(int N, const int *fine, int nfine, const int *coarse, int ncoarse, int *cmap, int *bad,
@@ -1993,7 +2144,10 @@ void launch_dot(const Launch &L, const double *a64, const double *b64, const Red
     k_finish<2, kEpiTj><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
-void launch_ctrl(const CgState &cs, int W, hipStream_t s) { k_ctrl<<<1, 64, 0, s>>>(cs, W); }
+void launch_ctrl(const Red &rd, const CgState &cs, int W, hipStream_t s) {
+    k_finish<2, kEpiCheck><<<W, kBlock, 0, s>>>(rd, cs);
+    k_ctrl<<<1, 64, 0, s>>>(cs, W);
+}
 
 // The same force for W >= 8, W threads per (site, mu) pair: thread j loads
 // lane j of the four rows the pair needs (coalesced, each once per pair) and
@@ -2131,7 +2285,7 @@ void launch_make_probes_abi(const Lat &lat, int nc, const ProbeGen &g, long long
 
 void launch_b_init(const BatchLaunch &B, int mixed) {
     DP_DISPATCH_PREC(B.prec, S, k_b_init<S><<<B.nblocks, kBlock, 0, B.stream>>>(B, mixed));
-    k_b_finish<1, kEpiInit><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotInit);
+    k_b_finish<2, kEpiInit><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotInit);
 }
 
 template <typename S, typename LS, int NC, bool LINKS, int M>
@@ -2161,51 +2315,50 @@ static void b_stencil(const BatchLaunch &B, hipEvent_t ev0 = nullptr, hipEvent_t
         B.links ? b_stencil_t<S, S, 1, true>(B, ev0, ev1) : b_stencil_t<S, S, 1, false>(B, ev0, ev1);
 }
 
-void launch_b_update2(const BatchLaunch &B) {
-    DP_DISPATCH_PREC(B.prec, S, k_b_update2<S><<<B.nblocks, kBlock, 0, B.stream>>>(B));
-}
-
 void launch_b_stencil(const BatchLaunch &B, hipEvent_t ev0, hipEvent_t ev1) {
     DP_DISPATCH_PREC(B.prec, S, b_stencil<S>(B, ev0, ev1));
 }
 
-void launch_b_update1(const BatchLaunch &B) {
-    k_b_finish<1, kEpiAlpha><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
-    DP_DISPATCH_PREC(B.prec, S, k_b_update1<S><<<B.nblocks, kBlock, 0, B.stream>>>(B));
-    k_b_finish<1, kEpiBeta><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
+void launch_b_update(const BatchLaunch &B) {
+    k_b_finish_cg<<<B.nslots * B.W, kBlock, 0, B.stream>>>(B);
+    DP_DISPATCH_PREC(B.prec, S, k_b_update<S><<<B.nblocks, kBlock, 0, B.stream>>>(B));
 }
 
-void launch_b_iteration(const BatchLaunch &B, bool update2) {
-    if (update2) launch_b_update2(B);
+void launch_b_reseed(const BatchLaunch &B) { k_b_reseed<<<B.nslots * B.W, kBlock, 0, B.stream>>>(B); }
+
+void launch_b_iteration(const BatchLaunch &B) {
     launch_b_stencil(B);
-    launch_b_update1(B);
+    launch_b_update(B);
 }
 
 template <typename S, int NC, bool LINKS>
-static void b_tr_t(const BatchLaunch &B, int phase) {
+static void b_tr_t(const BatchLaunch &B, int phase, int ru) {
     if (B.mode == 2)
-        k_b_true_resid<S, NC, LINKS, 2><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+        k_b_true_resid<S, NC, LINKS, 2><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase, ru);
     else if (B.mode == 1)
-        k_b_true_resid<S, NC, LINKS, 1><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+        k_b_true_resid<S, NC, LINKS, 1><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase, ru);
     else
-        k_b_true_resid<S, NC, LINKS, 0><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+        k_b_true_resid<S, NC, LINKS, 0><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase, ru);
 }
 
-// Reliable update (final_stats = 0: slots flagged kSlotRU) or the final
-// fold and statistics (final_stats = 1: slots flagged kSlotFinal).
+// Reliable update (final_stats = 0: slots flagged kSlotRU; mixed precision:
+// fold, then the true residual replaces r and continues p) or the final
+// statistics (final_stats = 1: slots flagged kSlotFinal; FP64, whose iterate
+// is already the solution: the true residual's norm only).
 void launch_b_ru(const BatchLaunch &B, int final_stats) {
     const int phase = final_stats ? kSlotFinal : kSlotRU;
+    const int ru = final_stats ? 0 : 1;
     DP_DISPATCH_PREC(B.prec, S, {
-        k_b_fold<S><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
+        if (B.prec != kF64) k_b_fold<S><<<B.nblocks, kBlock, 0, B.stream>>>(B, phase);
         if (B.nc == 3)
-            B.links ? b_tr_t<S, 3, true>(B, phase) : b_tr_t<S, 3, false>(B, phase);
+            B.links ? b_tr_t<S, 3, true>(B, phase, ru) : b_tr_t<S, 3, false>(B, phase, ru);
         else
-            B.links ? b_tr_t<S, 1, true>(B, phase) : b_tr_t<S, 1, false>(B, phase);
+            B.links ? b_tr_t<S, 1, true>(B, phase, ru) : b_tr_t<S, 1, false>(B, phase, ru);
     });
     if (final_stats)
-        k_b_finish<1, kEpiStats><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, phase);
+        k_b_finish<2, kEpiStats><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, phase);
     else
-        k_b_finish<1, kEpiRU><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, phase);
+        k_b_finish<2, kEpiRU><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, phase);
 }
 
 void launch_b_dot(const BatchLaunch &B) {
@@ -2213,7 +2366,10 @@ void launch_b_dot(const BatchLaunch &B) {
     k_b_finish<2, kEpiTj><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotFinal);
 }
 
-void launch_b_ctrl(const BatchLaunch &B) { k_b_ctrl<<<B.nslots, 64, 0, B.stream>>>(B); }
+void launch_b_ctrl(const BatchLaunch &B) {
+    k_b_finish<2, kEpiCheck><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
+    k_b_ctrl<<<B.nslots, 64, 0, B.stream>>>(B);
+}
 
 
 void launch_init_b64(const Launch &L, int prec, double *b64, void *r, void *p, void *xlo, double *x64, int mixed,
@@ -2223,7 +2379,7 @@ void launch_init_b64(const Launch &L, int prec, double *b64, void *r, void *p, v
                      k_init<S, 2><<<L.nblk, kBlock, 0, L.stream>>>(L, g, nullptr, 0, 0, (double2 *)b64, (S *)r,
                                                                    (S *)p, (S *)xlo, (double2 *)x64, mixed, rd,
                                                                    cs));
-    k_finish<1, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+    k_finish<2, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
 void launch_dot_shift(const Launch &L, const double *u, const double *w, int p, const Red &rd, const CgState &cs) {
@@ -2234,7 +2390,7 @@ void launch_dot_shift(const Launch &L, const double *u, const double *w, int p, 
 void launch_resid_norm(const Launch &L, const double *u, const double *w, const double *theta, const Red &rd,
                        const CgState &cs) {
     k_resid_norm<<<L.nblk, kBlock, 0, L.stream>>>(L, (const double2 *)u, (const double2 *)w, theta, rd);
-    k_finish<1, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+    k_finish<1, kEpiStatsP1><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
 void launch_axpby(long long n, double a, const double *q, double b, const double *v, double *out, hipStream_t s) {

@@ -182,8 +182,8 @@ extern "C" dp_status dp_solve_noalloc(dp_ctx *ctx, const dp_operator *op, const 
         OpPrep opp;
         DP_TRY(prepare_operator(ctx, *op, cfg.inner, opp, stream));
         Launch L;
-        Red rd;
-        CgState cs;
+        Red rd{};
+        CgState cs{};
         DP_TRY(make_launch(ctx, opp, W, stream, L, rd, cs, cfg));
         // every buffer of the layout is written before it is read: the init
         // kernel writes b, r, p, x (and the FP64 copies) at every site and

@@ -174,7 +174,7 @@ size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W)
         case kSlotP:
         case kSlotQ: return lo;
         case kSlotXLo: return inner != kF64 ? lo : 0;
-        case kSlotPart1: return (size_t)launch_blocks(lat, W) * W * 2 * sizeof(double);
+        case kSlotPart1: return (size_t)launch_blocks(lat, W) * W * 6 * sizeof(double);  // part1 [.][4], part2 [.][2]
         case kSlotState: return state_bytes();
         default: return 0;
     }
@@ -241,11 +241,12 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
         if (b) DP_TRY(ctx->ensure(slot, b));
     }
     rd.part1 = (double *)ctx->at(kSlotPart1);
+    rd.part2 = rd.part1 + (size_t)L.nblk * W * 4;
     rd.nblk = L.nblk;
     const size_t nd = 9 * kMaxW + 8;
     double *d = (double *)ctx->at(kSlotState);
     cs.rr = d;
-    cs.rr_prev = d + kMaxW;
+    cs.qp = d + kMaxW;
     cs.rr_ref = d + 2 * kMaxW;
     cs.bb = d + 3 * kMaxW;
     cs.alpha = d + 4 * kMaxW;
@@ -263,12 +264,13 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     cs.tol2 = cfg.tol * cfg.tol;
     cs.delta2 = cfg.delta * cfg.delta;
     cs.hold = cfg.inner == kBF16;
+    cs.rq_direct = cfg.inner == kBF16;  // see the finishing kernel
     cs.exact = cfg.inner == kF64;
     return DP_OK;
 }
 
-static dp_status read_ctrl(dp_ctx *ctx, const CgState &cs, int W, hipStream_t s) {
-    launch_ctrl(cs, W, s);
+static dp_status read_ctrl(dp_ctx *ctx, const Red &rd, const CgState &cs, int W, hipStream_t s) {
+    launch_ctrl(rd, cs, W, s);
     DP_HIP(hipStreamSynchronize(s));
     return DP_OK;
 }
@@ -346,8 +348,7 @@ void block_stats(const void *state, BlockStats &bs, dp_solve_stats *acc) {
 
 // Every argument a captured iteration group passes to its kernels, as a
 // lookup key of the graph cache.
-static std::string graph_key(int steps, int inner, const Launch &L, const StencilArgs &a, const void *r,
-                             const void *xlo) {
+static std::string graph_key(int steps, int inner, const Launch &L, const StencilArgs &a, const void *xlo) {
     std::string k;
     auto put = [&k](const void *v, size_t n) { k.append((const char *)v, n); };
     auto val = [&put](auto v) { put(&v, sizeof v); };
@@ -368,10 +369,12 @@ static std::string graph_key(int steps, int inner, const Launch &L, const Stenci
     val(a.U);
     val((const void *)a.nbr);
     val(a.cg);
+    val(a.rin);
     val((const void *)a.rd.part1);
+    val((const void *)a.rd.part2);
     val(a.rd.nblk);
     const CgState &c = a.cs;
-    for (const void *ptr : {(const void *)c.rr, (const void *)c.rr_prev, (const void *)c.rr_ref,
+    for (const void *ptr : {(const void *)c.rr, (const void *)c.qp, (const void *)c.rr_ref,
                             (const void *)c.bb, (const void *)c.alpha, (const void *)c.beta,
                             (const void *)c.true_rr, (const void *)c.tj, (const void *)c.active,
                             (const void *)c.iters, (const void *)c.flags, (const void *)c.ctrl,
@@ -381,7 +384,7 @@ static std::string graph_key(int steps, int inner, const Launch &L, const Stenci
     val(c.delta2);
     val(c.exact);
     val(c.hold);
-    val(r);
+    val(c.rq_direct);
     val(xlo);
     return k;
 }
@@ -399,15 +402,15 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     DP_HIP(hipGetLastError());
     int nactive = bs.nvalid;
     if (!Init::kLanesNonzero) {
-        DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
+        DP_TRY(read_ctrl(ctx, rd, cs, L.W, L.stream));
         nactive = ctx->ctrl_host[0];
     }
     int it = 0;
-    bool pending = false;  // p = r + beta p not yet applied
     StencilArgs a;
     a.links = op.links;
     a.diag = diag;
     a.pin = p;
+    a.rin = r;
     a.q = q;
     a.U = op.U8;
     a.nbr = op.nbr;
@@ -421,13 +424,13 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     int it_prev = 0, it_ru = 0;
     while (nactive > 0 && it < cfg.max_iter) {
         const int steps = std::min(steps_next, cfg.max_iter - it);
-        if (cfg.use_graph && pending && !cfg.profile) {
-            // the group [update2, stencil, update1] x steps replayed from a
+        if (cfg.use_graph && !cfg.profile) {
+            // the group [stencil, finish, update] x steps replayed from a
             // graph; a graph holds the kernel arguments it was captured with,
             // so it is looked up by all of them (two solves of one call, say
             // the forward and adjoint solves of a gradient, or instances of
             // different shapes, never share a graph)
-            const std::string key = graph_key(steps, cfg.inner, L, a, r, xlo);
+            const std::string key = graph_key(steps, cfg.inner, L, a, xlo);
             auto g = ctx->graphs.find(key);
             if (g == ctx->graphs.end()) {
                 if (ctx->graphs.size() >= 64) ctx->drop_graphs();
@@ -435,9 +438,8 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
                 hipGraphExec_t exec = nullptr;
                 DP_HIP(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal));
                 for (int c = 0; c < steps; ++c) {
-                    launch_update2(L, cfg.inner, r, p, xlo, cs);
                     launch_stencil(L, cfg.inner, a);
-                    launch_update1(L, cfg.inner, r, q, rd, cs);
+                    launch_update(L, cfg.inner, xlo, r, p, q, rd, cs);
                 }
                 DP_HIP(hipStreamEndCapture(L.stream, &graph));
                 const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -448,15 +450,13 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             DP_HIP(hipGraphLaunch(g->second, L.stream));
         } else {
             for (int c = 0; c < steps; ++c) {
-                if (pending) launch_update2(L, cfg.inner, r, p, xlo, cs);
                 DP_TRY(timed_stencil(ctx, cfg, L, a));
-                launch_update1(L, cfg.inner, r, q, rd, cs);
-                pending = true;
+                launch_update(L, cfg.inner, xlo, r, p, q, rd, cs);
             }
         }
         DP_HIP(hipGetLastError());
         it += steps;
-        DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
+        DP_TRY(read_ctrl(ctx, rd, cs, L.W, L.stream));
         nactive = ctx->ctrl_host[0];
         {
             double ratio, ru_ratio;
@@ -471,24 +471,26 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             (ctx->ctrl_host[2] > 0 || ctx->ctrl_host[1] == nactive || it >= cfg.max_iter ||
              it - it_ru >= cfg.ru_gap)) {
             it_ru = it;
-            // reliable update: x64 += xlo, r = b - A x64 in FP64, beta from it
-            launch_fold(L, cfg.inner, x64, xlo, p, cs);
-            launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 1,
+            // reliable update: x64 += xlo, r = b - A x64 in FP64 (p continued
+            // from it), the residual norms restart from it
+            launch_fold(L, cfg.inner, x64, xlo);
+            launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, p, q, 1,
                               rd, cs, init.probe());
             DP_HIP(hipGetLastError());
             ++bs.ru;
-            DP_TRY(read_ctrl(ctx, cs, L.W, L.stream));
+            DP_TRY(read_ctrl(ctx, rd, cs, L.W, L.stream));
             nactive = ctx->ctrl_host[0];
         }
     }
     // Mixed precision: lanes stop only at a reliable update, which folded
     // x and left the FP64 true residual of the final x64 in true_rr, so
     // with no lane active there is nothing left to do.  Otherwise (FP64, or
-    // max_iter reached) apply the deferred solution update of the last
-    // iteration (and xlo) and take the final true residual (statistics).
+    // max_iter reached) fold what is left (mixed) and take the final true
+    // residual (statistics).
     if (!(mixed && nactive == 0)) {
-        launch_fold(L, cfg.inner, x64, mixed ? xlo : nullptr, p, cs);
-        launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, 0, rd, cs, init.probe());
+        if (mixed) launch_fold(L, cfg.inner, x64, xlo);
+        launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, p, q, 0, rd, cs,
+                          init.probe());
         DP_HIP(hipGetLastError());
     }
     // the block's state (one copy); deferred: the caller reads it after its
@@ -559,8 +561,8 @@ static void save_tune_file(dp_ctx *ctx) {
 static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, int W, hipStream_t s,
                             float &ms) {
     Launch L;
-    Red rd;
-    CgState cs;
+    Red rd{};
+    CgState cs{};
     DP_TRY(make_launch(ctx, op, W, s, L, rd, cs, cfg));
     DP_TRY(ctx->ensure(kSlotColors, (size_t)op.lat.N * sizeof(int), true));
     ProbeGen g{};
@@ -578,6 +580,7 @@ static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, 
     a.links = op.links;
     a.diag = op.m2 + 8.0;
     a.pin = ctx->at(kSlotP);
+    a.rin = ctx->at(kSlotR);
     a.q = ctx->at(kSlotQ);
     a.U = op.U8;
     a.nbr = op.nbr;
@@ -585,9 +588,8 @@ static dp_status time_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, 
     a.rd = rd;
     a.cs = cs;
     auto iter = [&]() {
-        launch_update2(L, cfg.inner, ctx->at(kSlotR), ctx->at(kSlotP), xlo, cs);
         launch_stencil(L, cfg.inner, a);
-        launch_update1(L, cfg.inner, ctx->at(kSlotR), ctx->at(kSlotQ), rd, cs);
+        launch_update(L, cfg.inner, xlo, ctx->at(kSlotR), ctx->at(kSlotP), ctx->at(kSlotQ), rd, cs);
     };
     iter();
     iter();
@@ -623,7 +625,8 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
         // Many instances in one launch: the slots keep thousands of lanes in
         // flight at every width, so a width costs what its CG iteration moves
         // per lane-site, 10 vector passes plus the eight hop links of a site
-        // shared by the W lanes, times the padding of every instance's last
+        // shared by the W lanes (stencil: p, r read, q written; update: x, r,
+        // p, q read, x, r, p written), times the padding of every instance's last
         // block (sum ceil(n_i/W) W N_i / sum n_i N_i).  Timing one instance
         // alone instead rewards wide blocks that fill the GPU by themselves
         // (64 uneven lattices: this ranks W = 16/32/64/128 as the measured
