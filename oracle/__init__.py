@@ -246,6 +246,19 @@ def cg_many(dims, nc, m2, links, B, tol=1e-12, maxit=100000):
     return X.reshape(-1, N, nc), it, rel
 
 
+def contractions(dims, nc, V, X, p) -> np.ndarray:
+    """t_j = sum_x sum_b conj(v_j(x, b)) x_j(x + p e0, b) for V, X
+    [nrhs, N, nc] (Sec. 3: the displaced contraction z^H P x with
+    (P x)(x) = x(x + p e0)); unnormalised, one complex value per right-hand
+    side.  A numpy restatement of the definition, beside the C one inside
+    trace(), for contractions of solutions the caller already has."""
+    D = [int(v) for v in _dims(dims)]
+    Vs = np.asarray(V, dtype=np.complex128).reshape(-1, *D, nc)
+    Xs = np.asarray(X, dtype=np.complex128).reshape(-1, *D, nc)
+    Xp = np.roll(Xs, -int(p), axis=1)  # Xp[:, x0] = X[:, x0 + p]
+    return np.sum(np.conj(Vs) * Xp, axis=tuple(range(1, Vs.ndim)))
+
+
 # ----------------------------------------------------------------- estimator
 
 

@@ -421,7 +421,8 @@ class Context:
 
     def trace_grad(self, op, ps, p, opts, want_links=True, check=True):
         """Returns (T, dT/dm2, dT/dU, dT/dUbar, stats); the link gradients are
-        complex128 cuda tensors [4, N, nc, nc] (None if want_links is False)."""
+        complex128 cuda tensors [4, N, nc, nc] (None if want_links is False);
+        stats["tj"] holds the per-right-hand-side contractions t_j."""
         torch = self.torch
         N = int(np.prod(list(op.dims)))
         res = TraceResult()
@@ -437,7 +438,9 @@ class Context:
                                  ctypes.byref(res), g,
                                  None if dU is None else self._cdev(dU, torch.complex128),
                                  None if dUb is None else self._cdev(dUb, torch.complex128), self._stream())
-        out = (complex(res.tr[0], res.tr[1]), complex(g[0], g[1]), dU, dUb, res.solve.asdict())
+        stats = res.solve.asdict()
+        stats["tj"] = per_r.view(np.complex128).copy()  # per-RHS contractions of the forward solves
+        out = (complex(res.tr[0], res.tr[1]), complex(g[0], g[1]), dU, dUb, stats)
         if st != OK and (check or st not in (ENOCONV, EBREAKDOWN)):
             self._err(st, out)
         return out

@@ -311,3 +311,25 @@ def test_gradient_central_differences(dims, p):
         dUdh = 1j * X @ U
         an = np.sum(dU * dUdh) + np.sum(dUb * np.conj(dUdh))
         assert abs(fd - an) < 1e-6 * max(abs(an), 1e-3), (fd, an)
+
+
+def test_contractions_equal_the_trace_per_rhs_terms():
+    """The numpy contraction of the oracle's own solutions equals the per-
+    right-hand-side terms t_j of its C trace (two restatements of Sec. 3's
+    z^H P x), for p = 0, 1 and -1 on a 3-colour gauge lattice, and for p = 0
+    its sum is the dense Hutchinson sum of the probes."""
+    dims, nc, m2 = (4, 2, 3, 2), 3, 0.3
+    U = workloads.random_links(dims, 0.4, 5, nc)
+    col, n, _ = oracle.coloring(dims, 1, 1, oracle.NATURAL)
+    V = oracle.probes(dims, nc, col, n, 9, 0, 1, oracle.Z2_COMPLEX, True)
+    X, its, rel = oracle.cg_many(dims, nc, m2, U, V, tol=1e-13)
+    assert (its > 0).all()
+    for p in (0, 1, -1):
+        t = oracle.contractions(dims, nc, V, X, p)
+        ref = oracle.trace(dims, nc, m2, U, p % dims[0], col, n, 9, 0, 1, oracle.Z2_COMPLEX, True,
+                           tol=1e-13)["tj"]
+        assert np.abs(t - ref).max() < 1e-12 * np.abs(ref).max(), p
+    Ainv = np.linalg.inv(oracle.dense(dims, nc, m2, U))
+    t0 = oracle.contractions(dims, nc, V, X, 0)
+    want = sum(np.vdot(v.ravel(), Ainv @ v.ravel()) for v in V)
+    assert abs(t0.sum() - want) < 1e-10 * abs(want)
