@@ -34,7 +34,9 @@ steps, roofline, CPU oracle baseline and error against the oracle):
       single-right-hand-side FP64 CG (W = 1), tol 1e-10.
 
 value = RHS * site * CG-iteration / s over the K timed steps (iterations
-counted per right-hand side up to its own convergence).  roofline: the
+counted per right-hand side up to its own convergence).  Block widths and
+stencil launches come from the library's autotuner (rhs_block = 0; the
+batch's width from its traffic model), timed in the untimed warm-up.  roofline: the
 stencil kernel (the dominant kernel), its launches timed with HIP events on
 the stream they run on, inside the timed region, against the algorithmic
 bytes the library reports for them.  cg_bandwidth: the whole CG at the
@@ -221,7 +223,8 @@ def cpu_baseline(work, tc, used, sample, rhs_per_sample, samples_1e3):
 def run_gauge16(a, torch, dp, workloads, steps, warmup, cpu, plain):
     w = workloads.GAUGE_16
     inner = a.inner or "f32"
-    W_req = 32 if a.rhs_block is None else a.rhs_block
+    # the block width and stencil launch from the autotuner (timed in the warm-up step)
+    W_req = 0 if a.rhs_block is None else a.rhs_block
     dims, nc, p, N = w.dims, w.nc, w.p, w.volume
     t0 = time.time()
     cols, ncols, _ = dp.build_coloring(dims, p, list(w.ks), "natural")
@@ -408,7 +411,7 @@ def run_uneven(a, torch, dp, workloads, steps, warmup, cpu, plain):
 def run_gauge32(a, torch, dp, workloads, steps, warmup, cpu, plain):
     w = workloads.GAUGE_32
     inner = a.inner or "f32"
-    W_req = 32 if a.rhs_block is None else a.rhs_block
+    W_req = 0 if a.rhs_block is None else a.rhs_block
     dims, nc, p, N = w.dims, w.nc, w.p, w.volume
     t0 = time.time()
     # BEST picks natural here (32 colours; red-black gives more): natural is taken directly

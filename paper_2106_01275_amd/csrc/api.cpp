@@ -3,6 +3,8 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -168,6 +170,17 @@ dp_status dp_create(dp_ctx **out, int32_t hip_device) {
         return DP_ENOMEM;
     }
     ctx->device = hip_device;
+    // DP_STENCIL: unset or "tune" (time the stencil launches per shape),
+    // "rule" (the built-in choice), or "m,w,n" (mode, walk, workgroups)
+    if (const char *e = std::getenv("DP_STENCIL")) {
+        int m = -1, w = 0, n = 0;
+        if (std::strcmp(e, "rule") == 0) {
+            ctx->stencil_policy = 1;
+        } else if (std::sscanf(e, "%d,%d,%d", &m, &w, &n) == 3) {
+            ctx->stencil_policy = 2;
+            ctx->stencil_forced = {{m, w, n}};
+        }
+    }
     if (hipHostMalloc((void **)&ctx->ctrl_host, 64, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->state_host, state_bytes(), hipHostMallocDefault) != hipSuccess) {
         g_err = "dp_create: pinned allocation failed";

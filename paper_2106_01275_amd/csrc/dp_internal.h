@@ -93,6 +93,8 @@ struct Launch {
     int nc, W, logW;
     int nblk, ntiles;   // grid size and number of site tiles
     hipStream_t stream;
+    int smode = -1;     // stencil mode (kernels.hip); -1: the built-in choice for the shape
+    int walk = 0;       // x2-rows per column block of the stencil's slab walk (0: site order)
 };
 
 // One job of a multi-instance launch: a block of W right-hand sides of one
@@ -165,6 +167,9 @@ struct StencilArgs {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // if set: the stencil kernel's own start and stop times
 };
 void launch_stencil(const Launch &L, int prec, const StencilArgs &a);
+// stencil modes 0..6 a launch shape admits, and the choice without timing
+bool stencil_mode_valid(const Launch &L, int prec, int mode);
+int stencil_mode_rule(const Launch &L, int prec);
 // The vector update of a CG iteration: x += alpha p, r -= alpha q,
 // p = r + beta p, and |r|^2 per lane into rd.part2
 void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const void *q, const Red &rd,

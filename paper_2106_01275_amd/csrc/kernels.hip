@@ -138,10 +138,16 @@ __device__ __forceinline__ void tile_range(const Blk &bk, int ntiles, int &t0, i
 // blockIdx % 8 == x) owns the x0-slices [x*D0/8, (x+1)*D0/8) when D0 is a
 // multiple of 8 (otherwise one eighth of the site range); its workgroups
 // walk the slab in steps, all together: step k covers consecutive work
-// items, item w mapping to site (x0_lo + w % n0) * V3 + w / n0 (x0
-// varies fastest).  The sites in flight then form a compact window whose
-// neighbours (x0 ones included) are read at nearly the same time, so they
-// hit in the XCD's L2.
+// items, item w mapping to x0-slice x0_lo + w % n0 (x0 varies fastest) and
+// column c = w / n0 of the (x1, x2, x3) cross-section.  The sites in
+// flight then form a compact window whose neighbours (x0 ones included)
+// are read at nearly the same time, so they hit in the XCD's L2.  Columns
+// are taken in site order (walk == 0: x3 fastest, then x2, then x1), or
+// (walk = b > 0) in blocks of b x2-rows: x3 fastest, then the b rows of
+// the block, then x1, then the block, so that the x1 neighbours of a
+// window are the planes of the block just read or about to be read (a
+// window that spans a whole x1-plane, 32^4 at W = 32, otherwise re-reads
+// both neighbouring planes from beyond the L2).
 struct SiteWalk {
     int items;      // work items of this XCD
     int n0, x0_lo;  // x0-slices of the slab (n0 == 0: plain range)
@@ -149,9 +155,13 @@ struct SiteWalk {
     int V3;         // sites per x0-slice
     int first, stride;  // first tile of this workgroup and tile stride
     int n0s;            // log2 n0 if n0 is a power of two, else -1
+    int b2;             // x2-rows per column block (0: site order)
+    int R, rs;          // columns per x1-plane of a block (b2 * D3), log2 R (or -1)
+    int D1, d1s, D2D3;  // D1, log2 D1 (or -1), D2 * D3
 };
 
-__device__ __forceinline__ SiteWalk site_walk(const Lat &lat, const Blk &bk) {
+__device__ __forceinline__ SiteWalk site_walk(const Launch &L, const Blk &bk) {
+    const Lat &lat = L.lat;
     SiteWalk w;
     const int nb = bk.nb, b = bk.b;
     w.V3 = lat.D[1] * lat.D[2] * lat.D[3];
@@ -179,15 +189,48 @@ __device__ __forceinline__ SiteWalk site_walk(const Lat &lat, const Blk &bk) {
         w.items = lat.N;
     }
     w.n0s = w.n0 > 0 && (w.n0 & (w.n0 - 1)) == 0 ? __builtin_ctz(w.n0) : -1;
+    auto lg = [](int v) { return v > 0 && (v & (v - 1)) == 0 ? __builtin_ctz(v) : -1; };
+    w.b2 = (w.n0 > 0 && L.walk > 0 && L.walk < lat.D[2] && lat.D[2] % L.walk == 0) ? L.walk : 0;
+    w.R = w.b2 * lat.D[3];
+    w.rs = lg(w.R);
+    w.D1 = lat.D[1];
+    w.d1s = lg(lat.D[1]);
+    w.D2D3 = lat.D[2] * lat.D[3];
     return w;
 }
 
-// (a shift and a mask where n0 is a power of two: the walk is taken for
-// every staged link element; 32^4, FP32, W = 32: 1.4% off the stencil)
+// (shifts and masks where the sizes are powers of two: the walk is taken
+// for every staged link element; 32^4, FP32, W = 32: 1.4% off the stencil)
 __device__ __forceinline__ int walk_site(const SiteWalk &w, int item) {
     if (w.n0 == 0) return w.base + item;
-    if (w.n0s >= 0) return (w.x0_lo + (item & (w.n0 - 1))) * w.V3 + (item >> w.n0s);
-    return (w.x0_lo + item % w.n0) * w.V3 + item / w.n0;
+    int x0l, c;
+    if (w.n0s >= 0) {
+        x0l = item & (w.n0 - 1);
+        c = item >> w.n0s;
+    } else {
+        x0l = item % w.n0;
+        c = item / w.n0;
+    }
+    if (w.b2) {
+        // c = ((block * D1 + x1) * b2 + row) * D3 + x3 -> site order
+        int inb, rest, x1, blk;
+        if (w.rs >= 0) {
+            inb = c & (w.R - 1);
+            rest = c >> w.rs;
+        } else {
+            inb = c % w.R;
+            rest = c / w.R;
+        }
+        if (w.d1s >= 0) {
+            x1 = rest & (w.D1 - 1);
+            blk = rest >> w.d1s;
+        } else {
+            x1 = rest % w.D1;
+            blk = rest / w.D1;
+        }
+        c = x1 * w.D2D3 + blk * w.R + inb;
+    }
+    return (w.x0_lo + x0l) * w.V3 + c;
 }
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
@@ -812,7 +855,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const SiteWalk wk = site_walk(L.lat, bk);
+    const SiteWalk wk = site_walk(L, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
         if (MODE == 1) {
@@ -968,7 +1011,7 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const SiteWalk wk = site_walk(L.lat, bk);
+    const SiteWalk wk = site_walk(L, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
         if (MODE == 1) stage_hops<LS, R, NC, LINKS>(su, snb, wk, item0, sites_per_tile, U, nbr);
@@ -1062,6 +1105,9 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
                                                      S *__restrict__ q, const LS *__restrict__ U,
                                                      const int *__restrict__ nbr, int cg, Red rd) {
     using R = typename St<S>::R;
+    // BF16 storage (FP32 arithmetic on the unpacked values here) sums r^H q
+    // and r^H p itself, like the packed BF16 body
+    constexpr bool kDirect = std::is_same<S, bf16x2>::value;
     constexpr int kMaxItems = G == 2 ? 2 * (kBlock / 16) : 4 * (kBlock / 32);
     __shared__ R su[kMaxItems * 8 * NC * NC * 2];
     __shared__ int snb[kMaxItems * 8];
@@ -1071,7 +1117,7 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
     const int sl = tid >> logW;
     const int items_per_tile = G * (kBlock >> logW);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const SiteWalk wk = site_walk(L.lat, bk);
+    const SiteWalk wk = site_walk(L, bk);
     for (int t = wk.first; t * items_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * items_per_tile;
         stage_hops<LS, R, NC, LINKS>(su, snb, wk, item0, items_per_tile, U, nbr);
@@ -1081,11 +1127,13 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
 #pragma unroll
         for (int h = 0; h < G; ++h)
             ld_site<S, NC>(pin, s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1)), logW, j, vor[h], voi[h]);
-        R pqs = 0, qqs = 0;
+        R pqs = 0, qqs = 0, rqs = 0, rps = 0;
 #pragma unroll
         for (int h = 0; h < G; ++h) {
             const int ls = G * sl + h;
             const int site = s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1));
+            R rr_[NC], ri_[NC];  // BF16 storage: the residual (r^H q, r^H p summed here)
+            if (kDirect && cg) ld_site<S, NC>(rin, site, logW, j, rr_, ri_);
             R vr[8][NC], vi[8][NC];
 #pragma unroll
             for (int dir = 0; dir < 8; ++dir) {
@@ -1129,13 +1177,21 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
             for (int a = 0; a < NC; ++a) {
                 St<S>::st(qrow, (unsigned)((a << logW) + j), ar[a], ai[a]);
                 if (cg) {
-                    pqs = fmaR(vor[h][a], ar[a], fmaR(voi[h][a], ai[a], pqs));
-                    qqs = fmaR(ar[a], ar[a], fmaR(ai[a], ai[a], qqs));
+                    R qr = ar[a], qi = ai[a];
+                    St<S>::round(qr, qi);  // the dot products of the stored q
+                    pqs = fmaR(vor[h][a], qr, fmaR(voi[h][a], qi, pqs));
+                    qqs = fmaR(qr, qr, fmaR(qi, qi, qqs));
+                    if (kDirect) {
+                        rqs = fmaR(rr_[a], qr, fmaR(ri_[a], qi, rqs));
+                        rps = fmaR(rr_[a], vor[h][a], fmaR(ri_[a], voi[h][a], rps));
+                    }
                 }
             }
         }
         acc[0] += (double)pqs;
+        acc[1] += (double)rqs;
         acc[2] += (double)qqs;
+        acc[3] += (double)rps;
     }
     if (!cg) return;
     block_partials<4>(bk, acc, W, logW, rd, sm);
@@ -1375,7 +1431,7 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
     double acc[2] = {0.0, 0.0};
-    const SiteWalk wk = site_walk(L.lat, bk);
+    const SiteWalk wk = site_walk(L, bk);
     const unsigned long long seedmix = gen ? mix64(g.seed) : 0ull;
     const ProbeLane pl = gen ? probe_lane(g, NC, g.rhs0 + j) : ProbeLane{};
     const bool restart = ru && (cs.flags[j] & kFlagRestart);
@@ -2023,6 +2079,39 @@ void launch_init_abi(const Launch &L, int prec, const double *babi, long long rh
     k_finish<2, kEpiInit><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
 }
 
+// Stencil modes a launch shape admits.  The grouped modes need the slab walk
+// (a grid of a multiple of 8 workgroups over x0-slabs): pairs an even
+// number of slices per slab, quads two slices and an even D3, lines a
+// multiple of four slices; the LDS tiles take W >= 16 (pairs, mode 1) or
+// W >= 32 (quads, lines); mode 2 a wavefront per site (W >= 64); mode 5
+// one right-hand side (not BF16).
+bool stencil_mode_valid(const Launch &L, int prec, int mode) {
+    const bool slabs = L.nblk >= 8 && L.nblk % 8 == 0 && L.lat.D[0] % 8 == 0;
+    const int n0 = L.lat.D[0] / 8;
+    switch (mode) {
+        case 0: return true;
+        case 1: return L.W >= 16;
+        case 2: return L.W >= 64;
+        case 3: return slabs && n0 % 2 == 0 && L.W >= 16;
+        case 4: return slabs && n0 == 2 && L.lat.D[3] % 2 == 0 && L.W >= 32;
+        case 5: return L.W == 1 && prec != kBF16;
+        case 6: return slabs && n0 % 4 == 0 && L.W >= 32;
+        default: return false;
+    }
+}
+
+// The choice without timing: the grouped modes where they apply (not for
+// BF16, whose packed-dot body has none), else by width.
+int stencil_mode_rule(const Launch &L, int prec) {
+    const bool bf = prec == kBF16;
+    if (L.W == 1 && !bf) return 5;
+    if (L.W >= 64) return 2;
+    if (!bf && stencil_mode_valid(L, prec, 4)) return 4;
+    if (!bf && stencil_mode_valid(L, prec, 6)) return 6;
+    if (!bf && stencil_mode_valid(L, prec, 3)) return 3;
+    return L.W >= 16 ? 1 : 0;
+}
+
 template <typename S, typename LS, int NC, bool LINKS>
 static void stencil_nc(const Launch &L, const StencilArgs &a) {
     using R = typename St<S>::R;
@@ -2036,26 +2125,22 @@ static void stencil_nc(const Launch &L, const StencilArgs &a) {
                               (R)a.diag, pin, rin, q, U, a.nbr, a.cg, a.rd);                            \
     else                                                                                                \
         k_stencil<S, LS, NC, LINKS, M><<<grid, blk, 0, L.stream>>>(L, (R)a.diag, pin, rin, q, U, a.nbr, a.cg, a.rd)
-    // groups: x0-slabs of an even number of slices (the slab walk of
-    // site_walk); quads: slabs of two slices, D3 even, W >= 32 (LDS)
-    const bool slabs = !std::is_same<S, bf16x2>::value && L.nblk >= 8 && L.nblk % 8 == 0;
-    const bool pairs = slabs && L.lat.D[0] % 16 == 0;
-    const bool quads = slabs && L.lat.D[0] == 16 && L.lat.D[3] % 2 == 0 && L.W >= 32;
-    const bool lines = slabs && L.lat.D[0] % 32 == 0 && L.W >= 32;  // slabs of 4k slices
-    if (L.W == 1 && !std::is_same<S, bf16x2>::value)
-        DP_ST(5);
-    else if (L.W >= 64)
-        DP_ST(2);
-    else if (quads)
-        DP_ST(4);
-    else if (lines)
-        DP_ST(6);
-    else if (L.W >= 16 && pairs)
-        DP_ST(3);
-    else if (L.W >= 16)
-        DP_ST(1);
-    else
-        DP_ST(0);
+    constexpr int prec = std::is_same<S, double2>::value ? kF64 : (std::is_same<S, float2>::value ? kF32 : kBF16);
+    const int mode = L.smode >= 0 && stencil_mode_valid(L, prec, L.smode) ? L.smode : stencil_mode_rule(L, prec);
+    switch (mode) {
+        case 5:
+            if constexpr (prec != kBF16) {
+                DP_ST(5);
+                break;
+            }
+            [[fallthrough]];
+        case 0: DP_ST(0); break;
+        case 1: DP_ST(1); break;
+        case 2: DP_ST(2); break;
+        case 3: DP_ST(3); break;
+        case 4: DP_ST(4); break;
+        default: DP_ST(6); break;
+    }
 #undef DP_ST
 }
 

@@ -152,14 +152,34 @@ dp_status WorkStream::leave() {
 
 static size_t prec_bytes(int prec) { return prec == kF64 ? 16 : (prec == kF32 ? 8 : 4); }
 
-int launch_blocks(const Lat &lat, int W) {
+// work units of a launch: site tiles, or for one right-hand side groups of
+// eight sites (the stencil splits a site over 32 threads, eight sites per
+// workgroup, so the launch takes up to N / 8 workgroups; the other kernels
+// leave the extra ones idle)
+static int launch_units(const Lat &lat, int W) {
     int logW = 0;
     while ((1 << logW) < W) ++logW;
     const int ntiles = (lat.N + (kBlock >> logW) - 1) / (kBlock >> logW);
-    // one right-hand side: the stencil splits a site over 32 threads, eight
-    // sites per workgroup, so the launch takes up to N / 8 workgroups (the
-    // other kernels leave the extra ones idle)
-    return grid_blocks(W == 1 ? std::max(ntiles, (lat.N + 7) / 8) : ntiles);
+    return W == 1 ? std::max(ntiles, (lat.N + 7) / 8) : ntiles;
+}
+
+int launch_blocks(const Lat &lat, int W) { return grid_blocks(launch_units(lat, W)); }
+
+// grids the stencil tuner times: the default and 256 .. 2048 workgroups
+// (multiples of 8, not above the work units)
+static std::vector<int> grid_candidates(const Lat &lat, int W) {
+    const int units = launch_units(lat, W), base = launch_blocks(lat, W);
+    std::vector<int> out{base};
+    if (units <= 8) return out;
+    for (int n : {256, 512, 1024, 2048})
+        if (n < units && n != base) out.push_back(n);
+    return out;
+}
+
+int max_launch_blocks(const Lat &lat, int W) {
+    int m = 0;
+    for (int n : grid_candidates(lat, W)) m = std::max(m, n);
+    return m;
 }
 
 size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W) {
@@ -174,7 +194,7 @@ size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W)
         case kSlotP:
         case kSlotQ: return lo;
         case kSlotXLo: return inner != kF64 ? lo : 0;
-        case kSlotPart1: return (size_t)launch_blocks(lat, W) * W * 6 * sizeof(double);  // part1 [.][4], part2 [.][2]
+        case kSlotPart1: return (size_t)max_launch_blocks(lat, W) * W * 6 * sizeof(double);  // part1 [.][4], part2 [.][2]
         case kSlotState: return state_bytes();
         default: return 0;
     }
@@ -225,6 +245,142 @@ dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep
     return DP_OK;
 }
 
+// ---------------------------------------------------------------- stencil tuner
+//
+// The stencil launch of a shape (lattice, nc, precision, links, W) is chosen
+// by timing: every admissible mode (kernels.hip: per-lane links, LDS tiles,
+// wave-uniform sites, x0 pairs, x0 x x3 quads, x0 lines), every grid of
+// grid_candidates and, where the slab walk applies, the column orders
+// (site order, or blocks of 2..16 x2-rows), each over four CG iterations of
+// a block of dense probes (the workgroup count is that of the whole
+// iteration); the built-in choice stands unless another is 2% faster.  Choices are cached per shape in the context and
+// with the block widths in the DP_TUNE_CACHE file.  DP_STENCIL=rule (at
+// context creation) takes the built-in rule instead, DP_STENCIL=m,w,n forces
+// mode m, walk w and n workgroups (-1 / 0 / 0 keep the rule's), where the
+// shape admits them.
+static std::string stencil_key(const OpPrep &op, int inner, int W) {
+    char k[160];
+    std::snprintf(k, sizeof k, "stencil gfx950 dims=%dx%dx%dx%d nc=%d prec=%d links=%d W=%d", op.lat.D[0],
+                  op.lat.D[1], op.lat.D[2], op.lat.D[3], op.nc, inner, op.links ? 1 : 0, W);
+    return k;
+}
+
+static void load_tune_file(dp_ctx *ctx);
+static void save_tune_file(dp_ctx *ctx);
+
+static void apply_choice(const std::array<int, 3> &c, const Lat &lat, int inner, Launch &L) {
+    // any grid up to the largest candidate (the partial sums are sized for it)
+    if (c[2] > 0 && c[2] <= max_launch_blocks(lat, L.W)) L.nblk = c[2];
+    if (c[0] >= 0 && stencil_mode_valid(L, inner, c[0])) L.smode = c[0];
+    L.walk = c[1] > 0 ? c[1] : 0;
+}
+
+// Mean time of one CG iteration (stencil, finish, update) of the block in
+// the workspace under launch shape Lc: the block is initialised with dense
+// probes, one iteration runs untimed, four are timed.
+static dp_status time_iterations(dp_ctx *ctx, const OpPrep &op, int inner, const Launch &Lc, const CgState &cs,
+                                 hipEvent_t e0, hipEvent_t e1, float &ms) {
+    Red rd;
+    rd.part1 = (double *)ctx->at(kSlotPart1);
+    rd.part2 = rd.part1 + (size_t)Lc.nblk * Lc.W * 4;
+    rd.nblk = Lc.nblk;
+    const bool mixed = inner != kF64;
+    void *xlo = mixed ? ctx->at(kSlotXLo) : ctx->at(kSlotX64);
+    ProbeGen g{};
+    g.colors = (const int *)ctx->at(kSlotColors);  // one colour: dense noise
+    g.seed = 12345;
+    g.ncolors = 1;
+    g.noise = DP_NOISE_Z2_COMPLEX;
+    g.nvalid = Lc.W;
+    launch_init_probe(Lc, inner, g, (double *)ctx->at(kSlotB64), ctx->at(kSlotR), ctx->at(kSlotP), xlo,
+                      (double *)ctx->at(kSlotX64), mixed ? 1 : 0, rd, cs);
+    StencilArgs a;
+    a.links = op.links;
+    a.diag = op.m2 + 8.0;
+    a.pin = ctx->at(kSlotP);
+    a.rin = ctx->at(kSlotR);
+    a.q = ctx->at(kSlotQ);
+    a.U = op.U8;
+    a.nbr = op.nbr;
+    a.cg = 1;
+    a.rd = rd;
+    a.cs = cs;
+    auto iter = [&]() {
+        launch_stencil(Lc, inner, a);
+        launch_update(Lc, inner, xlo, ctx->at(kSlotR), ctx->at(kSlotP), ctx->at(kSlotQ), rd, cs);
+    };
+    iter();
+    DP_HIP(hipEventRecord(e0, Lc.stream));
+    for (int k = 0; k < 4; ++k) iter();
+    DP_HIP(hipEventRecord(e1, Lc.stream));
+    DP_HIP(hipEventSynchronize(e1));
+    DP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    DP_HIP(hipGetLastError());
+    return DP_OK;
+}
+
+static dp_status tune_stencil(dp_ctx *ctx, const OpPrep &op, int inner, Launch &L, const CgState &cs,
+                              std::array<int, 3> &best) {
+    DP_TRY(ctx->ensure(kSlotColors, (size_t)L.lat.N * sizeof(int), true));
+    hipEvent_t e0, e1;
+    DP_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    DP_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    // the built-in choice first: another one has to beat it by 2% (timing
+    // noise is about 1%)
+    float best_ms = 1e30f;
+    best = {{-1, 0, L.nblk}};
+    dp_status st = time_iterations(ctx, op, inner, L, cs, e0, e1, best_ms);
+    best_ms *= 0.98f;
+    for (int n : grid_candidates(L.lat, L.W)) {
+        if (st != DP_OK) break;
+        Launch Lc = L;
+        Lc.nblk = n;
+        const bool slab_walk = n >= 8 && n % 8 == 0 && L.lat.D[0] % 8 == 0;
+        for (int mode = 0; mode <= 6 && st == DP_OK; ++mode) {
+            if (!stencil_mode_valid(Lc, inner, mode)) continue;
+            std::vector<int> walks{0};
+            if (slab_walk && mode != 5)
+                for (int b = 2; b <= 16; b *= 2)
+                    if (b < L.lat.D[2] && L.lat.D[2] % b == 0) walks.push_back(b);
+            for (int w : walks) {
+                Lc.smode = mode;
+                Lc.walk = w;
+                float ms = 0;
+                st = time_iterations(ctx, op, inner, Lc, cs, e0, e1, ms);
+                if (st != DP_OK) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = {{mode, w, n}};
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+dp_status pick_stencil(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, Launch &L, const CgState &cs) {
+    const int inner = cfg.inner;
+    if (ctx->stencil_policy == 1) return DP_OK;
+    if (ctx->stencil_policy == 2) {
+        apply_choice(ctx->stencil_forced, L.lat, inner, L);
+        return DP_OK;
+    }
+    load_tune_file(ctx);
+    const std::string key = stencil_key(op, inner, L.W);
+    auto it = ctx->tuned_st.find(key);
+    if (it == ctx->tuned_st.end()) {
+        if (ctx->no_alloc) return DP_OK;  // (timing takes events: the built-in rule)
+        std::array<int, 3> best;
+        DP_TRY(tune_stencil(ctx, op, inner, L, cs, best));
+        it = ctx->tuned_st.emplace(key, best).first;
+        save_tune_file(ctx);
+    }
+    apply_choice(it->second, L.lat, inner, L);
+    return DP_OK;
+}
+
 dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launch &L, Red &rd, CgState &cs,
                       const SolveCfg &cfg) {
     int logW = 0;
@@ -236,13 +392,12 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     L.ntiles = (op.lat.N + (kBlock >> logW) - 1) / (kBlock >> logW);
     L.nblk = launch_blocks(op.lat, W);
     L.stream = s;
+    L.smode = -1;
+    L.walk = 0;
     for (int slot : {kSlotB64, kSlotX64, kSlotR, kSlotP, kSlotQ, kSlotXLo, kSlotPart1, kSlotState}) {
         const size_t b = slot_size(slot, op.lat, op.nc, op.links, cfg.inner, W);
         if (b) DP_TRY(ctx->ensure(slot, b));
     }
-    rd.part1 = (double *)ctx->at(kSlotPart1);
-    rd.part2 = rd.part1 + (size_t)L.nblk * W * 4;
-    rd.nblk = L.nblk;
     const size_t nd = 9 * kMaxW + 8;
     double *d = (double *)ctx->at(kSlotState);
     cs.rr = d;
@@ -266,6 +421,10 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     cs.hold = cfg.inner == kBF16;
     cs.rq_direct = cfg.inner == kBF16;  // see the finishing kernel
     cs.exact = cfg.inner == kF64;
+    DP_TRY(pick_stencil(ctx, op, cfg, L, cs));
+    rd.part1 = (double *)ctx->at(kSlotPart1);
+    rd.part2 = rd.part1 + (size_t)L.nblk * W * 4;
+    rd.nblk = L.nblk;
     return DP_OK;
 }
 
@@ -509,11 +668,11 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
 }
 
 // Autotuner of the right-hand-side block width W (one instance): for each
-// candidate W (powers of two from 8 to 128, not above the next power of two
+// candidate W (powers of two from 8 to 256, not above the next power of two
 // of nrhs, within a memory budget) a block of dense random right-hand sides
-// runs 2 + 6 CG iterations of the real kernels; the 6 are timed with HIP
-// events and the cost per useful right-hand side and iteration,
-// time / min(W, nrhs), decides.  The choices are cached per (N, nc,
+// runs 2 + 6 CG iterations of the real kernels, each width with its own
+// tuned stencil launch; the 6 are timed with HIP events and the cost per
+// useful right-hand side and iteration, time / min(W, nrhs), decides.  The choices are cached per (N, nc,
 // precision, links, next power of two of nrhs) in the context, and in the
 // JSON file named by DP_TUNE_CACHE when that variable is set.  A batch of
 // instances is not timed: its width comes from a traffic model (see
@@ -535,12 +694,20 @@ static void load_tune_file(dp_ctx *ctx) {
     if (!f) return;
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
-        // lines of the form   "<key>": <W>,
+        // lines of the form   "<key>": <W>,   or   "<stencil key>": "<mode>,<walk>,<workgroups>",
         char *a = std::strchr(line, '"');
         char *b = a ? std::strchr(a + 1, '"') : nullptr;
         char *c = b ? std::strchr(b, ':') : nullptr;
         if (!c) continue;
-        ctx->tuned_w[std::string(a + 1, b)] = std::atoi(c + 1);
+        const std::string key(a + 1, b);
+        const char *v = c + 1;
+        while (*v == ' ') ++v;
+        if (*v == '"') {
+            std::array<int, 3> ch{{-1, 0, 0}};
+            if (std::sscanf(v + 1, "%d,%d,%d", &ch[0], &ch[1], &ch[2]) == 3) ctx->tuned_st[key] = ch;
+        } else {
+            ctx->tuned_w[key] = std::atoi(v);
+        }
     }
     std::fclose(f);
 }
@@ -551,9 +718,12 @@ static void save_tune_file(dp_ctx *ctx) {
     FILE *f = std::fopen(path, "w");
     if (!f) return;
     std::fprintf(f, "{\n");
+    const size_t n = ctx->tuned_w.size() + ctx->tuned_st.size();
     size_t i = 0;
-    for (auto &kv : ctx->tuned_w)
-        std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < ctx->tuned_w.size() ? "," : "");
+    for (auto &kv : ctx->tuned_w) std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < n ? "," : "");
+    for (auto &kv : ctx->tuned_st)
+        std::fprintf(f, "  \"%s\": \"%d,%d,%d\"%s\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2],
+                     ++i < n ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
 }
@@ -668,7 +838,7 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
     double best = 1e300;
     int best_w = 1;
     bool timed = false;
-    for (int w = 8; w <= 128; w *= 2) {
+    for (int w = 8; w <= kMaxW; w *= 2) {
         if (w > 8 && w / 2 >= nrhs) break;
         if (bytes_per_w * w > ((size_t)32 << 30)) break;
         float ms = 0;

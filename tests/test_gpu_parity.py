@@ -471,3 +471,61 @@ def test_autotuned_width(ctx, tmp_path, monkeypatch):
     assert r3["solve"]["rhs_block"] == W
     c2.close()
     c3.close()
+
+
+# ------------------------------------------------------------------ stencil launches
+
+
+def _forced_context(monkeypatch, cfg):
+    """A context whose stencil launches are forced to cfg = (mode, walk,
+    workgroups) (the DP_STENCIL variable is read at context creation)."""
+    monkeypatch.setenv("DP_STENCIL", ",".join(str(v) for v in cfg))
+    c = dp.Context(0)
+    monkeypatch.delenv("DP_STENCIL")
+    return c
+
+
+@pytest.mark.parametrize("prec,rtol", [("f64", 1e-14), ("f32", 2e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("dims,nc,links,nrhs,modes", [
+    # two-slice slabs (D0 = 16): pairs, quads; four-slice slabs (D0 = 32): lines
+    ((16, 4, 4, 4), 3, True, 32, (0, 1, 3, 4)), ((32, 4, 4, 2), 3, True, 32, (0, 1, 3, 6)),
+    ((16, 2, 4, 4), 1, False, 64, (0, 1, 2, 3, 4)), ((32, 2, 4, 2), 3, True, 16, (0, 1, 3))])
+def test_apply_every_stencil_mode(monkeypatch, prec, rtol, dims, nc, links, nrhs, modes):
+    """Every stencil launch the tuner may pick gives the operator: each
+    admissible mode (the BF16 grouped ones included), with the slab walk in
+    site order and in blocks of two x2-rows, on a grid of 8 and of 16
+    workgroups, against the oracle's operator."""
+    _say("apply modes", prec, dims, nc, links, nrhs, modes)
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(17)
+    U = workloads.random_links(dims, 0.7, 4, nc) if links else None
+    V = rng.standard_normal((nrhs, N, nc)) + 1j * rng.standard_normal((nrhs, N, nc))
+    want = np.stack([oracle.apply(dims, nc, 0.3, U, v) for v in V])
+    for mode in modes:
+        for walk in (0, 2):
+            for nblk in (8, 16):
+                c = _forced_context(monkeypatch, (mode, walk, nblk))
+                op = c.operator(dims, nc, 0.3, None if U is None else cuda(U))
+                got = c.apply(op, cuda(V), prec).cpu().numpy()
+                c.close()
+                err = np.abs(got - want).max() / np.abs(want).max()
+                assert err < rtol, (mode, walk, nblk, err)
+
+
+def test_stencil_choice_solves(monkeypatch):
+    """Solves through forced grouped launches (FP32 lines with a blocked
+    walk; BF16 quads, whose stencil sums r^H q and r^H p itself) meet the
+    oracle like the default launch."""
+    dims, nc = (32, 4, 4, 2), 3
+    U = workloads.random_links(dims, 0.4, 8, nc)
+    col, n, _ = oracle.coloring(dims, 1, 2, oracle.NATURAL)
+    o = oracle.trace(dims, nc, 0.1, U, 1, col, n, 2, 0, 1, oracle.Z2_COMPLEX, True, tol=1e-12)
+    for cfg, inner in (((6, 2, 16), "f32"), ((3, 0, 16), "bf16"), ((1, 2, 8), "bf16")):
+        c = _forced_context(monkeypatch, cfg)
+        colg = cuda(col)
+        ps = c.probe_spec(dims, nc, colg, n, 2, 0, 1, "z2_complex", True)
+        op = c.operator(dims, nc, 0.1, cuda(U))
+        r = c.trace_estimate([op], [ps], [1], c.opts(tol=1e-10, inner=inner, rhs_block=32))[0]
+        c.close()
+        assert abs(r["T"] - o["T"]) < 1e-6 * abs(o["T"]), (cfg, inner, r["T"], o["T"])
+        assert np.abs(r["tj"] - o["tj"]).max() < 1e-6 * np.abs(o["tj"]).max()

@@ -1,0 +1,153 @@
+"""The launch autotuner against explicit sweeps.
+
+The stencil tuner (rhs_block given, DP_STENCIL unset) picks a stencil mode,
+slab-walk order and workgroup count per shape by timing CG iterations; here
+every candidate it considers is forced in turn (DP_STENCIL=m,w,n) and timed
+by the same solve, and the tuned choice must be within 6% of the fastest
+(median of repeated timings of the finalists).  For a multi-instance batch the width
+comes from a traffic model; it must be within 6% of the fastest of the
+widths 16..128 timed one by one.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2106_01275_amd as dp  # noqa: E402
+
+SLACK = 1.06
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _candidates(dims, W, inner):
+    """The tuner's candidate launches (mode, walk, workgroups) for a shape."""
+    N = int(np.prod(dims))
+    units = -(-N // (256 // W)) if W > 1 else max(-(-N // 256), -(-N // 8))
+    base = units if units <= 8 else min(units, 1024) - min(units, 1024) % 8
+    grids = [base] + [n for n in (256, 512, 1024, 2048) if n < units and n != base]
+    out = []
+    for n in grids:
+        slabs = n >= 8 and n % 8 == 0 and dims[0] % 8 == 0
+        n0 = dims[0] // 8
+        valid = {0: True, 1: W >= 16, 2: W >= 64, 3: slabs and n0 % 2 == 0 and W >= 16,
+                 4: slabs and n0 == 2 and dims[3] % 2 == 0 and W >= 32, 5: W == 1 and inner != "bf16",
+                 6: slabs and n0 % 4 == 0 and W >= 32}
+        for mode in range(7):
+            if not valid[mode]:
+                continue
+            walks = [0]
+            if slabs and mode != 5:
+                walks += [b for b in (2, 4, 8, 16) if b < dims[2] and dims[2] % b == 0]
+            out += [(mode, w, n) for w in walks]
+    return out
+
+
+def _iter_time(c, dims, nc, U, B, inner, W, iters=12, reps=3):
+    """Least wall time over reps of a solve of exactly `iters` CG iterations
+    (tol unreachable), after one untimed solve (which tunes, when the
+    context tunes)."""
+    op = c.operator(dims, nc, 0.05, U)
+    o = c.opts(tol=1e-30, max_iter=iters, inner=inner, rhs_block=W)
+    c.solve_batch([op], [B], o, check=False)
+    best = 1e30
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c.solve_batch([op], [B], o, check=False)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (32, 32, 32, 32)])
+def test_stencil_tuner_matches_sweep(monkeypatch, tmp_path, dims):
+    """Every candidate launch timed once; then the tuned choice and the three
+    fastest candidates timed again, round-robin, five times each (the
+    medians are compared: single short solves vary by several per cent on a
+    busy GPU)."""
+    inner, W, nc = "f32", 32, 3
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(3)
+    # timing only: links need not be unitary
+    U = torch.from_numpy(rng.standard_normal((4, N, nc, nc)) * 0.3 + 0j).cuda()
+    B = torch.from_numpy(rng.standard_normal((W, N, nc)) + 1j * rng.standard_normal((W, N, nc))).cuda()
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("DP_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("DP_STENCIL", raising=False)
+    ct = dp.Context(0)
+    _iter_time(ct, dims, nc, U, B, inner, W, reps=1)
+    ct.close()
+    key = f"stencil gfx950 dims={'x'.join(map(str, dims))} nc={nc} prec=1 links=1 W={W}"
+    text = cache.read_text()
+    assert key in text
+    tuned = tuple(int(v) for v in text.split(key)[1].split('"')[2].split(","))
+    monkeypatch.delenv("DP_TUNE_CACHE")
+
+    def forced(cfg):
+        monkeypatch.setenv("DP_STENCIL", ",".join(map(str, cfg)))
+        c = dp.Context(0)
+        monkeypatch.delenv("DP_STENCIL")
+        return c
+
+    times = {}
+    for cfg in _candidates(dims, W, inner):
+        c = forced(cfg)
+        times[cfg] = _iter_time(c, dims, nc, U, B, inner, W, reps=2)
+        c.close()
+    top = sorted(times, key=times.get)[:3]
+    finalists = [tuned] + [t for t in top if t != tuned]
+    ctxs = {cfg: forced(cfg) for cfg in finalists}
+    runs = {cfg: [] for cfg in finalists}
+    for _ in range(5):
+        for cfg in finalists:
+            runs[cfg].append(_iter_time(ctxs[cfg], dims, nc, U, B, inner, W, iters=24, reps=1))
+    for c in ctxs.values():
+        c.close()
+    med = {cfg: float(np.median(v)) for cfg, v in runs.items()}
+    best = min(med, key=med.get)
+    _say(dims, "tuned", tuned, "medians", {k: round(v * 1e3, 2) for k, v in med.items()})
+    assert med[tuned] <= SLACK * med[best], (tuned, med)
+
+
+def test_batch_width_model_matches_sweep():
+    """The 64-instance uneven BF16 batch: the width of the traffic model
+    (rhs_block = 0) against the widths 16, 32, 64, 128 timed one by one."""
+    inst = workloads.uneven_batch()
+    c = dp.Context(0)
+    ops, specs = [], []
+    for w in inst:
+        col, m, _ = dp.build_coloring(w.dims, w.p, w.ks[0], w.order)
+        ops.append(c.operator(w.dims, w.nc, w.m2, torch.from_numpy(w.links()).cuda()))
+        specs.append(c.probe_spec(w.dims, w.nc, torch.from_numpy(np.ascontiguousarray(col)).cuda(), m,
+                                  w.noise_seed, 0, 1, "z2_complex", True))
+    ps = [w.p for w in inst]
+
+    def step_time(W):
+        o = c.opts(tol=1e-8, inner="bf16", rhs_block=W)
+        r = c.trace_estimate(ops, specs, ps, o)
+        best = 1e30
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            c.trace_estimate(ops, specs, ps, o)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best, r[0]["solve"]["rhs_block"]
+
+    t_model, W_model = step_time(0)
+    times = {W: step_time(W)[0] for W in (16, 32, 64, 128)}
+    best = min(times, key=times.get)
+    _say("batch width: model", W_model, f"{t_model * 1e3:.1f} ms", "sweep",
+         {k: round(v * 1e3, 1) for k, v in times.items()})
+    assert t_model <= SLACK * times[best], (W_model, t_model, best, times[best])
+    c.close()
