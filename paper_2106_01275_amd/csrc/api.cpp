@@ -171,14 +171,14 @@ dp_status dp_create(dp_ctx **out, int32_t hip_device) {
     }
     ctx->device = hip_device;
     // DP_STENCIL: unset or "tune" (time the stencil launches per shape),
-    // "rule" (the built-in choice), or "m,w,n" (mode, walk, workgroups)
+    // "rule" (the built-in choice), or "m,n" (mode, workgroups)
     if (const char *e = std::getenv("DP_STENCIL")) {
-        int m = -1, w = 0, n = 0;
+        int m = -1, n = 0;
         if (std::strcmp(e, "rule") == 0) {
             ctx->stencil_policy = 1;
-        } else if (std::sscanf(e, "%d,%d,%d", &m, &w, &n) == 3) {
+        } else if (std::sscanf(e, "%d,%d", &m, &n) == 2) {
             ctx->stencil_policy = 2;
-            ctx->stencil_forced = {{m, w, n}};
+            ctx->stencil_forced = {{m, n}};
         }
     }
     if (hipHostMalloc((void **)&ctx->ctrl_host, 64, hipHostMallocDefault) != hipSuccess ||

@@ -69,12 +69,12 @@ struct dp_ctx {
     double ev_bytes_all = 0;                  // algorithmic bytes of every profiled launch
     dp_status harvest_events(size_t n);       // reads and recycles the n oldest pending event pairs
     std::map<std::string, int> tuned_w;       // autotuned block widths
-    // autotuned stencil launches: mode, walk, workgroups per (shape, precision, W)
-    std::map<std::string, std::array<int, 3>> tuned_st;
+    // autotuned stencil launches: mode, workgroups per (shape, precision, W)
+    std::map<std::string, std::array<int, 2>> tuned_st;
     // DP_STENCIL at context creation: 0 tune (default), 1 the built-in rule,
-    // 2 forced to stencil_forced (mode, walk, workgroups; -1 / 0 keep the rule's)
+    // 2 forced to stencil_forced (mode, workgroups; -1 / 0 keep the rule's)
     int stencil_policy = 0;
-    std::array<int, 3> stencil_forced{{-1, 0, 0}};
+    std::array<int, 2> stencil_forced{{-1, 0}};
     bool tune_loaded = false;
     int check_every = 8;
     hipStream_t gstream = nullptr;            // library stream for graph capture
@@ -128,7 +128,7 @@ int max_launch_blocks(const Lat &lat, int W);
 size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W);
 dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launch &L, Red &rd, CgState &cs,
                       const SolveCfg &cfg);
-// the stencil launch (mode, slab walk, workgroups) of L's shape: cached,
+// the stencil launch (mode, workgroups) of L's shape: cached,
 // else timed (solver.cpp), or as DP_STENCIL says
 dp_status pick_stencil(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, Launch &L, const CgState &cs);
 // Runs CG on the block initialised by `init` (a callable launching the init

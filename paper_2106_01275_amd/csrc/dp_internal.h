@@ -94,7 +94,6 @@ struct Launch {
     int nblk, ntiles;   // grid size and number of site tiles
     hipStream_t stream;
     int smode = -1;     // stencil mode (kernels.hip); -1: the built-in choice for the shape
-    int walk = 0;       // x2-rows per column block of the stencil's slab walk (0: site order)
 };
 
 // One job of a multi-instance launch: a block of W right-hand sides of one

@@ -249,15 +249,14 @@ dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep
 //
 // The stencil launch of a shape (lattice, nc, precision, links, W) is chosen
 // by timing: every admissible mode (kernels.hip: per-lane links, LDS tiles,
-// wave-uniform sites, x0 pairs, x0 x x3 quads, x0 lines), every grid of
-// grid_candidates and, where the slab walk applies, the column orders
-// (site order, or blocks of 2..16 x2-rows), each over four CG iterations of
-// a block of dense probes (the workgroup count is that of the whole
-// iteration); the built-in choice stands unless another is 2% faster.  Choices are cached per shape in the context and
+// wave-uniform sites, x0 pairs, x0 x x3 quads, x0 lines) on every grid of
+// grid_candidates, each over four CG iterations of a block of dense probes
+// (the workgroup count is that of the whole iteration); the built-in
+// choice stands unless another is 2% faster.  Choices are cached per shape in the context and
 // with the block widths in the DP_TUNE_CACHE file.  DP_STENCIL=rule (at
-// context creation) takes the built-in rule instead, DP_STENCIL=m,w,n forces
-// mode m, walk w and n workgroups (-1 / 0 / 0 keep the rule's), where the
-// shape admits them.
+// context creation) takes the built-in rule instead, DP_STENCIL=m,n forces
+// mode m and n workgroups (-1 / 0 keep the rule's), where the shape admits
+// them.
 static std::string stencil_key(const OpPrep &op, int inner, int W) {
     char k[160];
     std::snprintf(k, sizeof k, "stencil gfx950 dims=%dx%dx%dx%d nc=%d prec=%d links=%d W=%d", op.lat.D[0],
@@ -268,11 +267,10 @@ static std::string stencil_key(const OpPrep &op, int inner, int W) {
 static void load_tune_file(dp_ctx *ctx);
 static void save_tune_file(dp_ctx *ctx);
 
-static void apply_choice(const std::array<int, 3> &c, const Lat &lat, int inner, Launch &L) {
+static void apply_choice(const std::array<int, 2> &c, const Lat &lat, int inner, Launch &L) {
     // any grid up to the largest candidate (the partial sums are sized for it)
-    if (c[2] > 0 && c[2] <= max_launch_blocks(lat, L.W)) L.nblk = c[2];
+    if (c[1] > 0 && c[1] <= max_launch_blocks(lat, L.W)) L.nblk = c[1];
     if (c[0] >= 0 && stencil_mode_valid(L, inner, c[0])) L.smode = c[0];
-    L.walk = c[1] > 0 ? c[1] : 0;
 }
 
 // Mean time of one CG iteration (stencil, finish, update) of the block in
@@ -320,7 +318,7 @@ static dp_status time_iterations(dp_ctx *ctx, const OpPrep &op, int inner, const
 }
 
 static dp_status tune_stencil(dp_ctx *ctx, const OpPrep &op, int inner, Launch &L, const CgState &cs,
-                              std::array<int, 3> &best) {
+                              std::array<int, 2> &best) {
     DP_TRY(ctx->ensure(kSlotColors, (size_t)L.lat.N * sizeof(int), true));
     hipEvent_t e0, e1;
     DP_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
@@ -328,30 +326,21 @@ static dp_status tune_stencil(dp_ctx *ctx, const OpPrep &op, int inner, Launch &
     // the built-in choice first: another one has to beat it by 2% (timing
     // noise is about 1%)
     float best_ms = 1e30f;
-    best = {{-1, 0, L.nblk}};
+    best = {{-1, L.nblk}};
     dp_status st = time_iterations(ctx, op, inner, L, cs, e0, e1, best_ms);
     best_ms *= 0.98f;
     for (int n : grid_candidates(L.lat, L.W)) {
         if (st != DP_OK) break;
         Launch Lc = L;
         Lc.nblk = n;
-        const bool slab_walk = n >= 8 && n % 8 == 0 && L.lat.D[0] % 8 == 0;
         for (int mode = 0; mode <= 6 && st == DP_OK; ++mode) {
             if (!stencil_mode_valid(Lc, inner, mode)) continue;
-            std::vector<int> walks{0};
-            if (slab_walk && mode != 5)
-                for (int b = 2; b <= 16; b *= 2)
-                    if (b < L.lat.D[2] && L.lat.D[2] % b == 0) walks.push_back(b);
-            for (int w : walks) {
-                Lc.smode = mode;
-                Lc.walk = w;
-                float ms = 0;
-                st = time_iterations(ctx, op, inner, Lc, cs, e0, e1, ms);
-                if (st != DP_OK) break;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = {{mode, w, n}};
-                }
+            Lc.smode = mode;
+            float ms = 0;
+            st = time_iterations(ctx, op, inner, Lc, cs, e0, e1, ms);
+            if (st == DP_OK && ms < best_ms) {
+                best_ms = ms;
+                best = {{mode, n}};
             }
         }
     }
@@ -372,7 +361,7 @@ dp_status pick_stencil(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, Launc
     auto it = ctx->tuned_st.find(key);
     if (it == ctx->tuned_st.end()) {
         if (ctx->no_alloc) return DP_OK;  // (timing takes events: the built-in rule)
-        std::array<int, 3> best;
+        std::array<int, 2> best;
         DP_TRY(tune_stencil(ctx, op, inner, L, cs, best));
         it = ctx->tuned_st.emplace(key, best).first;
         save_tune_file(ctx);
@@ -393,7 +382,6 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     L.nblk = launch_blocks(op.lat, W);
     L.stream = s;
     L.smode = -1;
-    L.walk = 0;
     for (int slot : {kSlotB64, kSlotX64, kSlotR, kSlotP, kSlotQ, kSlotXLo, kSlotPart1, kSlotState}) {
         const size_t b = slot_size(slot, op.lat, op.nc, op.links, cfg.inner, W);
         if (b) DP_TRY(ctx->ensure(slot, b));
@@ -694,7 +682,7 @@ static void load_tune_file(dp_ctx *ctx) {
     if (!f) return;
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
-        // lines of the form   "<key>": <W>,   or   "<stencil key>": "<mode>,<walk>,<workgroups>",
+        // lines of the form   "<key>": <W>,   or   "<stencil key>": "<mode>,<workgroups>",
         char *a = std::strchr(line, '"');
         char *b = a ? std::strchr(a + 1, '"') : nullptr;
         char *c = b ? std::strchr(b, ':') : nullptr;
@@ -703,8 +691,8 @@ static void load_tune_file(dp_ctx *ctx) {
         const char *v = c + 1;
         while (*v == ' ') ++v;
         if (*v == '"') {
-            std::array<int, 3> ch{{-1, 0, 0}};
-            if (std::sscanf(v + 1, "%d,%d,%d", &ch[0], &ch[1], &ch[2]) == 3) ctx->tuned_st[key] = ch;
+            std::array<int, 2> ch{{-1, 0}};
+            if (std::sscanf(v + 1, "%d,%d", &ch[0], &ch[1]) == 2) ctx->tuned_st[key] = ch;
         } else {
             ctx->tuned_w[key] = std::atoi(v);
         }
@@ -722,8 +710,7 @@ static void save_tune_file(dp_ctx *ctx) {
     size_t i = 0;
     for (auto &kv : ctx->tuned_w) std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < n ? "," : "");
     for (auto &kv : ctx->tuned_st)
-        std::fprintf(f, "  \"%s\": \"%d,%d,%d\"%s\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2],
-                     ++i < n ? "," : "");
+        std::fprintf(f, "  \"%s\": \"%d,%d\"%s\n", kv.first.c_str(), kv.second[0], kv.second[1], ++i < n ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
 }

@@ -477,7 +477,7 @@ def test_autotuned_width(ctx, tmp_path, monkeypatch):
 
 
 def _forced_context(monkeypatch, cfg):
-    """A context whose stencil launches are forced to cfg = (mode, walk,
+    """A context whose stencil launches are forced to cfg = (mode,
     workgroups) (the DP_STENCIL variable is read at context creation)."""
     monkeypatch.setenv("DP_STENCIL", ",".join(str(v) for v in cfg))
     c = dp.Context(0)
@@ -492,9 +492,8 @@ def _forced_context(monkeypatch, cfg):
     ((16, 2, 4, 4), 1, False, 64, (0, 1, 2, 3, 4)), ((32, 2, 4, 2), 3, True, 16, (0, 1, 3))])
 def test_apply_every_stencil_mode(monkeypatch, prec, rtol, dims, nc, links, nrhs, modes):
     """Every stencil launch the tuner may pick gives the operator: each
-    admissible mode (the BF16 grouped ones included), with the slab walk in
-    site order and in blocks of two x2-rows, on a grid of 8 and of 16
-    workgroups, against the oracle's operator."""
+    admissible mode (the BF16 grouped ones included), on a grid of 8 and of
+    16 workgroups, against the oracle's operator."""
     _say("apply modes", prec, dims, nc, links, nrhs, modes)
     N = int(np.prod(dims))
     rng = np.random.default_rng(17)
@@ -502,25 +501,24 @@ def test_apply_every_stencil_mode(monkeypatch, prec, rtol, dims, nc, links, nrhs
     V = rng.standard_normal((nrhs, N, nc)) + 1j * rng.standard_normal((nrhs, N, nc))
     want = np.stack([oracle.apply(dims, nc, 0.3, U, v) for v in V])
     for mode in modes:
-        for walk in (0, 2):
-            for nblk in (8, 16):
-                c = _forced_context(monkeypatch, (mode, walk, nblk))
-                op = c.operator(dims, nc, 0.3, None if U is None else cuda(U))
-                got = c.apply(op, cuda(V), prec).cpu().numpy()
-                c.close()
-                err = np.abs(got - want).max() / np.abs(want).max()
-                assert err < rtol, (mode, walk, nblk, err)
+        for nblk in (8, 16):
+            c = _forced_context(monkeypatch, (mode, nblk))
+            op = c.operator(dims, nc, 0.3, None if U is None else cuda(U))
+            got = c.apply(op, cuda(V), prec).cpu().numpy()
+            c.close()
+            err = np.abs(got - want).max() / np.abs(want).max()
+            assert err < rtol, (mode, nblk, err)
 
 
 def test_stencil_choice_solves(monkeypatch):
-    """Solves through forced grouped launches (FP32 lines with a blocked
-    walk; BF16 quads, whose stencil sums r^H q and r^H p itself) meet the
-    oracle like the default launch."""
+    """Solves through forced launches (FP32 lines on 16 workgroups; BF16
+    pairs, whose grouped stencil sums r^H q and r^H p itself, and the BF16
+    LDS tiles on 8) meet the oracle like the default launch."""
     dims, nc = (32, 4, 4, 2), 3
     U = workloads.random_links(dims, 0.4, 8, nc)
     col, n, _ = oracle.coloring(dims, 1, 2, oracle.NATURAL)
     o = oracle.trace(dims, nc, 0.1, U, 1, col, n, 2, 0, 1, oracle.Z2_COMPLEX, True, tol=1e-12)
-    for cfg, inner in (((6, 2, 16), "f32"), ((3, 0, 16), "bf16"), ((1, 2, 8), "bf16")):
+    for cfg, inner in (((6, 16), "f32"), ((3, 16), "bf16"), ((1, 8), "bf16")):
         c = _forced_context(monkeypatch, cfg)
         colg = cuda(col)
         ps = c.probe_spec(dims, nc, colg, n, 2, 0, 1, "z2_complex", True)
