@@ -68,7 +68,7 @@ struct dp_ctx {
     unsigned ev_seq = 0;                      // timed-launch candidates so far (sampling)
     double ev_bytes_all = 0;                  // algorithmic bytes of every profiled launch
     dp_status harvest_events(size_t n);       // reads and recycles the n oldest pending event pairs
-    std::map<std::string, int> tuned_w;       // autotuned block widths
+    std::map<std::string, double> tuned_w;    // ms per CG iteration at a block width
     // autotuned stencil launches: mode, workgroups per (shape, precision, W)
     std::map<std::string, std::array<int, 2>> tuned_st;
     // DP_STENCIL at context creation: 0 tune (default), 1 the built-in rule,

@@ -659,18 +659,18 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
 // candidate W (powers of two from 8 to 256, not above the next power of two
 // of nrhs, within a memory budget) a block of dense random right-hand sides
 // runs 2 + 6 CG iterations of the real kernels, each width with its own
-// tuned stencil launch; the 6 are timed with HIP events and the cost per
-// useful right-hand side and iteration, time / min(W, nrhs), decides.  The choices are cached per (N, nc,
-// precision, links, next power of two of nrhs) in the context, and in the
-// JSON file named by DP_TUNE_CACHE when that variable is set.  A batch of
-// instances is not timed: its width comes from a traffic model (see
-// choose_width).
-static std::string tune_key(const OpPrep &op, const SolveCfg &cfg, long long nrhs) {
-    long long b = 1;
-    while (b < nrhs && b < kMaxW) b *= 2;
+// tuned stencil launch; the 6 are timed with HIP events.  The chosen W
+// solves all nrhs right-hand sides in the least time per iteration,
+// ceil(nrhs / W) blocks times the time of one (the padding of the last block
+// is paid for: 96 right-hand sides take 3 blocks of 32 or 2 of 64).  The
+// time per width is cached per (dims, nc, precision, links, W) in the
+// context, and in the JSON file named by DP_TUNE_CACHE when that variable is
+// set.  A batch of instances is not timed: its width comes from a traffic
+// model (see choose_width).
+static std::string width_key(const OpPrep &op, const SolveCfg &cfg, int W) {
     char k[160];
-    std::snprintf(k, sizeof k, "gfx950 N=%d dims=%dx%dx%dx%d nc=%d prec=%d links=%d rhs=%lld", op.lat.N,
-                  op.lat.D[0], op.lat.D[1], op.lat.D[2], op.lat.D[3], op.nc, cfg.inner, op.links ? 1 : 0, b);
+    std::snprintf(k, sizeof k, "width gfx950 dims=%dx%dx%dx%d nc=%d prec=%d links=%d W=%d", op.lat.D[0],
+                  op.lat.D[1], op.lat.D[2], op.lat.D[3], op.nc, cfg.inner, op.links ? 1 : 0, W);
     return k;
 }
 
@@ -682,7 +682,7 @@ static void load_tune_file(dp_ctx *ctx) {
     if (!f) return;
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
-        // lines of the form   "<key>": <W>,   or   "<stencil key>": "<mode>,<workgroups>",
+        // lines of the form   "<width key>": <ms>,   or   "<stencil key>": "<mode>,<workgroups>",
         char *a = std::strchr(line, '"');
         char *b = a ? std::strchr(a + 1, '"') : nullptr;
         char *c = b ? std::strchr(b, ':') : nullptr;
@@ -694,7 +694,7 @@ static void load_tune_file(dp_ctx *ctx) {
             std::array<int, 2> ch{{-1, 0}};
             if (std::sscanf(v + 1, "%d,%d", &ch[0], &ch[1]) == 2) ctx->tuned_st[key] = ch;
         } else {
-            ctx->tuned_w[key] = std::atoi(v);
+            ctx->tuned_w[key] = std::strtod(v, nullptr);
         }
     }
     std::fclose(f);
@@ -708,7 +708,8 @@ static void save_tune_file(dp_ctx *ctx) {
     std::fprintf(f, "{\n");
     const size_t n = ctx->tuned_w.size() + ctx->tuned_st.size();
     size_t i = 0;
-    for (auto &kv : ctx->tuned_w) std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < n ? "," : "");
+    for (auto &kv : ctx->tuned_w)
+        std::fprintf(f, "  \"%s\": %.6g%s\n", kv.first.c_str(), kv.second, ++i < n ? "," : "");
     for (auto &kv : ctx->tuned_st)
         std::fprintf(f, "  \"%s\": \"%d,%d\"%s\n", kv.first.c_str(), kv.second[0], kv.second[1], ++i < n ? "," : "");
     std::fprintf(f, "}\n");
@@ -815,12 +816,6 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
         return DP_OK;
     }
     load_tune_file(ctx);
-    const std::string key = tune_key(op, cfg, nrhs);
-    auto it = ctx->tuned_w.find(key);
-    if (it != ctx->tuned_w.end()) {
-        W = it->second;
-        return DP_OK;
-    }
     const size_t bytes_per_w = (size_t)op.lat.N * op.nc * (2 * 16 + 4 * (cfg.inner == kF64 ? 16 : 8));
     double best = 1e300;
     int best_w = 1;
@@ -828,17 +823,21 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
     for (int w = 8; w <= kMaxW; w *= 2) {
         if (w > 8 && w / 2 >= nrhs) break;
         if (bytes_per_w * w > ((size_t)32 << 30)) break;
-        float ms = 0;
-        DP_TRY(time_width(ctx, op, cfg, w, s, ms));
-        timed = true;
-        const double cost = ms / (double)std::min<long long>(w, nrhs);
+        const std::string key = width_key(op, cfg, w);
+        auto it = ctx->tuned_w.find(key);
+        if (it == ctx->tuned_w.end()) {
+            float ms = 0;
+            DP_TRY(time_width(ctx, op, cfg, w, s, ms));
+            timed = true;
+            it = ctx->tuned_w.emplace(key, (double)ms / 6.0).first;
+        }
+        const double cost = (double)((nrhs + w - 1) / w) * it->second;
         if (cost < best) {
             best = cost;
             best_w = w;
         }
     }
     W = best_w;
-    ctx->tuned_w[key] = W;
     if (timed) save_tune_file(ctx);
     return DP_OK;
 }

@@ -118,6 +118,39 @@ def test_stencil_tuner_matches_sweep(monkeypatch, tmp_path, dims):
     assert med[tuned] <= SLACK * med[best], (tuned, med)
 
 
+def test_width_tuner_pays_for_the_last_block():
+    """96 right-hand sides on 16^4 (the count of one gradient solve): the
+    tuned width against the widths 8..128 timed one by one on whole solves
+    (a width of 64 solves 128 lanes, one of 32 solves 96)."""
+    dims, nc, nrhs, inner = (16, 16, 16, 16), 3, 96, "f32"
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(5)
+    U = torch.from_numpy(workloads.random_links(dims, 0.5, 2)).cuda()
+    B = torch.from_numpy(rng.standard_normal((nrhs, N, nc)) + 1j * rng.standard_normal((nrhs, N, nc))).cuda()
+    c = dp.Context(0)
+    op = c.operator(dims, nc, 0.05, U)
+
+    def solve_time(W):
+        o = c.opts(tol=1e-8, inner=inner, rhs_block=W)
+        _, st = c.solve_batch([op], [B], o)
+        best = 1e30
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            c.solve_batch([op], [B], o)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best, st[0]["rhs_block"]
+
+    t_tuned, W_tuned = solve_time(0)
+    times = {W: solve_time(W)[0] for W in (8, 16, 32, 64, 128)}
+    best = min(times, key=times.get)
+    _say("96 RHS on 16^4: tuned", W_tuned, f"{t_tuned * 1e3:.2f} ms", "sweep",
+         {k: round(v * 1e3, 2) for k, v in times.items()})
+    assert t_tuned <= SLACK * times[best], (W_tuned, t_tuned, best, times[best])
+    c.close()
+
+
 def test_batch_width_model_matches_sweep():
     """The 64-instance uneven BF16 batch: the width of the traffic model
     (rhs_block = 0) against the widths 16, 32, 64, 128 timed one by one."""
