@@ -184,10 +184,13 @@ typedef struct {
                                FP64 reliable updates */
     int32_t rhs_block;      /* right-hand sides solved together (W): 0 = autotune
                                (one instance: a few timed CG iterations per width,
-                               cached, DP_TUNE_CACHE names a file; several: the
-                               least traffic per useful lane-site, padding of each
-                               instance's last block included), else a power of
-                               two <= 256 (DP_EINVAL otherwise) */
+                               cached, DP_TUNE_CACHE names a file; the least time
+                               for all right-hand sides, padding of the last block
+                               included; several: the least traffic per useful
+                               lane-site, padding of each instance's last block
+                               included), else a power of two <= 256 whose block
+                               vectors (N * nc * W elements of the inner precision)
+                               stay under 4 GiB (DP_EINVAL otherwise) */
     double reliable_delta;  /* mixed precision: replace the residual by the FP64
                                true residual once it dropped by this factor; a lane
                                that reaches it waits for that update before it moves

@@ -70,6 +70,12 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     const bool mixed = cfg.inner != kF64;
     const int nc = in[0].nc;
     const bool links = in[0].links;
+    for (auto &I : in)
+        if (!block_fits(I.lat, nc, W, cfg.inner)) {
+            ctx->err = "rhs_block too wide for an instance: a block vector (N * nc * rhs_block elements) must "
+                       "stay under 4 GiB";
+            return DP_EINVAL;
+        }
     int logW = 0;
     while ((1 << logW) < W) ++logW;
     DevBuf mem(ctx, s);

@@ -142,6 +142,9 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
                       void *defer = nullptr);
 size_t state_bytes();
 void block_stats(const void *state, BlockStats &bs, dp_solve_stats *acc);
+// whether a block vector of W right-hand sides stays under 4 GiB (the stencil
+// kernels address it through 32-bit byte offsets)
+bool block_fits(const Lat &lat, int nc, int W, int inner);
 // For a batch, `work` lists (right-hand sides, sites) of every instance: the
 // width then comes from the traffic per lane-site of a CG iteration times the
 // padded lanes of each instance's last block (no timing).

@@ -56,6 +56,35 @@ __device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
     return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16v2, a), __builtin_bit_cast(bf16v2, b), c, false);
 }
 
+// Global-memory pointers.  A pointer that the compiler cannot trace to a
+// kernel argument (one read from a slot descriptor) is a generic one to it,
+// and generic (flat) accesses also count against the LDS wait counter, so
+// that every wait for an LDS read waits for them too.  The accessors below
+// cast to the global address space at each access (every vector, link and
+// index array of this library is in global memory).
+template <typename T>
+using gp = __attribute__((address_space(1))) T *;
+
+// (the value moves as raw bits: copying a class type binds a generic
+// reference, which brings the flat access back)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "4, 8 or 16 bytes");
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, *(gp<const uint32_t>)p);
+    else if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, *(gp<const uint64_t>)p);
+    else return __builtin_bit_cast(T, *(gp<const u32x4>)p);
+}
+
+template <typename T>
+__device__ __forceinline__ void stg(T *p, const T &v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "4, 8 or 16 bytes");
+    if constexpr (sizeof(T) == 4) *(gp<uint32_t>)p = __builtin_bit_cast(uint32_t, v);
+    else if constexpr (sizeof(T) == 8) *(gp<uint64_t>)p = __builtin_bit_cast(uint64_t, v);
+    else *(gp<u32x4>)p = __builtin_bit_cast(u32x4, v);
+}
+
 template <typename S>
 struct St;
 
@@ -63,12 +92,12 @@ template <>
 struct St<double2> {
     using R = double;
     __device__ static __forceinline__ void ld(const double2 *__restrict__ a, size_t i, R &re, R &im) {
-        double2 v = a[i];
+        double2 v = ldg(a + i);
         re = v.x;
         im = v.y;
     }
     __device__ static __forceinline__ void st(double2 *__restrict__ a, size_t i, R re, R im) {
-        a[i] = make_double2(re, im);
+        stg(a + i, make_double2(re, im));
     }
     __device__ static __forceinline__ void round(R &, R &) {}
 };
@@ -77,12 +106,12 @@ template <>
 struct St<float2> {
     using R = float;
     __device__ static __forceinline__ void ld(const float2 *__restrict__ a, size_t i, R &re, R &im) {
-        float2 v = a[i];
+        float2 v = ldg(a + i);
         re = v.x;
         im = v.y;
     }
     __device__ static __forceinline__ void st(float2 *__restrict__ a, size_t i, R re, R im) {
-        a[i] = make_float2(re, im);
+        stg(a + i, make_float2(re, im));
     }
     __device__ static __forceinline__ void round(R &, R &) {}
 };
@@ -91,14 +120,14 @@ template <>
 struct St<bf16x2> {
     using R = float;
     __device__ static __forceinline__ void ld(const bf16x2 *__restrict__ a, size_t i, R &re, R &im) {
-        uint32_t v = a[i].v;
+        uint32_t v = ldg(a + i).v;
         re = __uint_as_float(v << 16);
         im = __uint_as_float(v & 0xffff0000u);
     }
     __device__ static __forceinline__ void st(bf16x2 *__restrict__ a, size_t i, R re, R im) {
         bf16x2 o;
         o.v = pack_bf16(re, im);
-        a[i] = o;
+        stg(a + i, o);
     }
     // the value a store followed by a load would give
     __device__ static __forceinline__ void round(R &re, R &im) {
@@ -299,7 +328,7 @@ __device__ void block_partials_to(const Blk &bk, const double (&val)[NV], int W,
         for (int v = 0; v < NV; ++v) {
             double s = 0.0;
             for (int k = 0; k < nsum; ++k) s += sm[v * kBlock + k * W + tid];
-            dst[((size_t)tid * nblk + bk.b) * NV + v] = s;
+            stg(dst + ((size_t)tid * nblk + bk.b) * NV + v, s);
         }
     }
 }
@@ -684,15 +713,71 @@ __global__ __launch_bounds__(kBlock) void k_init(Launch L, ProbeGen g, const dou
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
 
-// colour components of lane j at site y; `row` arithmetic is uniform when y is
-// (32-bit lane offsets from a row base: with a uniform y the base stays in
-// scalar registers and the loads use the scalar-base + offset form)
+// Element i of a block vector, addressed by a 32-bit byte offset from the
+// vector's base: with the base uniform (a kernel argument, or read from a
+// slot descriptor by the whole workgroup) the access takes the scalar-base +
+// 32-bit-offset form, with no 64-bit address arithmetic per element.  Every
+// block vector of the stencil kernels is smaller than 4 GiB (the host
+// rejects wider blocks).
+template <typename T>
+__device__ __forceinline__ const T *at32(const T *base, unsigned i) {
+    return (const T *)((const char *)base + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T *at32(T *base, unsigned i) {
+    return (T *)((char *)base + i * (unsigned)sizeof(T));
+}
+
+// p as an opaque uniform value (p must be the same in every thread of the
+// wavefront): the compiler cannot then fold a colour row's offset into
+// per-thread 64-bit address arithmetic, and every load of a site's colours
+// shares the one 32-bit site offset, each from its own scalar base.
+template <typename T>
+__device__ __forceinline__ T *ubase(T *p) {
+    const unsigned long long a = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    return (T *)(((unsigned long long)hi << 32) | lo);
+}
+
+// The colour-row bases v + b * W (b < NC) of a block vector.
+template <typename T, int NC>
+struct Rows {
+    T *b[NC];
+    __device__ __forceinline__ Rows(T *v, int logW) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) b[c] = ubase(v + ((size_t)c << logW));
+    }
+};
+
+// element (site y, colour b, lane j) of a block vector
+__device__ __forceinline__ unsigned vidx(int y, int nc, int b, int logW, int j) {
+    return ((unsigned)(y * nc + b) << logW) + (unsigned)j;
+}
+
+// colour components of lane j at site y
 template <typename S, int NC>
 __device__ __forceinline__ void ld_site(const S *__restrict__ v, int y, int logW, int j,
                                         typename St<S>::R (&re)[NC], typename St<S>::R (&im)[NC]) {
     const S *row = v + ((size_t)(y * NC) << logW);
 #pragma unroll
     for (int b = 0; b < NC; ++b) St<S>::ld(row, (unsigned)((b << logW) + j), re[b], im[b]);
+}
+
+// the same from colour-row bases, through one 32-bit site offset
+template <typename S, int NC>
+__device__ __forceinline__ void ld_rows(const Rows<const S, NC> &v, int y, int logW, int j,
+                                        typename St<S>::R (&re)[NC], typename St<S>::R (&im)[NC]) {
+    const unsigned i = vidx(y, NC, 0, logW, j);
+#pragma unroll
+    for (int b = 0; b < NC; ++b) St<S>::ld(at32(v.b[b], i), 0, re[b], im[b]);
+}
+
+// and stores colour components to colour-row bases
+template <typename S, int NC>
+__device__ __forceinline__ void st_rows(const Rows<S, NC> &v, int y, int logW, int j, int b,
+                                        typename St<S>::R re, typename St<S>::R im) {
+    St<S>::st(at32(v.b[b], vidx(y, NC, 0, logW, j)), 0, re, im);
 }
 
 // acc -= U v (DAG = false) or acc -= U^H v (DAG = true), u = 3x3 (or 1x1)
@@ -745,7 +830,7 @@ __device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, 
             typename St<LS>::R re = 0, im = 0;
             if (item0 + s_l < wk.items) {
                 const int gs = walk_site(wk, item0 + s_l);
-                const int src = dir < 4 ? gs : nbr[gs * 8 + dir];
+                const int src = dir < 4 ? gs : ldg(nbr + gs * 8 + dir);
                 St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, re, im);
             }
             su[2 * e] = (R)re;
@@ -753,7 +838,7 @@ __device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, 
         }
     }
     for (int e = tid; e < sites_per_tile * 8; e += kBlock)
-        snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
+        snb[e] = item0 + e / 8 < wk.items ? ldg(nbr + walk_site(wk, item0 + e / 8) * 8 + (e & 7)) : 0;
     __syncthreads();
 }
 
@@ -768,9 +853,82 @@ __device__ __forceinline__ void hop_words(uint32_t w, bool dag, uint32_t &A, uin
     B = dag ? n : w;
 }
 
+// Orders this wavefront's LDS accesses before the call against those after
+// it (LDS operations of one wavefront complete in issue order; the fences
+// keep the compiler from moving accesses across).
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The tile items a wavefront stages and works on: n items from `first` (in
+// the tile) into LDS slots from slot0.  With W <= 64 a wavefront holds 64 / W
+// whole lane groups of G items each; with W > 64 a lane group spans W / 64
+// wavefronts, which stage a copy each.  slot: the slot of member 0 of this
+// thread's lane group.
+struct WaveItems {
+    int first, n, slot0, slot;
+};
+
+__device__ __forceinline__ WaveItems wave_items(int logW, int G) {
+    const int tid = threadIdx.x, wv = tid >> 6, sl = tid >> logW;
+    WaveItems w;
+    if (logW <= 6) {
+        w.n = G << (6 - logW);
+        w.first = wv * w.n;
+        w.slot0 = w.first;
+        w.slot = G * sl;
+    } else {
+        w.n = G;
+        w.first = G * sl;
+        w.slot0 = wv * G;
+        w.slot = w.slot0;
+    }
+    return w;
+}
+
+// Stages the hop links (converted to R) and neighbour indices of the
+// wavefront's items item0 + wi.first .. + wi.n - 1 into its LDS slots, by
+// that wavefront alone: each wavefront stages what its own threads read, so
+// the tile loop takes no workgroup barrier.  Where the LDS layout is the
+// memory layout (FP32 and FP64 links) the copy moves 16 bytes per thread.
+template <typename LS, typename R, int NC, bool LINKS>
+__device__ __forceinline__ void stage_hops_wave(R *su, int *snb, const SiteWalk &wk, int item0, const WaveItems &wi,
+                                                const LS *__restrict__ U8, const int *__restrict__ nbr) {
+    const int lane = threadIdx.x & 63;
+    constexpr int kE = 8 * NC * NC;  // complex link elements of a site
+    const int first = item0 + wi.first, n = wi.n;
+    wave_fence();  // this wavefront's reads of the previous tile come first
+    if (LINKS) {
+        if constexpr (sizeof(LS) == 2 * sizeof(R)) {
+            constexpr int kV = kE * (int)sizeof(LS) / 16;
+            for (int e = lane; e < n * kV; e += 64) {
+                const int i = e / kV, k = e - i * kV;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (first + i < wk.items) v = ldg((const uint4 *)(U8 + (size_t)walk_site(wk, first + i) * kE) + k);
+                ((uint4 *)(su + (size_t)(wi.slot0 + i) * kE * 2))[k] = v;
+            }
+        } else {
+            for (int e = lane; e < n * kE; e += 64) {
+                const int i = e / kE, k = e - i * kE;
+                typename St<LS>::R re = 0, im = 0;
+                if (first + i < wk.items) St<LS>::ld(U8, (size_t)walk_site(wk, first + i) * kE + k, re, im);
+                su[((size_t)(wi.slot0 + i) * kE + k) * 2] = (R)re;
+                su[((size_t)(wi.slot0 + i) * kE + k) * 2 + 1] = (R)im;
+            }
+        }
+    }
+    for (int e = lane; e < n * 8; e += 64)
+        snb[wi.slot0 * 8 + e] = first + e / 8 < wk.items ? ldg(nbr + walk_site(wk, first + e / 8) * 8 + (e & 7)) : 0;
+    wave_fence();
+}
+
 // Stages the hop words (A, B) of the tile's sites from the hop-link array,
 // element (a, b) of every hop already transposed for the backward ones, and
-// the neighbour indices.
+// the neighbour indices.  (Workgroup barriers here: with each wavefront
+// staging its own sites, as the FP32 and FP64 bodies do, the packed body
+// took 93 registers instead of 69 and ran 15% slower at the occupancy left.)
 template <int NC>
 __device__ __forceinline__ void stage_tile_bf16(uint32_t *su, int *snb, const SiteWalk &wk, int item0,
                                                 int sites_per_tile, const bf16x2 *__restrict__ U,
@@ -787,13 +945,13 @@ __device__ __forceinline__ void stage_tile_bf16(uint32_t *su, int *snb, const Si
             const int gs = walk_site(wk, item0 + s_l);
             const int a = ab / NC, b = ab - a * NC;
             const int el = dir < 4 ? ab : b * NC + a;
-            hop_words(U[((size_t)gs * 8 + dir) * NC * NC + el].v, dir >= 4, A, B);
+            hop_words(ldg(U + ((size_t)gs * 8 + dir) * NC * NC + el).v, dir >= 4, A, B);
         }
         su[2 * e] = A;
         su[2 * e + 1] = B;
     }
     for (int e = tid; e < sites_per_tile * 8; e += kBlock)
-        snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
+        snb[e] = item0 + e / 8 < wk.items ? ldg(nbr + walk_site(wk, item0 + e / 8) * 8 + (e & 7)) : 0;
     __syncthreads();
 }
 
@@ -808,13 +966,17 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
                                                     Red rd) {
     constexpr bool STAGE = MODE == 1 && LINKS;
     constexpr int kMaxSites = kBlock / 16;
-    __shared__ uint32_t su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
+    constexpr bool kReuse = STAGE && kMaxSites * 8 * NC * NC * 2 * sizeof(uint32_t) >= 4 * kBlock * sizeof(double);
+    __shared__ __align__(16) uint32_t su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
     __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
-    __shared__ double sm[4 * kBlock];
+    __shared__ double sm_own[kReuse ? 1 : 4 * kBlock];
+    double *sm = kReuse ? (double *)su : sm_own;
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
+    const Rows<const bf16x2, NC> P(pin, logW), Rr(rin ? rin : pin, logW);
+    const Rows<bf16x2, NC> Q(q, logW);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const SiteWalk wk = site_walk(L, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
@@ -828,19 +990,19 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
         int y[9];
         y[0] = site;
 #pragma unroll
-        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
+        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : ldg(nbr + site * 8 + dir);
         uint32_t v[9][NC], vs[9][NC];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const bf16x2 *row = pin + ((size_t)(y[k] * NC) << logW);
+            const unsigned i = vidx(y[k], NC, 0, logW, j);
 #pragma unroll
-            for (int b = 0; b < NC; ++b) v[k][b] = row[(unsigned)((b << logW) + j)].v;
+            for (int b = 0; b < NC; ++b) v[k][b] = ldg(at32(P.b[b], i)).v;
         }
         uint32_t rv[NC];  // the residual at the site (CG: r^H q and r^H p summed here)
         if (cg) {
-            const bf16x2 *rrow = rin + ((size_t)(site * NC) << logW);
+            const unsigned i = vidx(site, NC, 0, logW, j);
 #pragma unroll
-            for (int b = 0; b < NC; ++b) rv[b] = rrow[(unsigned)((b << logW) + j)].v;
+            for (int b = 0; b < NC; ++b) rv[b] = ldg(at32(Rr.b[b], i)).v;
         }
 #pragma unroll
         for (int k = 1; k < 9; ++k)
@@ -868,14 +1030,13 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
                         B = su[((sl * 8 + dir) * NC * NC + a * NC + b) * 2 + 1];
                     } else {
                         const int el = dir < 4 ? a * NC + b : b * NC + a;
-                        hop_words(U[((size_t)site * 8 + dir) * NC * NC + el].v, dir >= 4, A, B);
+                        hop_words(ldg(U + ((size_t)site * 8 + dir) * NC * NC + el).v, dir >= 4, A, B);
                     }
                     hr[a] = dot2_bf16(A, v[dir + 1][b], hr[a]);
                     hi[a] = dot2_bf16(B, vs[dir + 1][b], hi[a]);
                 }
             }
         }
-        bf16x2 *qrow = q + ((size_t)(site * NC) << logW);
         float pqs = 0, rqs = 0, qqs = 0, rps = 0;
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
@@ -883,7 +1044,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             const float ar = fmaf(diag, pr, -hr[a]), ai = fmaf(diag, pi, -hi[a]);
             bf16x2 o;
             o.v = pack_bf16(ar, ai);
-            qrow[(unsigned)((a << logW) + j)] = o;
+            stg(at32(Q.b[a], vidx(site, NC, 0, logW, j)), o);
             if (cg) {
                 // the dot products of the stored (rounded) q
                 const float qr = __uint_as_float(o.v << 16), qi = __uint_as_float(o.v & 0xffff0000u);
@@ -900,31 +1061,8 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
         acc[3] += (double)rps;
     }
     if (!cg) return;
+    if (kReuse) __syncthreads();  // every wavefront is done with the link tile
     block_partials<4>(bk, acc, W, logW, rd, sm);
-}
-
-// Stages the hop links of the tile's sites (one contiguous record of 8 links
-// per site) converted to R, and their neighbour indices.  All threads call
-// it; it ends with a barrier.
-template <typename LS, typename R, int NC, bool LINKS>
-__device__ __forceinline__ void stage_hops(R *su, int *snb, const SiteWalk &wk, int item0, int sites_per_tile,
-                                           const LS *__restrict__ U8, const int *__restrict__ nbr) {
-    const int tid = threadIdx.x;
-    __syncthreads();
-    if (LINKS) {
-        const int ne = sites_per_tile * 8 * NC * NC;
-        for (int e = tid; e < ne; e += kBlock) {
-            const int s_l = e / (8 * NC * NC);
-            const int rem = e - s_l * 8 * NC * NC;
-            typename St<LS>::R re = 0, im = 0;
-            if (item0 + s_l < wk.items) St<LS>::ld(U8, (size_t)walk_site(wk, item0 + s_l) * 8 * NC * NC + rem, re, im);
-            su[2 * e] = (R)re;
-            su[2 * e + 1] = (R)im;
-        }
-    }
-    for (int e = tid; e < sites_per_tile * 8; e += kBlock)
-        snb[e] = item0 + e / 8 < wk.items ? nbr[walk_site(wk, item0 + e / 8) * 8 + (e & 7)] : 0;
-    __syncthreads();
 }
 
 // hop link dir of site from the hop-link array, converted to R
@@ -964,27 +1102,33 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
     using R = typename St<S>::R;
     constexpr bool STAGE = MODE == 1 && LINKS;
     constexpr int kMaxSites = kBlock / 16;
-    __shared__ R su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
+    // the reduction at the end reuses the link tile when there is one
+    constexpr bool kReuse = STAGE && kMaxSites * 8 * NC * NC * 2 * sizeof(R) >= 4 * kBlock * sizeof(double);
+    __shared__ __align__(16) R su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
     __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
-    __shared__ double sm[4 * kBlock];
+    __shared__ double sm_own[kReuse ? 1 : 4 * kBlock];
+    double *sm = kReuse ? (double *)su : sm_own;
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
     const int sites_per_tile = kBlock >> logW;
+    const WaveItems wi = wave_items(logW, 1);
+    const Rows<const S, NC> P(pin, logW);
+    const Rows<S, NC> Q(q, logW);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const SiteWalk wk = site_walk(L, bk);
     for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * sites_per_tile;
-        if (MODE == 1) stage_hops<LS, R, NC, LINKS>(su, snb, wk, item0, sites_per_tile, U, nbr);
+        if (MODE == 1) stage_hops_wave<LS, R, NC, LINKS>(su, snb, wk, item0, wi, U, nbr);
         if (item0 + sl >= wk.items) continue;
         const int site = walk_site(wk, item0 + sl);
         int y[9];
         y[0] = site;
 #pragma unroll
-        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
+        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[wi.slot * 8 + dir] : ldg(nbr + site * 8 + dir);
         R vr[9][NC], vi[9][NC];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) ld_site<S, NC>(pin, y[k], logW, j, vr[k], vi[k]);
+        for (int k = 0; k < 9; ++k) ld_rows<S, NC>(P, y[k], logW, j, vr[k], vi[k]);
         R ar[NC], ai[NC];
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
@@ -1004,7 +1148,7 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
             R u[2 * NC * NC];
             if (STAGE) {
 #pragma unroll
-                for (int e = 0; e < 2 * NC * NC; ++e) u[e] = su[(sl * 8 + dir) * NC * NC * 2 + e];
+                for (int e = 0; e < 2 * NC * NC; ++e) u[e] = su[(wi.slot * 8 + dir) * NC * NC * 2 + e];
             } else {
                 ld_hop<LS, R, NC>(U, site, dir, u);
             }
@@ -1013,11 +1157,10 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
             else
                 mul_sub<R, NC, true>(u, vr[dir + 1], vi[dir + 1], ar, ai);
         }
-        S *qrow = q + ((size_t)(site * NC) << logW);
         R pqs = 0, qqs = 0;
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            St<S>::st(qrow, (unsigned)((a << logW) + j), ar[a], ai[a]);
+            st_rows<S, NC>(Q, site, logW, j, a, ar[a], ai[a]);
             if (cg) {
                 pqs = fmaR(vr[0][a], ar[a], fmaR(vi[0][a], ai[a], pqs));
                 qqs = fmaR(ar[a], ar[a], fmaR(ai[a], ai[a], qqs));
@@ -1027,6 +1170,7 @@ __device__ __forceinline__ void k_stencil_body(const Blk &bk, Launch L, typename
         acc[2] += (double)qqs;
     }
     if (!cg) return;
+    if (kReuse) __syncthreads();  // every wavefront is done with the link tile
     block_partials<4>(bk, acc, W, logW, rd, sm);
 }
 
@@ -1069,32 +1213,39 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
     // BF16 storage (FP32 arithmetic on the unpacked values here) sums r^H q
     // and r^H p itself, like the packed BF16 body
     constexpr bool kDirect = std::is_same<S, bf16x2>::value;
+    // (pairs need W >= 16, quads and lines W >= 32: at most 32 items per tile)
     constexpr int kMaxItems = G == 2 ? 2 * (kBlock / 16) : 4 * (kBlock / 32);
-    __shared__ R su[kMaxItems * 8 * NC * NC * 2];
+    // the reduction at the end reuses the link tile when it is large enough
+    constexpr bool kReuse = LINKS && kMaxItems * 8 * NC * NC * 2 * sizeof(R) >= 4 * kBlock * sizeof(double);
+    __shared__ __align__(16) R su[LINKS ? kMaxItems * 8 * NC * NC * 2 : 1];
     __shared__ int snb[kMaxItems * 8];
-    __shared__ double sm[4 * kBlock];
+    __shared__ double sm_own[kReuse ? 1 : 4 * kBlock];
+    double *sm = kReuse ? (double *)su : sm_own;
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = tid >> logW;
     const int items_per_tile = G * (kBlock >> logW);
+    const WaveItems wi = wave_items(logW, G);
+    const Rows<const S, NC> P(pin, logW), Rr(kDirect && rin ? rin : pin, logW);
+    const Rows<S, NC> Q(q, logW);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const SiteWalk wk = site_walk(L, bk);
     for (int t = wk.first; t * items_per_tile < wk.items; t += wk.stride) {
         const int item0 = t * items_per_tile;
-        stage_hops<LS, R, NC, LINKS>(su, snb, wk, item0, items_per_tile, U, nbr);
+        stage_hops_wave<LS, R, NC, LINKS>(su, snb, wk, item0, wi, U, nbr);
         if (item0 + G * sl >= wk.items) continue;
         const int s0 = walk_site(wk, item0 + G * sl);
         R vor[G][NC], voi[G][NC];  // the members' own vectors
 #pragma unroll
         for (int h = 0; h < G; ++h)
-            ld_site<S, NC>(pin, s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1)), logW, j, vor[h], voi[h]);
+            ld_rows<S, NC>(P, s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1)), logW, j, vor[h], voi[h]);
         R pqs = 0, qqs = 0, rqs = 0, rps = 0;
 #pragma unroll
         for (int h = 0; h < G; ++h) {
-            const int ls = G * sl + h;
+            const int ls = wi.slot + h;
             const int site = s0 + (LINE ? h * wk.V3 : (h & 1) * wk.V3 + (h >> 1));
             R rr_[NC], ri_[NC];  // BF16 storage: the residual (r^H q, r^H p summed here)
-            if (kDirect && cg) ld_site<S, NC>(rin, site, logW, j, rr_, ri_);
+            if (kDirect && cg) ld_rows<S, NC>(Rr, site, logW, j, rr_, ri_);
             R vr[8][NC], vi[8][NC];
 #pragma unroll
             for (int dir = 0; dir < 8; ++dir) {
@@ -1106,7 +1257,7 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
                         vi[dir][b] = voi[m][b];
                     }
                 } else {
-                    ld_site<S, NC>(pin, snb[ls * 8 + dir], logW, j, vr[dir], vi[dir]);
+                    ld_rows<S, NC>(P, snb[ls * 8 + dir], logW, j, vr[dir], vi[dir]);
                 }
             }
             R ar[NC], ai[NC];
@@ -1133,10 +1284,9 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
                 else
                     mul_sub<R, NC, true>(u, vr[dir], vi[dir], ar, ai);
             }
-            S *qrow = q + ((size_t)(site * NC) << logW);
 #pragma unroll
             for (int a = 0; a < NC; ++a) {
-                St<S>::st(qrow, (unsigned)((a << logW) + j), ar[a], ai[a]);
+                st_rows<S, NC>(Q, site, logW, j, a, ar[a], ai[a]);
                 if (cg) {
                     R qr = ar[a], qi = ai[a];
                     St<S>::round(qr, qi);  // the dot products of the stored q
@@ -1155,6 +1305,7 @@ __device__ __forceinline__ void k_stencil_group_body(const Blk &bk, Launch L, ty
         acc[3] += (double)rps;
     }
     if (!cg) return;
+    if (kReuse) __syncthreads();  // every wavefront is done with the link tile
     block_partials<4>(bk, acc, W, logW, rd, sm);
 }
 
@@ -1255,9 +1406,9 @@ __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__rest
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> logW;
-    const R alpha = (R)cs.alpha[j];
-    const R beta = (R)cs.beta[j];
-    const bool keep = (cs.flags[j] & kFlagHold) || !cs.active[j];
+    const R alpha = (R)ldg(cs.alpha + j);
+    const R beta = (R)ldg(cs.beta + j);
+    const bool keep = (ldg(cs.flags + j) & kFlagHold) || !ldg(cs.active + j);
     double acc[2] = {0.0, 0.0};
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
@@ -1330,7 +1481,7 @@ __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__rest
     // a kept direction keeps the Re q_prev^H p of the update that formed it
     // (the q loaded here is A of the kept direction itself): its total comes
     // back from cs.qp, once per lane
-    if (keep) acc[1] = (bk.b == 0 && tid < W) ? cs.qp[j] : 0.0;
+    if (keep) acc[1] = (bk.b == 0 && tid < W) ? ldg(cs.qp + j) : 0.0;
     block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
 }
 
@@ -1403,7 +1554,7 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
         int y[9];
         y[0] = site;
 #pragma unroll
-        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : nbr[site * 8 + dir];
+        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : ldg(nbr + site * 8 + dir);
         // Two halves: the site and its forward neighbours, then the backward
         // ones, each half's loads in flight together before its arithmetic
         // (all nine at once hold 108 registers of FP64 values: two waves per
@@ -1714,8 +1865,8 @@ __global__ __launch_bounds__(kBlock) void k_b_init(BatchLaunch B, int mixed) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, kSlotInit);
     if (!d) return;
-    k_init_body<S, 0>(bk, d->L, d->g, nullptr, 0, 0, (double2 *)d->b64, (S *)d->r, (S *)d->p, (S *)d->xlo,
-                      (double2 *)d->x64, mixed, d->rd, d->cs);
+    k_init_body<S, 0>(bk, d->L, d->g, nullptr, 0, 0, (double2 *)d->b64, (S *)d->r, (S *)d->p,
+                      (S *)d->xlo, (double2 *)d->x64, mixed, d->rd, d->cs);
 }
 
 template <typename S, typename LS, int NC, bool LINKS, int MODE>
@@ -1724,7 +1875,8 @@ __global__ __launch_bounds__(kBlock) void k_b_stencil(BatchLaunch B) {
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
     k_stencil_body<S, LS, NC, LINKS, MODE>(bk, d->L, (typename St<S>::R)d->diag, (const S *)d->p,
-                                           (const S *)d->r, (S *)d->q, (const LS *)d->U, d->nbr, 1, d->rd);
+                                           (const S *)d->r, (S *)d->q, (const LS *)d->U,
+                                           d->nbr, 1, d->rd);
 }
 
 template <typename S>
@@ -1733,7 +1885,8 @@ __global__ __launch_bounds__(kBlock) void k_b_update(BatchLaunch B) {
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
     // FP64: the iterate is x64 itself (xlo aliases it)
-    k_update_body<S>(bk, d->L, (S *)d->xlo, (S *)d->r, (S *)d->p, (const S *)d->q, d->rd, d->cs);
+    k_update_body<S>(bk, d->L, (S *)d->xlo, (S *)d->r, (S *)d->p, (const S *)d->q,
+                     d->rd, d->cs);
 }
 
 template <typename S>
@@ -1749,9 +1902,10 @@ __global__ __launch_bounds__(kBlock) void k_b_true_resid(BatchLaunch B, int phas
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, phase);
     if (!d) return;
-    k_true_resid_body<S, NC, LINKS, MODE>(bk, d->L, d->diag, (const double2 *)d->b64, (const double2 *)d->x64,
-                                          (const double2 *)d->U64, d->nbr, (S *)d->r, (S *)d->p, (const S *)d->q,
-                                          ru, d->rd, d->cs, d->g, d->gen_b);
+    k_true_resid_body<S, NC, LINKS, MODE>(bk, d->L, d->diag, (const double2 *)d->b64,
+                                          (const double2 *)d->x64, (const double2 *)d->U64, d->nbr,
+                                          (S *)d->r, (S *)d->p, (const S *)d->q, ru, d->rd,
+                                          d->cs, d->g, d->gen_b);
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_dot(BatchLaunch B) {

@@ -370,8 +370,17 @@ dp_status pick_stencil(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, Launc
     return DP_OK;
 }
 
+bool block_fits(const Lat &lat, int nc, int W, int inner) {
+    return (double)lat.N * nc * W * (double)prec_bytes(inner) < 4294967296.0;
+}
+
 dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launch &L, Red &rd, CgState &cs,
                       const SolveCfg &cfg) {
+    if (!block_fits(op.lat, op.nc, W, cfg.inner)) {
+        ctx->err = "rhs_block too wide for this lattice: a block vector (N * nc * rhs_block elements) must stay "
+                   "under 4 GiB";
+        return DP_EINVAL;
+    }
     int logW = 0;
     while ((1 << logW) < W) ++logW;
     L.lat = op.lat;
@@ -822,7 +831,7 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
     bool timed = false;
     for (int w = 8; w <= kMaxW; w *= 2) {
         if (w > 8 && w / 2 >= nrhs) break;
-        if (bytes_per_w * w > ((size_t)32 << 30)) break;
+        if (bytes_per_w * w > ((size_t)32 << 30) || !block_fits(op.lat, op.nc, w, cfg.inner)) break;
         const std::string key = width_key(op, cfg, w);
         auto it = ctx->tuned_w.find(key);
         if (it == ctx->tuned_w.end()) {
