@@ -81,8 +81,9 @@ def parse():
                     help="one workload alone (default: the headline with the others as extra_workloads)")
     ap.add_argument("--rhs-block", type=int, default=None, help="W (0: autotune; default per workload)")
     ap.add_argument("--inner", default=None, help="inner storage precision (default per workload)")
-    ap.add_argument("--delta", type=float, default=0.0,
-                    help="reliable-update residual drop (0: the library default for the precision)")
+    ap.add_argument("--delta", type=float, default=None,
+                    help="reliable-update residual drop (0: the library default for the precision; "
+                         "default per workload: 0.01 for uneven-batch, else 0)")
     ap.add_argument("--graph", type=int, default=None, help="replay CG iteration groups from hipGraphs")
     ap.add_argument("--profile", type=int, default=1, help="time the stencil launches with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -237,7 +238,7 @@ def run_gauge16(a, torch, dp, workloads, steps, warmup, cpu, plain):
     Ug = torch.from_numpy(U).cuda()
     colg = torch.from_numpy(col).cuda()
     op = c.operator(dims, nc, w.m2, Ug)
-    opts = c.opts(tol=w.tol, inner=inner, rhs_block=W_req, reliable_delta=a.delta, use_graph=a.graph or 0)
+    opts = c.opts(tol=w.tol, inner=inner, rhs_block=W_req, reliable_delta=a.delta or 0.0, use_graph=a.graph or 0)
 
     def step(sample, in_timed):
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, sample, 1, "z2_complex", True)
@@ -351,7 +352,10 @@ def run_uneven(a, torch, dp, workloads, steps, warmup, cpu, plain):
         cols.append((torch.from_numpy(np.ascontiguousarray(col)).cuda(), m, col))
         ops.append(c.operator(w.dims, w.nc, w.m2, torch.from_numpy(U).cuda()))
     t_color = time.time() - t0
-    opts = c.opts(tol=inst[0].tol, inner=inner, rhs_block=W_req, reliable_delta=a.delta, use_graph=a.graph or 0)
+    # reliable-update drop: swept on this batch (BF16, W = 32, ms per step):
+    # 0.005 / 0.01 / 0.02 / 0.05 -> 115.2 / 116.6 / 116.6 / 118.6; the middle of the flat optimum
+    delta = 0.01 if a.delta is None else a.delta
+    opts = c.opts(tol=inst[0].tol, inner=inner, rhs_block=W_req, reliable_delta=delta, use_graph=a.graph or 0)
 
     def specs(sample):
         return [c.probe_spec(w.dims, w.nc, cg, m, w.noise_seed, sample, 1, "z2_complex", True)
@@ -368,7 +372,7 @@ def run_uneven(a, torch, dp, workloads, steps, warmup, cpu, plain):
     out = {"steps": steps, "warmup": warmup, "elapsed": elapsed, "work": site_iters, "dtype": inner}
     if plain:
         # the same instances, one call each (same options), on the first timed sample
-        seq_opts = c.opts(tol=inst[0].tol, inner=inner, rhs_block=W, reliable_delta=a.delta, use_graph=a.graph or 0)
+        seq_opts = c.opts(tol=inst[0].tol, inner=inner, rhs_block=W, reliable_delta=delta, use_graph=a.graph or 0)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         for i, ps in enumerate(specs(0)):
@@ -401,7 +405,7 @@ def run_uneven(a, torch, dp, workloads, steps, warmup, cpu, plain):
                                  "m2 ~ U[0.05,0.5], eps ~ U[0.2,0.5], p in {1,2,3}, distance-4 colourings, one "
                                  "Z2 complex sample per instance per step, tol 1e-8",
                      "rhs_per_step": sum(s["nrhs"] for s in stats) // steps, "rhs_block": W, "inner": inner,
-                     "sites": sum(w.volume for w in inst), "coloring_seconds": t_color}
+                     "reliable_delta": delta, "sites": sum(w.volume for w in inst), "coloring_seconds": t_color}
     out["roofline"] = roofline(stats, f"batch64_{inner}_w{W}", "k_b_stencil (q = A p and its dot products)")
     out["cg_bandwidth"] = cg_bandwidth(site_iters, elapsed, inner, W)
     out["stats"] = stats
@@ -422,7 +426,7 @@ def run_gauge32(a, torch, dp, workloads, steps, warmup, cpu, plain):
     Ug = torch.from_numpy(U).cuda()
     colg = torch.from_numpy(np.ascontiguousarray(col)).cuda()
     op = c.operator(dims, nc, w.m2, Ug)
-    opts = c.opts(tol=w.tol, inner=inner, rhs_block=W_req, reliable_delta=a.delta, use_graph=a.graph or 0)
+    opts = c.opts(tol=w.tol, inner=inner, rhs_block=W_req, reliable_delta=a.delta or 0.0, use_graph=a.graph or 0)
 
     def step(sample, in_timed):
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, sample, 1, "z2_complex", True)
@@ -468,7 +472,7 @@ def run_gauge8(a, torch, dp, workloads, steps, warmup, cpu, plain):
     c = dp.context(0)
     colg = torch.from_numpy(np.ascontiguousarray(col)).cuda()
     op = c.operator(dims, nc, w.m2, torch.from_numpy(U).cuda())
-    opts = c.opts(tol=w.tol, inner=inner, rhs_block=W_req, reliable_delta=a.delta, use_graph=a.graph or 0)
+    opts = c.opts(tol=w.tol, inner=inner, rhs_block=W_req, reliable_delta=a.delta or 0.0, use_graph=a.graph or 0)
 
     def step(sample, in_timed):
         ps = c.probe_spec(dims, nc, colg, m, w.noise_seed, sample, 1, "z2_complex", True)

@@ -1,14 +1,19 @@
 // Solver driver: operator preparation, workspace, the batched CG loop with
 // FP64 reliable updates, and the right-hand-side block width choice.
 //
-// CG (Hestenes-Stiefel, x0 = 0) runs on a block of W right-hand sides at
-// once; every right-hand side keeps its own scalars on the device (alpha,
-// beta, |r|^2), and right-hand sides that have converged are frozen
-// (alpha = 0) while the others continue.  One iteration is three kernels:
-//   stencil   q = A p, p^H q            -> alpha (finishing workgroup)
-//   update1   x += alpha p, r -= alpha q, |r|^2 -> beta, convergence flags
-//   update2   p = r + beta p
-// The host reads a 16-byte control word every `check_every` iterations.
+// CG (x0 = 0) runs on a block of W right-hand sides at once; every
+// right-hand side keeps its own scalars on the device (alpha, beta, |r|^2),
+// and right-hand sides that have converged are frozen (alpha = 0) while the
+// others continue.  One iteration is three kernels and one reduction:
+//   stencil   q = A p; p^H q, |q|^2 (BF16 storage: r^H q, r^H p too)
+//   finish    alpha = |r|^2 / p^H q, the new |r|^2 from the recurrence
+//             |r - alpha q|^2 = |r|^2 - 2 alpha Re r^H q + alpha^2 |q|^2 with
+//             Re r^H q = Re p^H q - beta Re q_prev^H p (BF16: alpha from the
+//             direct r^H p, the line search along p), beta, convergence flags
+//   update    x += alpha p, r -= alpha q, p = r + beta p; |r|^2 and
+//             Re q^H p of the new p as stored
+// The host reads a control word after groups of iterations whose length is
+// predicted from the residual decay.
 //
 // Mixed precision (inner = F32 or BF16): x, r, p, q are stored in the inner
 // precision and the stencil accumulates in FP32; the solution is kept in
