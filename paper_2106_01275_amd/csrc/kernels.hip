@@ -843,14 +843,15 @@ __device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, 
 }
 
 // The two bf16x2 words of link element (a, b) of one hop for the packed dot
-// products: with v = (vr, vi) and its swap vs = (vi, vr), re += dot(A, v)
-// and im += dot(B, vs).  Forward hop U, w = U[a][b] = (Ur, Ui):
-// A = (Ur, -Ui), B = (Ur, Ui).  Backward hop U^H, element (a, b) =
-// conj(U[b][a]) from w = U[b][a]: A = (Ur, Ui), B = (Ur, -Ui).
+// products with v = (vr, vi): re += dot(A, v), im += dot(B, v).  Forward hop
+// U, w = U[a][b] = (Ur, Ui): A = (Ur, -Ui), B = (Ui, Ur).  Backward hop U^H,
+// element (a, b) = conj(U[b][a]) from w = U[b][a]: A = (Ur, Ui),
+// B = (-Ui, Ur).  (The halves are swapped in the link word, once per staged
+// element, rather than in every lane's vector word.)
 __device__ __forceinline__ void hop_words(uint32_t w, bool dag, uint32_t &A, uint32_t &B) {
-    const uint32_t n = w ^ 0x80000000u;  // imaginary part negated
-    A = dag ? w : n;
-    B = dag ? n : w;
+    const uint32_t sw = (w >> 16) | (w << 16);  // (Ui, Ur)
+    A = dag ? w : w ^ 0x80000000u;
+    B = dag ? sw ^ 0x00008000u : sw;
 }
 
 // Orders this wavefront's LDS accesses before the call against those after
@@ -991,7 +992,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
         y[0] = site;
 #pragma unroll
         for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : ldg(nbr + site * 8 + dir);
-        uint32_t v[9][NC], vs[9][NC];
+        uint32_t v[9][NC];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const unsigned i = vidx(y[k], NC, 0, logW, j);
@@ -1004,10 +1005,6 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
 #pragma unroll
             for (int b = 0; b < NC; ++b) rv[b] = ldg(at32(Rr.b[b], i)).v;
         }
-#pragma unroll
-        for (int k = 1; k < 9; ++k)
-#pragma unroll
-            for (int b = 0; b < NC; ++b) vs[k][b] = (v[k][b] >> 16) | (v[k][b] << 16);
         float hr[NC], hi[NC];  // sum of the hops
 #pragma unroll
         for (int a = 0; a < NC; ++a) hr[a] = hi[a] = 0.0f;
@@ -1033,7 +1030,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
                         hop_words(ldg(U + ((size_t)site * 8 + dir) * NC * NC + el).v, dir >= 4, A, B);
                     }
                     hr[a] = dot2_bf16(A, v[dir + 1][b], hr[a]);
-                    hi[a] = dot2_bf16(B, vs[dir + 1][b], hi[a]);
+                    hi[a] = dot2_bf16(B, v[dir + 1][b], hi[a]);
                 }
             }
         }
@@ -1046,13 +1043,12 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             o.v = pack_bf16(ar, ai);
             stg(at32(Q.b[a], vidx(site, NC, 0, logW, j)), o);
             if (cg) {
-                // the dot products of the stored (rounded) q
-                const float qr = __uint_as_float(o.v << 16), qi = __uint_as_float(o.v & 0xffff0000u);
-                pqs = fmaf(pr, qr, fmaf(pi, qi, pqs));
-                qqs = fmaf(qr, qr, fmaf(qi, qi, qqs));
-                const float rr_ = __uint_as_float(rv[a] << 16), ri = __uint_as_float(rv[a] & 0xffff0000u);
-                rqs = fmaf(rr_, qr, fmaf(ri, qi, rqs));
-                rps = fmaf(rr_, pr, fmaf(ri, pi, rps));
+                // the real parts of the dot products of the stored words (the
+                // rounded q): one packed dot each, the products exact in FP32
+                pqs = dot2_bf16(v[0][a], o.v, pqs);
+                qqs = dot2_bf16(o.v, o.v, qqs);
+                rqs = dot2_bf16(rv[a], o.v, rqs);
+                rps = dot2_bf16(rv[a], v[0][a], rps);
             }
         }
         acc[0] += (double)pqs;
