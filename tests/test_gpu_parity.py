@@ -169,6 +169,21 @@ def test_solve_failure_statuses(ctx):
     assert e.value.status == dp.EINVAL
 
 
+def test_block_vectors_over_4gib_refused(ctx):
+    """The stencil addresses a block vector through 32-bit byte offsets: a
+    width whose vectors (N * nc * W elements of the inner precision) reach
+    4 GiB is refused before anything is allocated (32^4 x 3 at W = 256:
+    12.9 GB in FP64, 6.4 GB in FP32)."""
+    dims = (32, 32, 32, 32)
+    op = ctx.operator(dims, 3, 0.5, None)
+    B = torch.zeros((1, 32 ** 4, 3), dtype=torch.complex128, device="cuda")
+    B[0, 0, 0] = 1.0
+    for inner in ("f64", "f32"):
+        with pytest.raises(dp.DPError) as e:
+            ctx.solve_batch([op], [B], ctx.opts(tol=1e-8, inner=inner, rhs_block=256))
+        assert e.value.status == dp.EINVAL and "4 GiB" in str(e.value)
+
+
 def test_binding_rejects_bad_sizes(ctx):
     """The kernels trust the sizes they are given: the binding checks every
     tensor's element count (and device) on the host before any call."""
