@@ -28,8 +28,8 @@
 namespace dp {
 
 enum Slot {
-    kSlotNbr, kSlotU64, kSlotU8, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotXLo,
-    kSlotPart1, kSlotState, kSlotColors, kSlotVec, kSlotCmap, kNumSlots
+    kSlotNbr, kSlotU64, kSlotU8, kSlotU8x, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotQ64,
+    kSlotXLo, kSlotPart1, kSlotState, kSlotColors, kSlotVec, kSlotCmap, kNumSlots
 };
 
 // A prepared operator: neighbour table and links in the internal layout.
@@ -40,6 +40,7 @@ struct OpPrep {
     bool links = false;
     const void *U64 = nullptr;  // FP64 links [N][4][nc][nc] (the FP64 true residual)
     const void *U8 = nullptr;   // hop links of the inner precision [N][8][nc][nc]: U_mu(x), then U_mu(x-mu)
+    const void *U8x = nullptr;  // FP64 hop links (the true residual's FP64 stencil; U8 itself for FP64)
     const int *nbr = nullptr;
     int inner = kF64;
 };

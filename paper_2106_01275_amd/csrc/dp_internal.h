@@ -183,6 +183,10 @@ void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
 void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
                        const double *x64, const void *U64, const int *nbr, void *r, void *p, const void *q,
                        int ru_mode, const Red &rd, const CgState &cs, const ProbeGen *gen = nullptr);
+// The same from q64 = A x64 computed by the FP64 stencil beforehand:
+// r = b - q64 element by element (same outputs and epilogues)
+void launch_resid_q(const Launch &L, int prec, const double *b64, const double *q64, void *r, void *p,
+                    const void *q, int ru_mode, const Red &rd, const CgState &cs, const ProbeGen *gen);
 // cmap[c] = the coarse colour of the sites of fine colour c (-1 for a colour
 // no site has); *bad set to 1 when a colour is out of range or two sites of
 // one fine colour have different coarse colours (not nested).

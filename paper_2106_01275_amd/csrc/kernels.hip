@@ -1649,6 +1649,75 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, co
     k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, U, nbr, rout, pio, qin, ru, rd, cs, g, gen);
 }
 
+// The true residual from q64 = A x64 (the FP64 stencil, run just before on
+// x64 with the FP64 hop links): r = b - q64 in FP64 element by element, with
+// |r|^2 summed; with ru the inner-precision residual and direction are
+// replaced as in k_true_resid_body (the FP32 continuation p += r_new - r,
+// or p = r_new for a restarting lane) and Re q^H p of the new p summed.
+// b is read, or regenerated from the probes (gen).
+template <typename S, int NC>
+__device__ __forceinline__ void k_resid_q_body(const Blk &bk, Launch L, const double2 *__restrict__ b64,
+                                               const double2 *__restrict__ q64, S *__restrict__ rout,
+                                               S *__restrict__ pio, const S *__restrict__ qin, int ru, Red rd,
+                                               CgState cs, ProbeGen g, int gen) {
+    using R = typename St<S>::R;
+    __shared__ double sm[2 * kBlock];
+    const int tid = threadIdx.x, logW = L.logW, W = L.W;
+    const int j = tid & (W - 1);
+    const int sites_per_tile = kBlock >> logW;
+    const unsigned long long seedmix = gen ? mix64(g.seed) : 0ull;
+    const ProbeLane pl = gen ? probe_lane(g, NC, g.rhs0 + j) : ProbeLane{};
+    const bool restart = ru && (ldg(cs.flags + j) & kFlagRestart);
+    double acc[2] = {0.0, 0.0};
+    int t0, t1;
+    tile_range(bk, L.ntiles, t0, t1);
+    // element e = ((site * NC + a) << logW) + j: lane j is tid % W for every
+    // e = e0 + tid + k kBlock (kBlock is a multiple of W)
+    const size_t e0 = (size_t)t0 * sites_per_tile * NC * W;
+    const size_t e1 = min((size_t)t1 * sites_per_tile, (size_t)L.lat.N) * NC * W;
+    for (size_t e = e0 + tid; e < e1; e += kBlock) {
+        double qr, qi, br, bi;
+        St<double2>::ld(q64, e, qr, qi);
+        if (gen) {
+            const int row = (int)(e >> logW), site = row / NC, a = row - site * NC;
+            br = bi = 0.0;
+            if (j < g.nvalid) probe_at(g, seedmix, L.lat, NC, pl, site, a, br, bi);
+        } else {
+            St<double2>::ld(b64, e, br, bi);
+        }
+        const double nr64 = br - qr, ni64 = bi - qi;
+        acc[0] += nr64 * nr64 + ni64 * ni64;
+        if (ru) {
+            R nr = (R)nr64, ni = (R)ni64;
+            if (cs.rq_direct) {
+                St<S>::st(rout, e, nr, ni);
+                if (restart) St<S>::st(pio, e, nr, ni);
+            } else {
+                R ro_r, ro_i, po_r, po_i, sqr, sqi;
+                St<S>::ld(rout, e, ro_r, ro_i);
+                St<S>::ld(pio, e, po_r, po_i);
+                St<S>::ld(qin, e, sqr, sqi);
+                St<S>::st(rout, e, nr, ni);
+                St<S>::round(nr, ni);
+                R npr = restart ? nr : po_r + (nr - ro_r), npi = restart ? ni : po_i + (ni - ro_i);
+                St<S>::st(pio, e, npr, npi);
+                St<S>::round(npr, npi);
+                acc[1] += (double)(sqr * npr + sqi * npi);
+            }
+        }
+    }
+    if (ru && cs.rq_direct) acc[1] = (bk.b == 0 && tid < W) ? ldg(cs.qp + j) : 0.0;
+    block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
+}
+
+template <typename S, int NC>
+__global__ __launch_bounds__(kBlock) void k_resid_q(Launch L, const double2 *__restrict__ b64,
+                                                    const double2 *__restrict__ q64, S *__restrict__ rout,
+                                                    S *__restrict__ pio, const S *__restrict__ qin, int ru, Red rd,
+                                                    CgState cs, ProbeGen g, int gen) {
+    k_resid_q_body<S, NC>(own_blk(), L, b64, q64, rout, pio, qin, ru, rd, cs, g, gen);
+}
+
 // t_j = sum_x sum_b conj(v_j(x,b)) x_j(x + p e0, b), probes regenerated.
 __device__ __forceinline__ void k_displaced_dot_body(const Blk &bk, Launch L, ProbeGen g, int p,
                                                          const double2 *__restrict__ x64, Red rd, CgState cs) {
@@ -2326,6 +2395,25 @@ void launch_true_resid(const Launch &L, int prec, bool links, double diag, const
         }
     });
 #undef DP_TR
+    if (ru_mode)
+        k_finish<2, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+    else
+        k_finish<2, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
+}
+
+void launch_resid_q(const Launch &L, int prec, const double *b64, const double *q64, void *r, void *p,
+                    const void *q, int ru_mode, const Red &rd, const CgState &cs, const ProbeGen *gen) {
+    const ProbeGen g = gen ? *gen : ProbeGen{};
+    const int use_gen = gen ? 1 : 0;
+    const double2 *b = (const double2 *)b64, *qq = (const double2 *)q64;
+    DP_DISPATCH_PREC(prec, S, {
+        if (L.nc == 3)
+            k_resid_q<S, 3><<<L.nblk, kBlock, 0, L.stream>>>(L, b, qq, (S *)r, (S *)p, (const S *)q, ru_mode, rd, cs,
+                                                             g, use_gen);
+        else
+            k_resid_q<S, 1><<<L.nblk, kBlock, 0, L.stream>>>(L, b, qq, (S *)r, (S *)p, (const S *)q, ru_mode, rd, cs,
+                                                             g, use_gen);
+    });
     if (ru_mode)
         k_finish<2, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
     else

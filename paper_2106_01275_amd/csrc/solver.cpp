@@ -193,6 +193,8 @@ size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W)
         case kSlotNbr: return N * 8 * sizeof(int);
         case kSlotU64: return links ? N * 4 * nc * nc * 16 : 0;
         case kSlotU8: return links ? 2 * N * 4 * nc * nc * prec_bytes(inner) : 0;
+        case kSlotU8x: return links && inner != kF64 ? 2 * N * 4 * nc * nc * 16 : 0;
+        case kSlotQ64: return inner != kF64 ? vec * 16 : 0;
         case kSlotB64:
         case kSlotX64: return vec * 16;
         case kSlotR:
@@ -245,6 +247,13 @@ dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep
         DP_TRY(ctx->ensure(kSlotU8, sz(kSlotU8)));
         gather_links(inner, out.lat, op.nc, op.links, out.nbr, ctx->at(kSlotU8), s);
         out.U8 = ctx->at(kSlotU8);
+        if (inner != kF64) {
+            DP_TRY(ctx->ensure(kSlotU8x, sz(kSlotU8x)));
+            gather_links(kF64, out.lat, op.nc, op.links, out.nbr, ctx->at(kSlotU8x), s);
+            out.U8x = ctx->at(kSlotU8x);
+        } else {
+            out.U8x = out.U8;
+        }
     }
     DP_HIP(hipGetLastError());
     return DP_OK;
@@ -396,7 +405,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     L.nblk = launch_blocks(op.lat, W);
     L.stream = s;
     L.smode = -1;
-    for (int slot : {kSlotB64, kSlotX64, kSlotR, kSlotP, kSlotQ, kSlotXLo, kSlotPart1, kSlotState}) {
+    for (int slot : {kSlotB64, kSlotX64, kSlotR, kSlotP, kSlotQ, kSlotQ64, kSlotXLo, kSlotPart1, kSlotState}) {
         const size_t b = slot_size(slot, op.lat, op.nc, op.links, cfg.inner, W);
         if (b) DP_TRY(ctx->ensure(slot, b));
     }
@@ -550,6 +559,31 @@ static std::string graph_key(int steps, int inner, const Launch &L, const Stenci
     return k;
 }
 
+// The FP64 true residual r = b - A x64 of the block (ru: with the residual
+// replacement; else statistics only): the FP64 stencil on x64 into an FP64
+// q, then an element-wise pass that forms r,
+// continues p and sums |r|^2.  With FP64 storage q itself is the scratch
+// (its contents are dead whenever this runs).
+static void true_residual(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
+                          const CgState &cs, const double *b64, double *x64, int ru, const ProbeGen *gen) {
+    const bool mixed = cfg.inner != kF64;
+    double *q64 = (double *)ctx->at(mixed ? kSlotQ64 : kSlotQ);
+    StencilArgs a;
+    a.links = op.links;
+    a.diag = op.m2 + 8.0;
+    a.pin = x64;
+    a.q = q64;
+    a.U = op.U8x;
+    a.nbr = op.nbr;
+    a.cg = 0;
+    // the built-in choice (16^4, W = 32: FP64 quads 101 us, the LDS tile
+    // 106 us, although the quads hold 177 registers: two waves per SIMD)
+    Launch L64 = L;
+    L64.smode = -1;
+    launch_stencil(L64, kF64, a);
+    launch_resid_q(L, cfg.inner, b64, q64, ctx->at(kSlotR), ctx->at(kSlotP), ctx->at(kSlotQ), ru, rd, cs, gen);
+}
+
 template <typename Init>
 dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const Launch &L, const Red &rd,
                       const CgState &cs, double *x64, Init init, BlockStats &bs, dp_solve_stats *acc,
@@ -635,8 +669,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             // reliable update: x64 += xlo, r = b - A x64 in FP64 (p continued
             // from it), the residual norms restart from it
             launch_fold(L, cfg.inner, x64, xlo);
-            launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, p, q, 1,
-                              rd, cs, init.probe());
+            true_residual(ctx, op, cfg, L, rd, cs, b64, x64, 1, init.probe());
             DP_HIP(hipGetLastError());
             ++bs.ru;
             DP_TRY(read_ctrl(ctx, rd, cs, L.W, L.stream));
@@ -650,8 +683,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     // residual (statistics).
     if (!(mixed && nactive == 0)) {
         if (mixed) launch_fold(L, cfg.inner, x64, xlo);
-        launch_true_resid(L, cfg.inner, op.links, diag, b64, x64, op.U64, op.nbr, r, p, q, 0, rd, cs,
-                          init.probe());
+        true_residual(ctx, op, cfg, L, rd, cs, b64, x64, 0, init.probe());
         DP_HIP(hipGetLastError());
     }
     // the block's state (one copy); deferred: the caller reads it after its

@@ -4,7 +4,7 @@ The stencil tuner (rhs_block given, DP_STENCIL unset) picks a stencil mode
 and workgroup count per shape by timing CG iterations; here every candidate
 it considers is forced in turn (DP_STENCIL=m,n) and timed
 by the same solve, and the tuned choice must be within 6% of the fastest
-(median of repeated timings of the finalists).  For a multi-instance batch the width
+(least of repeated timings of the finalists).  For a multi-instance batch the width
 comes from a traffic model; it must be within 6% of the fastest of the
 widths 16..128 timed one by one.
 """
@@ -72,8 +72,8 @@ def _iter_time(c, dims, nc, U, B, inner, W, reps=3):
 @pytest.mark.parametrize("dims", [(16, 16, 16, 16), (32, 32, 32, 32)])
 def test_stencil_tuner_matches_sweep(monkeypatch, tmp_path, dims):
     """Every candidate launch timed once; then the tuned choice and the three
-    fastest candidates timed again, round-robin, five times each (the
-    medians of the time per CG iteration are compared)."""
+    fastest candidates timed again, round-robin, five times each (the least
+    time per CG iteration of each is compared)."""
     inner, W, nc = "f32", 32, 3
     N = int(np.prod(dims))
     rng = np.random.default_rng(3)
@@ -112,10 +112,14 @@ def test_stencil_tuner_matches_sweep(monkeypatch, tmp_path, dims):
             runs[cfg].append(_iter_time(ctxs[cfg], dims, nc, U, B, inner, W, reps=1))
     for c in ctxs.values():
         c.close()
-    med = {cfg: float(np.median(v)) for cfg, v in runs.items()}
-    best = min(med, key=med.get)
-    _say(dims, "tuned", tuned, "median ms per iteration", {k: round(v * 1e3, 3) for k, v in med.items()})
-    assert med[tuned] <= SLACK * med[best], (tuned, med)
+    # the least time of each (the launch's own cost; slower rounds are
+    # interference, which reached 9% between two contexts running the same
+    # launch)
+    low = {cfg: float(np.min(v)) for cfg, v in runs.items()}
+    best = min(low, key=low.get)
+    _say(dims, "tuned", tuned, "least ms per iteration", {k: round(v * 1e3, 3) for k, v in low.items()},
+         "medians", {k: round(float(np.median(v)) * 1e3, 3) for k, v in runs.items()})
+    assert low[tuned] <= SLACK * low[best], (tuned, low)
 
 
 def test_width_tuner_pays_for_the_last_block():
