@@ -85,14 +85,13 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     for (auto &I : in) {
         maxN = std::max(maxN, I.lat.N);
         DP_TRY(mem.alloc(ctx, (void **)&I.nbr, (size_t)I.lat.N * 8 * sizeof(int)));
-        build_neighbours(I.lat, I.nbr, s);
         if (I.links) {
             const size_t nl = (size_t)I.lat.N * 4 * nc * nc;
             DP_TRY(mem.alloc(ctx, &I.U64, nl * 16));
-            convert_links(kF64, I.lat, nc, I.links_abi, I.U64, s);
             DP_TRY(mem.alloc(ctx, &I.U8, 2 * nl * prec_bytes(cfg.inner)));
-            gather_links(cfg.inner, I.lat, nc, I.links_abi, I.nbr, I.U8, s);
         }
+        prepare_links(I.lat, nc, I.links ? I.links_abi : nullptr, I.nbr, (double *)I.U64, cfg.inner, I.U8,
+                      nullptr, s);
     }
     DP_HIP(hipGetLastError());
 
@@ -132,15 +131,40 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     const size_t st_stride = (st_doubles * sizeof(double) + st_ints * sizeof(int) + 255) / 256 * 256;
     char *st_all = nullptr;
     DP_TRY(mem.alloc(ctx, (void **)&st_all, st_stride * nslots));
+    // Uploads of the slot table go through a ring of pinned staging buffers:
+    // a copy from pageable memory waits for the stream's earlier work (one
+    // hidden synchronisation per upload: 33 refills of the uneven batch cost
+    // 190 us of idle GPU each).  A buffer is reused once the copy that last
+    // read it has run (an event per buffer).
+    constexpr int kRing = 4;
+    const size_t sd_bytes = sizeof(SlotDesc) * (nslots + 1), sd_al = (sd_bytes + 255) / 256 * 256;
+    const size_t so_bytes = sizeof(int) * (size_t)gblk;
+    const size_t ring_stride = sd_al + (so_bytes + 255) / 256 * 256;
+    const size_t ring_off = (st_stride * nslots + sizeof(int) * 16 * nslots + 255) / 256 * 256;
     char *st_host = nullptr;
-    DP_TRY(ctx->host_pinned(st_stride * nslots + sizeof(int) * 16 * nslots, (void **)&st_host));
+    DP_TRY(ctx->host_pinned(ring_off + kRing * ring_stride, (void **)&st_host));
+    char *ring_host = st_host + ring_off;
+    struct Ring {
+        hipEvent_t ev[kRing] = {};
+        bool used[kRing] = {};
+        int next = 0;
+        ~Ring() {
+            for (auto e : ev)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } ring;
+    for (auto &e : ring.ev) DP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // control words of the slots: pinned host memory that k_b_ctrl writes
     // through its device alias (no copy before the host reads them)
     int *hctrl = (int *)(st_host + st_stride * nslots);
     std::memset(hctrl, 0, sizeof(int) * 16 * nslots);
     char *st_dev = nullptr;
     DP_HIP(hipHostGetDevicePointer((void **)&st_dev, st_host, 0));
+    const char *ring_dev = st_dev + ring_off;
     int *ctrl_all = (int *)(st_dev + st_stride * nslots);
+    // per slot: its active lanes as the last control kernel counted them
+    int *live_all = nullptr;
+    DP_TRY(mem.alloc(ctx, (void **)&live_all, sizeof(int) * nslots));
     for (int k = 0; k < nslots; ++k) {
         SlotDesc &d = hsd[k];
         std::memset(&d, 0, sizeof d);
@@ -171,6 +195,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         cs.flags = iv + 2 * kMaxW;
         cs.ctrl = ctrl_all + 16 * k;
         cs.ctrld = (double *)(ctrl_all + 16 * k + 8);
+        cs.live = live_all + k;
         cs.tol2 = cfg.tol * cfg.tol;
         cs.delta2 = cfg.delta * cfg.delta;
         cs.hold = cfg.inner == kBF16;
@@ -276,9 +301,22 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     // by the check that preceded every change).
     auto upload = [&]() -> dp_status {
         const bool reshared = balance();
-        if (reshared)
-            DP_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int) * slot_of.size(), hipMemcpyHostToDevice, s));
-        DP_HIP(hipMemcpyAsync(d_sd, hsd.data(), sizeof(SlotDesc) * (nslots + 1), hipMemcpyHostToDevice, s));
+        const int i = ring.next;
+        ring.next = (ring.next + 1) % kRing;
+        if (ring.used[i]) DP_HIP(hipEventSynchronize(ring.ev[i]));
+        char *buf = ring_host + ring_stride * i;
+        const char *buf_dev = ring_dev + ring_stride * i;
+        std::memcpy(buf, hsd.data(), sd_bytes);
+        // copied by a kernel that reads the pinned buffer through its device
+        // alias (a DMA copy per upload cost more: set-up latency on every call)
+        if (reshared) {
+            std::memcpy(buf + sd_al, slot_of.data(), so_bytes);
+            launch_copy_in(d_slot_of, buf_dev + sd_al, so_bytes, s);
+        }
+        launch_copy_in(d_sd, buf_dev, sd_bytes, s);
+        DP_HIP(hipGetLastError());
+        DP_HIP(hipEventRecord(ring.ev[i], s));
+        ring.used[i] = true;
         if (reshared) launch_b_reseed(B);
         return DP_OK;
     };
@@ -307,7 +345,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         return DP_OK;
     };
     // contract / copy out the slots flagged kSlotFinal and record statistics
-    // (one copy per finished slot into its pinned mirror, one synchronisation)
+    // (their state blocks into the pinned mirror, one synchronisation)
     auto finish_slots = [&]() -> dp_status {
         DP_TRY(upload());
         // mixed precision: a slot finishes only after a reliable update
@@ -321,9 +359,11 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             if (!(hsd[k].flags & kSlotFinal)) continue;
             const Job &jb = jobs[slot_job[k]];
             if (!trace_mode) launch_to_abi(hsd[k].L, hsd[k].x64, in[jb.inst].xabi, jb.r0, jb.nv);
-            DP_HIP(hipMemcpyAsync(st_host + st_stride * k, st_all + st_stride * k, st_stride, hipMemcpyDeviceToHost,
-                                  s));
         }
+        // the finished slots' state blocks into their pinned mirrors: one
+        // kernel writing through the device alias, not one copy per slot
+        launch_b_state_out(B, st_all, st_dev, st_stride);
+        DP_HIP(hipGetLastError());
         DP_HIP(hipStreamSynchronize(s));
         for (int k = 0; k < nslots; ++k) {
             if (!(hsd[k].flags & kSlotFinal)) continue;
@@ -431,14 +471,18 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         if (any_ru) {
             DP_TRY(upload());
             launch_b_ru(B, 0);
+            // no host round trip: the slots' lane counts are refreshed on the
+            // device, a slot whose lanes all stopped at its update idles
+            // (its iteration workgroups return at once) until the next check
+            // retires it
+            launch_b_count(B);
             DP_HIP(hipGetLastError());
-            DP_TRY(read_ctrl_all());
             for (int k = 0; k < nslots; ++k) {
                 SlotDesc &d = hsd[k];
                 if (!(d.flags & kSlotRU)) continue;
                 ++in[jobs[slot_job[k]].inst].st.reliable_updates;
                 d.flags = kSlotIter;
-                if (hctrl[16 * k] == 0 || slot_it[k] >= cfg.max_iter) {
+                if (slot_it[k] >= cfg.max_iter) {
                     d.flags = kSlotFinal;
                     any_fin = true;
                 }
@@ -457,9 +501,10 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             }
             if (any_init) DP_TRY(init_slots());
             else DP_TRY(upload());
-        } else if (any_ru) {
-            DP_TRY(upload());
         }
+        // (after a reliable update alone the device table keeps the slots'
+        // update bit until the next upload, which precedes every launch that
+        // reads it: the iteration kernels look at the iteration bit only)
     }
     DP_HIP(hipStreamSynchronize(s));
     if (cfg.profile) DP_TRY(finish_profile(ctx, &in[0].st));

@@ -54,6 +54,9 @@ struct CgState {
     int rq_direct;       // 1 exactly for BF16 storage, whose stencil sums r^H q and
                          //    r^H p itself; 0: the finishing kernel forms r^H q from
                          //    p^H q and Re q^H p
+    int *live;           // multi-instance slots: the slot's active lanes (device),
+                         //    written by the control kernel, set by the initialisation;
+                         //    iteration kernels skip a slot with none.  Null otherwise.
 };
 
 // kFlagRestart (mixed precision): p^H A p <= 0 in low precision; the next
@@ -134,15 +137,24 @@ void launch_b_reseed(const BatchLaunch &B);
 void launch_b_ru(const BatchLaunch &B, int final_stats);
 void launch_b_dot(const BatchLaunch &B);
 void launch_b_ctrl(const BatchLaunch &B);
+// the control words and the slots' active-lane counts only (after a reliable
+// update, which has set the lanes' state itself)
+void launch_b_count(const BatchLaunch &B);
+// the state blocks of the finished slots to the device alias of their pinned mirror
+void launch_b_state_out(const BatchLaunch &B, const char *st_all, char *dst, size_t stride);
+// a device-side copy of `bytes` (a multiple of 4; both ends 16-byte aligned)
+// whose source may be the device alias of pinned host memory
+void launch_copy_in(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 int grid_blocks(int ntiles);
-void build_neighbours(const Lat &lat, int *nbr, hipStream_t s);
-void convert_links(int prec, const Lat &lat, int nc, const void *abi_links, void *out, hipStream_t s);
-// hop links [N][8][nc][nc] of storage precision prec: entry (x, mu) = U_mu(x),
-// entry (x, 4 + mu) = U_mu(x - mu) (not conjugated), gathered with the
-// neighbour table, so a site's eight hops are one contiguous record
-void gather_links(int prec, const Lat &lat, int nc, const void *abi_links, const int *nbr, void *out,
-                  hipStream_t s);
+// One launch: the neighbour table nbr[N][8] (x + mu, then x - mu) and, from
+// the ABI links (complex128 [4][N][nc][nc]; null for the free field), the
+// FP64 links [N][4][nc][nc] (u64), and the hop links [N][8][nc][nc], entry
+// (x, mu) = U_mu(x), entry (x, 4 + mu) = U_mu(x - mu) (not conjugated), so a
+// site's eight hops are one contiguous record, in storage precision prec (u8)
+// and in FP64 (u8x).  Null outputs are skipped.
+void prepare_links(const Lat &lat, int nc, const void *abi, int *nbr, double *u64, int prec, void *u8,
+                   double *u8x, hipStream_t s);
 
 void launch_init_probe(const Launch &L, int prec, const ProbeGen &g, double *b64, void *r, void *p,
                        void *xlo, double *x64, int mixed, const Red &rd, const CgState &cs);

@@ -427,6 +427,7 @@ __device__ __forceinline__ void k_finish_body(int lane, const Red &rd, const CgS
         cs.iters[j] = 0;
         cs.active[j] = t > 0.0;
         cs.flags[j] = t > 0.0 ? 0 : kFlagConverged;
+        if (cs.live && j == 0) *cs.live = 1;  // iterate until a control kernel counts the lanes
     } else if (EPI == kEpiCheck) {
         cs.rr[j] = t;
         cs.qp[j] = tot[NV - 1];
@@ -596,58 +597,45 @@ __device__ __forceinline__ void k_ctrl_body(const CgState &cs, int W) {
     for (int c = 0; c < 4; ++c) cs.ctrl[c] = cnt[c][0];
     cs.ctrld[0] = worst[0];
     cs.ctrld[1] = first[0];
+    if (cs.live) *cs.live = cnt[0][0];
 }
 
 __global__ void k_ctrl(CgState cs, int W) { k_ctrl_body(cs, W); }
 
 // ============================================================ kernels
 
-// neighbour table nbr[site][8]: x+mu (mu = 0..3), then x-mu
-__global__ void k_neighbours(Lat L, int *__restrict__ nbr) {
-    const int site = blockIdx.x * blockDim.x + threadIdx.x;
-    if (site >= L.N) return;
-    int x[4], r = site;
-    for (int d = 3; d >= 0; --d) {
-        x[d] = r % L.D[d];
+// The operator's device tables in one pass over the hop-link elements
+// e = ((site * 8 + dir) * nc + a) * nc + b: the neighbour table nbr[site][8]
+// (x + mu for dir = mu < 4, then x - mu; written by the elements a = b = 0),
+// the FP64 links [N][4][nc][nc] (from the forward elements; if u64), and
+// the hop links [N][8][nc][nc], entry (x, mu) = U_mu(x) and (x, 4 + mu) =
+// U_mu(x - mu) (not conjugated), in the storage LS (if u8) and in FP64 (if
+// u8x), so that a site's eight hops are one contiguous record.  The ABI links
+// are complex128 [4][N][nc][nc]; without links (abi null) only the
+// neighbour table.
+template <typename LS>
+__global__ void k_prepare(Lat L, int nc, const double2 *__restrict__ abi, int *__restrict__ nbr,
+                          double2 *__restrict__ u64, LS *__restrict__ u8, double2 *__restrict__ u8x) {
+    const int ne = abi ? nc * nc : 1;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 8LL * L.N * ne) return;
+    const int ab = (int)(e % ne);
+    const long long t = e / ne;
+    const int dir = (int)(t % 8), site = (int)(t / 8), mu = dir & 3;
+    int r = site, x = 0, stride = 1;
+    for (int d = 3; d >= mu; --d) {
+        if (d == mu) x = r % L.D[d];
+        else stride *= L.D[d];
         r /= L.D[d];
     }
-    int stride[4] = {L.D[1] * L.D[2] * L.D[3], L.D[2] * L.D[3], L.D[3], 1};
-    for (int mu = 0; mu < 4; ++mu) {
-        const int up = x[mu] + 1 == L.D[mu] ? -(L.D[mu] - 1) : 1;
-        const int dn = x[mu] == 0 ? L.D[mu] - 1 : -1;
-        nbr[site * 8 + mu] = site + up * stride[mu];
-        nbr[site * 8 + 4 + mu] = site + dn * stride[mu];
-    }
-}
-
-// ABI links complex128 [4][N][nc][nc] -> internal [N][4][nc][nc] of storage LS
-template <typename LS>
-__global__ void k_convert_links(Lat L, int nc, const double2 *__restrict__ in, LS *__restrict__ out) {
-    const long long n = 4LL * L.N * nc * nc;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const int ab = (int)(e % (nc * nc));
-    const long long t = e / (nc * nc);
-    const int site = (int)(t % L.N), mu = (int)(t / L.N);
-    const double2 v = in[e];
-    St<LS>::st(out, ((size_t)site * 4 + mu) * nc * nc + ab, (typename St<LS>::R)v.x,
-               (typename St<LS>::R)v.y);
-}
-
-// ABI links -> hop links [N][8][nc][nc] of storage LS: (x, mu) = U_mu(x),
-// (x, 4 + mu) = U_mu(x - mu)
-template <typename LS>
-__global__ void k_gather_links(Lat L, int nc, const double2 *__restrict__ in, const int *__restrict__ nbr,
-                               LS *__restrict__ out) {
-    const long long n = 8LL * L.N * nc * nc;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const int ab = (int)(e % (nc * nc));
-    const long long t = e / (nc * nc);
-    const int dir = (int)(t % 8), site = (int)(t / 8);
-    const int src = dir < 4 ? site : nbr[(size_t)site * 8 + dir];
-    const double2 v = in[((size_t)(dir & 3) * L.N + src) * nc * nc + ab];
-    St<LS>::st(out, e, (typename St<LS>::R)v.x, (typename St<LS>::R)v.y);
+    const int y = dir < 4 ? site + (x + 1 == L.D[mu] ? -(L.D[mu] - 1) : 1) * stride
+                          : site + (x == 0 ? L.D[mu] - 1 : -1) * stride;
+    if (ab == 0) stg(nbr + (size_t)site * 8 + dir, y);
+    if (!abi) return;
+    const double2 v = ldg(abi + ((size_t)mu * L.N + (dir < 4 ? site : y)) * nc * nc + ab);
+    if (u8) St<LS>::st(u8, e, (typename St<LS>::R)v.x, (typename St<LS>::R)v.y);
+    if (u8x) stg(u8x + e, v);
+    if (u64 && dir < 4) stg(u64 + ((size_t)site * 4 + mu) * nc * nc + ab, v);
 }
 
 // Initialise one block of W right-hand sides: b (FP64), r = p = b (storage
@@ -1920,6 +1908,9 @@ __device__ __forceinline__ const SlotDesc *slot_of_block(const BatchLaunch &B, B
     const int s = B.slot_of[blockIdx.x];
     const SlotDesc *d = B.sd + s;
     if (!(d->flags & phase)) return nullptr;
+    // an iterating slot whose lanes all stopped at a reliable update waits,
+    // idle, for the host to retire it at its next check
+    if (phase == kSlotIter && d->cs.live && ldg(d->cs.live) == 0) return nullptr;
     bk.b = (int)blockIdx.x - d->blk0;
     bk.nb = d->L.nblk;
     return d;
@@ -2009,7 +2000,7 @@ __global__ __launch_bounds__(kBlock) void k_b_reseed(BatchLaunch B) {
 __global__ __launch_bounds__(kBlock) void k_b_finish_cg(BatchLaunch B) {
     const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
     const SlotDesc *d = B.sd + s;
-    if (!(d->flags & kSlotIter)) return;
+    if (!(d->flags & kSlotIter) || (d->cs.live && ldg(d->cs.live) == 0)) return;
     k_finish_cg_body(lane, d->rd, d->cs);
 }
 
@@ -2210,30 +2201,19 @@ int grid_blocks(int ntiles) {
     return n - n % 8;
 }
 
-void build_neighbours(const Lat &lat, int *nbr, hipStream_t s) {
-    k_neighbours<<<blocks_for(lat.N), kBlock, 0, s>>>(lat, nbr);
-}
-
-void gather_links(int prec, const Lat &lat, int nc, const void *abi, const int *nbr, void *out, hipStream_t s) {
-    const long long n = 8LL * lat.N * nc * nc;
+void prepare_links(const Lat &lat, int nc, const void *abi, int *nbr, double *u64, int prec, void *u8,
+                   double *u8x, hipStream_t s) {
+    const long long n = 8LL * lat.N * (abi ? nc * nc : 1);
     const double2 *in = (const double2 *)abi;
     if (prec == kF64)
-        k_gather_links<double2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (double2 *)out);
+        k_prepare<double2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (double2 *)u64, (double2 *)u8,
+                                                            (double2 *)u8x);
     else if (prec == kF32)
-        k_gather_links<float2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (float2 *)out);
+        k_prepare<float2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (double2 *)u64, (float2 *)u8,
+                                                           (double2 *)u8x);
     else
-        k_gather_links<bf16x2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (bf16x2 *)out);
-}
-
-void convert_links(int prec, const Lat &lat, int nc, const void *abi, void *out, hipStream_t s) {
-    const long long n = 4LL * lat.N * nc * nc;
-    const double2 *in = (const double2 *)abi;
-    if (prec == kF64)
-        k_convert_links<double2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, (double2 *)out);
-    else if (prec == kF32)
-        k_convert_links<float2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, (float2 *)out);
-    else
-        k_convert_links<bf16x2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, (bf16x2 *)out);
+        k_prepare<bf16x2><<<blocks_for(n), kBlock, 0, s>>>(lat, nc, in, nbr, (double2 *)u64, (bf16x2 *)u8,
+                                                           (double2 *)u8x);
 }
 
 #define DP_DISPATCH_PREC(prec, S, ...)          \
@@ -2663,6 +2643,38 @@ void launch_b_dot(const BatchLaunch &B) {
 void launch_b_ctrl(const BatchLaunch &B) {
     k_b_finish<2, kEpiCheck><<<B.nslots * B.W, kBlock, 0, B.stream>>>(B, kSlotIter);
     k_b_ctrl<<<B.nslots, 64, 0, B.stream>>>(B);
+}
+
+void launch_b_count(const BatchLaunch &B) { k_b_ctrl<<<B.nslots, 64, 0, B.stream>>>(B); }
+
+// Copies the CG state block of every slot flagged kSlotFinal (stride bytes,
+// a multiple of 16) from st_all to dst, the device alias of a pinned host
+// buffer with the same layout.
+__global__ void k_b_state_out(BatchLaunch B, const char *__restrict__ st_all, char *__restrict__ dst, size_t stride) {
+    const SlotDesc *d = B.sd + blockIdx.x;
+    if (!(d->flags & kSlotFinal)) return;
+    const uint4 *src = (const uint4 *)(st_all + stride * blockIdx.x);
+    uint4 *out = (uint4 *)(dst + stride * blockIdx.x);
+    for (size_t i = threadIdx.x; i < stride / 16; i += blockDim.x) out[i] = ldg(src + i);
+}
+
+// dst[0 .. bytes) = src[0 .. bytes): bytes a multiple of 4; src may be the
+// device alias of pinned host memory
+__global__ void k_copy_in(void *__restrict__ dst, const void *__restrict__ src, size_t bytes) {
+    const size_t n16 = bytes / 16;
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, st = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = i0; i < n16; i += st) stg((uint4 *)dst + i, ldg((const uint4 *)src + i));
+    for (size_t i = n16 * 4 + i0; i < bytes / 4; i += st) stg((uint32_t *)dst + i, ldg((const uint32_t *)src + i));
+}
+
+void launch_copy_in(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    const int blocks = (int)std::min<size_t>(64, (bytes / 16 + kBlock - 1) / kBlock + 1);
+    k_copy_in<<<blocks, kBlock, 0, s>>>(dst, src, bytes);
+}
+
+void launch_b_state_out(const BatchLaunch &B, const char *st_all, char *dst, size_t stride) {
+    k_b_state_out<<<B.nslots, kBlock, 0, B.stream>>>(B, st_all, dst, stride);
 }
 
 

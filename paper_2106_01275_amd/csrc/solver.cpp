@@ -238,23 +238,17 @@ dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep
     out.inner = inner;
     auto sz = [&](int slot) { return slot_size(slot, out.lat, op.nc, out.links, inner, 1); };
     DP_TRY(ctx->ensure(kSlotNbr, sz(kSlotNbr)));
-    build_neighbours(out.lat, (int *)ctx->at(kSlotNbr), s);
     out.nbr = (const int *)ctx->at(kSlotNbr);
     if (out.links) {
         DP_TRY(ctx->ensure(kSlotU64, sz(kSlotU64)));
-        convert_links(kF64, out.lat, op.nc, op.links, ctx->at(kSlotU64), s);
-        out.U64 = ctx->at(kSlotU64);
         DP_TRY(ctx->ensure(kSlotU8, sz(kSlotU8)));
-        gather_links(inner, out.lat, op.nc, op.links, out.nbr, ctx->at(kSlotU8), s);
+        if (inner != kF64) DP_TRY(ctx->ensure(kSlotU8x, sz(kSlotU8x)));
+        out.U64 = ctx->at(kSlotU64);
         out.U8 = ctx->at(kSlotU8);
-        if (inner != kF64) {
-            DP_TRY(ctx->ensure(kSlotU8x, sz(kSlotU8x)));
-            gather_links(kF64, out.lat, op.nc, op.links, out.nbr, ctx->at(kSlotU8x), s);
-            out.U8x = ctx->at(kSlotU8x);
-        } else {
-            out.U8x = out.U8;
-        }
+        out.U8x = inner != kF64 ? ctx->at(kSlotU8x) : out.U8;
     }
+    prepare_links(out.lat, op.nc, op.links, (int *)out.nbr, (double *)out.U64, inner, (void *)out.U8,
+                  inner != kF64 ? (double *)out.U8x : nullptr, s);
     DP_HIP(hipGetLastError());
     return DP_OK;
 }
