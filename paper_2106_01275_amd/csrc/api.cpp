@@ -107,6 +107,10 @@ dp_status batch_inst(dp_ctx *ctx, const dp_operator &op, BatchInst &I) {
         ctx->err = "lattice too large";
         return DP_EUNSUPPORTED;
     }
+    if (!std::isfinite(op.m2)) {
+        ctx->err = "m2 must be finite";
+        return DP_EINVAL;
+    }
     for (int d = 0; d < 4; ++d) I.lat.D[d] = op.dims[d];
     I.lat.N = (int)N;
     I.nc = op.nc;
@@ -343,8 +347,13 @@ dp_status dp_solve_batch(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, con
                 if ((long long)ops[i].dims[0] * ops[i].dims[1] * ops[i].dims[2] * ops[i].dims[3] >
                     (long long)ops[imax].dims[0] * ops[imax].dims[1] * ops[imax].dims[2] * ops[imax].dims[3])
                     imax = i;
+            // (the width model reads the shape only: nothing is prepared)
             OpPrep opm;
-            DP_TRY(prepare_operator(ctx, ops[imax], cfg.inner, opm, stream));
+            opm.lat = in[imax].lat;
+            opm.nc = ops[imax].nc;
+            opm.links = ops[imax].links != nullptr;
+            opm.m2 = ops[imax].m2;
+            opm.inner = cfg.inner;
             std::vector<std::pair<long long, long long>> work;
             for (auto &I : in) work.emplace_back(I.nrhs, (long long)I.lat.N);
             DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W, &work));
@@ -579,8 +588,13 @@ dp_status dp_trace_estimate(dp_ctx *ctx, int32_t ninst, const dp_operator *ops, 
                 if ((long long)ops[i].dims[0] * ops[i].dims[1] * ops[i].dims[2] * ops[i].dims[3] >
                     (long long)ops[imax].dims[0] * ops[imax].dims[1] * ops[imax].dims[2] * ops[imax].dims[3])
                     imax = i;
+            // (the width model reads the shape only: nothing is prepared)
             OpPrep opm;
-            DP_TRY(prepare_operator(ctx, ops[imax], cfg.inner, opm, stream));
+            opm.lat = in[imax].lat;
+            opm.nc = ops[imax].nc;
+            opm.links = ops[imax].links != nullptr;
+            opm.m2 = ops[imax].m2;
+            opm.inner = cfg.inner;
             std::vector<std::pair<long long, long long>> work;
             for (auto &I : in) work.emplace_back(I.nrhs, (long long)I.lat.N);
             DP_TRY(choose_width(ctx, opm, cfg, maxr, o->rhs_block, stream, W, &work));
