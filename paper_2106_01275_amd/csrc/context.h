@@ -28,7 +28,7 @@
 namespace dp {
 
 enum Slot {
-    kSlotNbr, kSlotU64, kSlotU8, kSlotU8x, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotQ64,
+    kSlotNbr, kSlotU8, kSlotU8x, kSlotB64, kSlotX64, kSlotX64b, kSlotR, kSlotP, kSlotQ, kSlotQ64,
     kSlotXLo, kSlotPart1, kSlotState, kSlotColors, kSlotVec, kSlotCmap, kNumSlots
 };
 
@@ -38,7 +38,6 @@ struct OpPrep {
     int nc = 1;
     double m2 = 0;
     bool links = false;
-    const void *U64 = nullptr;  // FP64 links [N][4][nc][nc] (the FP64 true residual)
     const void *U8 = nullptr;   // hop links of the inner precision [N][8][nc][nc]: U_mu(x), then U_mu(x-mu)
     const void *U8x = nullptr;  // FP64 hop links (the true residual's FP64 stencil; U8 itself for FP64)
     const int *nbr = nullptr;

@@ -187,16 +187,13 @@ void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const v
                    const CgState &cs);
 // x64 += xlo, xlo = 0 (mixed precision)
 void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
-// FP64 true residual b - A x64 (gen set: b is regenerated from those probes
-// instead of read from b64).  ru_mode 1 (reliable update): r becomes it, p
-// is continued from it (FP32) or kept (BF16; restarted as r for lanes
-// flagged to restart), then the reliable-update epilogue; ru_mode 0: only
-// its norm, for the statistics.  q: A p_prev, read by the FP32 continuation.
-void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64,
-                       const double *x64, const void *U64, const int *nbr, void *r, void *p, const void *q,
-                       int ru_mode, const Red &rd, const CgState &cs, const ProbeGen *gen = nullptr);
-// The same from q64 = A x64 computed by the FP64 stencil beforehand:
-// r = b - q64 element by element (same outputs and epilogues)
+// The FP64 true residual r = b - q64, with q64 = A x64 computed by the FP64
+// stencil beforehand, element by element (gen set: b is regenerated from
+// those probes instead of read from b64).  ru_mode 1 (reliable update): r
+// becomes it, p is continued from it (FP32) or kept (BF16; restarted as r
+// for lanes flagged to restart), then the reliable-update epilogue; ru_mode
+// 0: only its norm, for the statistics.  q: A p_prev, read by the FP32
+// continuation.
 void launch_resid_q(const Launch &L, int prec, const double *b64, const double *q64, void *r, void *p,
                     const void *q, int ru_mode, const Red &rd, const CgState &cs, const ProbeGen *gen);
 // cmap[c] = the coarse colour of the sites of fine colour c (-1 for a colour

@@ -1627,15 +1627,6 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
     block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
 }
 
-template <typename S, int NC, bool LINKS, int MODE>
-__global__ __launch_bounds__(kBlock) void k_true_resid(Launch L, double diag, const double2 *__restrict__ b64,
-                                                       const double2 *__restrict__ x64,
-                                                       const double2 *__restrict__ U, const int *__restrict__ nbr,
-                                                       S *__restrict__ rout, S *__restrict__ pio,
-                                                       const S *__restrict__ qin, int ru, Red rd, CgState cs,
-                                                       ProbeGen g, int gen) {
-    k_true_resid_body<S, NC, LINKS, MODE>(own_blk(), L, diag, b64, x64, U, nbr, rout, pio, qin, ru, rd, cs, g, gen);
-}
 
 // The true residual from q64 = A x64 (the FP64 stencil, run just before on
 // x64 with the FP64 hop links): r = b - q64 in FP64 element by element, with
@@ -2349,37 +2340,6 @@ void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {
     DP_DISPATCH_PREC(prec, S, k_fold<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (double2 *)x64, (S *)xlo));
 }
 
-void launch_true_resid(const Launch &L, int prec, bool links, double diag, const double *b64, const double *x64,
-                       const void *U64, const int *nbr, void *r, void *p, const void *q, int ru_mode,
-                       const Red &rd, const CgState &cs, const ProbeGen *gen) {
-    const ProbeGen g = gen ? *gen : ProbeGen{};
-    const int use_gen = gen ? 1 : 0;
-    const double2 *b = (const double2 *)b64, *x = (const double2 *)x64, *u = (const double2 *)U64;
-#define DP_TR(NC_, LK_, M_)                                                                                  \
-    k_true_resid<S, NC_, LK_, M_><<<L.nblk, kBlock, 0, L.stream>>>(L, diag, b, x, u, nbr, (S *)r, (S *)p,     \
-                                                                   (const S *)q, ru_mode, rd, cs, g, use_gen)
-    DP_DISPATCH_PREC(prec, S, {
-        const int m = L.W >= 64 ? 2 : (L.W >= 16 ? 1 : 0);
-        if (L.nc == 3) {
-            if (links) {
-                if (m == 2) DP_TR(3, true, 2); else if (m == 1) DP_TR(3, true, 1); else DP_TR(3, true, 0);
-            } else {
-                if (m == 2) DP_TR(3, false, 2); else if (m == 1) DP_TR(3, false, 1); else DP_TR(3, false, 0);
-            }
-        } else {
-            if (links) {
-                if (m == 2) DP_TR(1, true, 2); else if (m == 1) DP_TR(1, true, 1); else DP_TR(1, true, 0);
-            } else {
-                if (m == 2) DP_TR(1, false, 2); else if (m == 1) DP_TR(1, false, 1); else DP_TR(1, false, 0);
-            }
-        }
-    });
-#undef DP_TR
-    if (ru_mode)
-        k_finish<2, kEpiRU><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
-    else
-        k_finish<2, kEpiStats><<<L.W, kBlock, 0, L.stream>>>(rd, cs);
-}
 
 void launch_resid_q(const Launch &L, int prec, const double *b64, const double *q64, void *r, void *p,
                     const void *q, int ru_mode, const Red &rd, const CgState &cs, const ProbeGen *gen) {

@@ -191,7 +191,6 @@ size_t slot_size(int slot, const Lat &lat, int nc, bool links, int inner, int W)
     const size_t N = (size_t)lat.N, vec = N * nc * W, lo = vec * prec_bytes(inner);
     switch (slot) {
         case kSlotNbr: return N * 8 * sizeof(int);
-        case kSlotU64: return links ? N * 4 * nc * nc * 16 : 0;
         case kSlotU8: return links ? 2 * N * 4 * nc * nc * prec_bytes(inner) : 0;
         case kSlotU8x: return links && inner != kF64 ? 2 * N * 4 * nc * nc * 16 : 0;
         case kSlotQ64: return inner != kF64 ? vec * 16 : 0;
@@ -240,14 +239,12 @@ dp_status prepare_operator(dp_ctx *ctx, const dp_operator &op, int inner, OpPrep
     DP_TRY(ctx->ensure(kSlotNbr, sz(kSlotNbr)));
     out.nbr = (const int *)ctx->at(kSlotNbr);
     if (out.links) {
-        DP_TRY(ctx->ensure(kSlotU64, sz(kSlotU64)));
         DP_TRY(ctx->ensure(kSlotU8, sz(kSlotU8)));
         if (inner != kF64) DP_TRY(ctx->ensure(kSlotU8x, sz(kSlotU8x)));
-        out.U64 = ctx->at(kSlotU64);
         out.U8 = ctx->at(kSlotU8);
         out.U8x = inner != kF64 ? ctx->at(kSlotU8x) : out.U8;
     }
-    prepare_links(out.lat, op.nc, op.links, (int *)out.nbr, (double *)out.U64, inner, (void *)out.U8,
+    prepare_links(out.lat, op.nc, op.links, (int *)out.nbr, nullptr, inner, (void *)out.U8,
                   inner != kF64 ? (double *)out.U8x : nullptr, s);
     DP_HIP(hipGetLastError());
     return DP_OK;

@@ -72,8 +72,8 @@ def _iter_time(c, dims, nc, U, B, inner, W, reps=3):
 @pytest.mark.parametrize("dims", [(16, 16, 16, 16), (32, 32, 32, 32)])
 def test_stencil_tuner_matches_sweep(monkeypatch, tmp_path, dims):
     """Every candidate launch timed once; then the tuned choice and the three
-    fastest candidates timed again, round-robin, five times each (the least
-    time per CG iteration of each is compared)."""
+    fastest candidates timed again, round-robin in rotating order, six times
+    each (the least time per CG iteration of each is compared)."""
     inner, W, nc = "f32", 32, 3
     N = int(np.prod(dims))
     rng = np.random.default_rng(3)
@@ -107,8 +107,11 @@ def test_stencil_tuner_matches_sweep(monkeypatch, tmp_path, dims):
     finalists = [tuned] + [t for t in top if t != tuned]
     ctxs = {cfg: forced(cfg) for cfg in finalists}
     runs = {cfg: [] for cfg in finalists}
-    for _ in range(5):
-        for cfg in finalists:
+    for rnd in range(6):
+        # each finalist takes every position in the round in turn (the first
+        # context of a round has run measurably slower)
+        k = rnd % len(finalists)
+        for cfg in finalists[k:] + finalists[:k]:
             runs[cfg].append(_iter_time(ctxs[cfg], dims, nc, U, B, inner, W, reps=1))
     for c in ctxs.values():
         c.close()
