@@ -830,16 +830,17 @@ __device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, 
     __syncthreads();
 }
 
-// The two bf16x2 words of link element (a, b) of one hop for the packed dot
-// products with v = (vr, vi): re += dot(A, v), im += dot(B, v).  Forward hop
-// U, w = U[a][b] = (Ur, Ui): A = (Ur, -Ui), B = (Ui, Ur).  Backward hop U^H,
-// element (a, b) = conj(U[b][a]) from w = U[b][a]: A = (Ur, Ui),
-// B = (-Ui, Ur).  (The halves are swapped in the link word, once per staged
-// element, rather than in every lane's vector word.)
-__device__ __forceinline__ void hop_words(uint32_t w, bool dag, uint32_t &A, uint32_t &B) {
-    const uint32_t sw = (w >> 16) | (w << 16);  // (Ui, Ur)
-    A = dag ? w : w ^ 0x80000000u;
-    B = dag ? sw ^ 0x00008000u : sw;
+// The packed products of one hop on bf16x2 words (low half real, high
+// half imaginary), from the stored link word w = (Ur, Ui) and the vector
+// word v = (vr, vi): re += dot(w, c1), im += dot(w, c2).  Forward hop
+// (U v): c1 = (vr, -vi), c2 = (vi, vr).  Backward hop (U^H v, element (a, b)
+// taken from U[b][a]): c1 = v, c2 = (vi, -vr).  The two words are formed once
+// per vector word and used for the NC link elements that multiply it; the
+// products are those of the complex multiplication, exactly.
+__device__ __forceinline__ void hop_vec_words(uint32_t v, bool dag, uint32_t &c1, uint32_t &c2) {
+    const uint32_t sw = (v >> 16) | (v << 16);  // (vi, vr)
+    c1 = dag ? v : v ^ 0x80000000u;
+    c2 = dag ? sw ^ 0x80000000u : sw;
 }
 
 // Orders this wavefront's LDS accesses before the call against those after
@@ -913,34 +914,38 @@ __device__ __forceinline__ void stage_hops_wave(R *su, int *snb, const SiteWalk 
     wave_fence();
 }
 
-// Stages the hop words (A, B) of the tile's sites from the hop-link array,
-// element (a, b) of every hop already transposed for the backward ones, and
-// the neighbour indices.  (Workgroup barriers here: with each wavefront
-// staging its own sites, as the FP32 and FP64 bodies do, the packed body
-// took 93 registers instead of 69 and ran 15% slower at the occupancy left.)
+// Starts the copy of one tile's hop links (the stored words, [site][dir][a][b])
+// and neighbour indices into an LDS buffer laid out [site][8 NC^2] words,
+// then [site][8] indices: 16-byte loads that write LDS directly, without
+// registers, issued by every wavefront for its share of the tile.  The copy
+// is complete for this wavefront after its next `s_waitcnt vmcnt(0)`, for
+// the workgroup after the barrier that follows it.  Sites past the walk's
+// end copy site 0 (their values are not used).
 template <int NC>
-__device__ __forceinline__ void stage_tile_bf16(uint32_t *su, int *snb, const SiteWalk &wk, int item0,
-                                                int sites_per_tile, const bf16x2 *__restrict__ U,
-                                                const int *__restrict__ nbr) {
-    const int tid = threadIdx.x;
-    __syncthreads();
-    const int ne = sites_per_tile * 8 * NC * NC;
-    for (int e = tid; e < ne; e += kBlock) {
-        const int s_l = e / (8 * NC * NC);
-        const int rem = e - s_l * 8 * NC * NC;
-        const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
-        uint32_t A = 0, B = 0;
-        if (item0 + s_l < wk.items) {
-            const int gs = walk_site(wk, item0 + s_l);
-            const int a = ab / NC, b = ab - a * NC;
-            const int el = dir < 4 ? ab : b * NC + a;
-            hop_words(ldg(U + ((size_t)gs * 8 + dir) * NC * NC + el).v, dir >= 4, A, B);
-        }
-        su[2 * e] = A;
-        su[2 * e + 1] = B;
+__device__ __forceinline__ void dma_tile_bf16(uint32_t *buf, const SiteWalk &wk, int item0, int sites_per_tile,
+                                              const bf16x2 *__restrict__ U, const int *__restrict__ nbr) {
+    constexpr int kLC = 8 * NC * NC / 4;  // 16-byte pieces of a site's links
+    static_assert(8 * NC * NC % 4 == 0, "a site's hop links are whole 16-byte pieces");
+    const int nlc = sites_per_tile * kLC, nch = nlc + sites_per_tile * 2;
+    const int lane = threadIdx.x & 63;
+    for (int c0 = (threadIdx.x >> 6) * 64; c0 < nch; c0 += kBlock) {
+        const int c = c0 + lane;
+        if (c >= nch) continue;
+        const bool link = c < nlc;
+        const int s_l = link ? c / kLC : (c - nlc) >> 1;
+        const int k = link ? c - s_l * kLC : (c - nlc) & 1;
+        const int site = item0 + s_l < wk.items ? walk_site(wk, item0 + s_l) : 0;
+        const uint32_t *src = link ? (const uint32_t *)U + (size_t)site * 8 * NC * NC + 4 * k
+                                   : (const uint32_t *)nbr + (size_t)site * 8 + 4 * k;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                         (__attribute__((address_space(3))) void *)(buf + 4 * c0), 16, 0, 0);
     }
-    for (int e = tid; e < sites_per_tile * 8; e += kBlock)
-        snb[e] = item0 + e / 8 < wk.items ? ldg(nbr + walk_site(wk, item0 + e / 8) * 8 + (e & 7)) : 0;
+}
+
+// Waits for this wavefront's outstanding vector memory operations (the LDS
+// copies above among them), then for the workgroup.
+__device__ __forceinline__ void dma_wait_barrier() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt not waited for
     __syncthreads();
 }
 
@@ -955,9 +960,13 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
                                                     Red rd) {
     constexpr bool STAGE = MODE == 1 && LINKS;
     constexpr int kMaxSites = kBlock / 16;
-    constexpr bool kReuse = STAGE && kMaxSites * 8 * NC * NC * 2 * sizeof(uint32_t) >= 4 * kBlock * sizeof(double);
-    __shared__ __align__(16) uint32_t su[STAGE ? kMaxSites * 8 * NC * NC * 2 : 1];
-    __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
+    // STAGE: two tile buffers, each [site][8 NC^2] link words then [site][8]
+    // neighbour indices; the next tile is copied into one while the other is
+    // read
+    constexpr int kBuf = kMaxSites * 8 * NC * NC + kMaxSites * 8;
+    constexpr bool kReuse = STAGE && 2 * kBuf * sizeof(uint32_t) >= 4 * kBlock * sizeof(double);
+    __shared__ __align__(16) uint32_t su[STAGE ? 2 * kBuf : 1];
+    __shared__ int snb[MODE == 1 && !STAGE ? kMaxSites * 8 : 1];
     __shared__ double sm_own[kReuse ? 1 : 4 * kBlock];
     double *sm = kReuse ? (double *)su : sm_own;
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
@@ -968,18 +977,48 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
     const Rows<bf16x2, NC> Q(q, logW);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const SiteWalk wk = site_walk(L, bk);
-    for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
+    // STAGE: the copy of the next tile is in flight while this tile is worked
+    // on, so that a tile waits for one round trip to memory rather than two
+    if (STAGE && wk.first * sites_per_tile < wk.items)
+        dma_tile_bf16<NC>(su, wk, wk.first * sites_per_tile, sites_per_tile, U, nbr);
+    // q of a tile is stored at the start of the next one, after the wait for
+    // that tile's copy: the wait (for every outstanding vector memory
+    // operation) then does not wait for the stores too
+    uint32_t qw[NC];
+    unsigned qi = 0;
+    bool qpend = false;
+    auto store_q = [&]() {
+        if (!qpend) return;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            bf16x2 o;
+            o.v = qw[a];
+            stg(at32(Q.b[a], qi), o);
+        }
+        qpend = false;
+    };
+    int cur = 0;
+    for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride, cur ^= 1) {
         const int item0 = t * sites_per_tile;
-        if (MODE == 1) {
-            if (STAGE) stage_tile_bf16<NC>(su, snb, wk, item0, sites_per_tile, U, nbr);
-            else stage_tile<bf16x2, float, NC, false>(nullptr, snb, wk, item0, sites_per_tile, U, nbr);
+        const uint32_t *lw = su + cur * kBuf;                       // this tile's link words
+        const int *tnb = (const int *)lw + sites_per_tile * 8 * NC * NC;  // and neighbour indices
+        if (STAGE) {
+            // this tile's copy is complete, and every wavefront is done with the other buffer
+            dma_wait_barrier();
+            store_q();
+            const int next0 = (t + wk.stride) * sites_per_tile;
+            if (next0 < wk.items) dma_tile_bf16<NC>(su + (cur ^ 1) * kBuf, wk, next0, sites_per_tile, U, nbr);
+        } else {
+            store_q();
+            if (MODE == 1) stage_tile<bf16x2, float, NC, false>(nullptr, snb, wk, item0, sites_per_tile, U, nbr);
         }
         if (item0 + sl >= wk.items) continue;
         const int site = walk_site(wk, item0 + sl);
         int y[9];
         y[0] = site;
 #pragma unroll
-        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : ldg(nbr + site * 8 + dir);
+        for (int dir = 0; dir < 8; ++dir)
+            y[dir + 1] = STAGE ? tnb[sl * 8 + dir] : (MODE == 1 ? snb[sl * 8 + dir] : ldg(nbr + site * 8 + dir));
         uint32_t v[9][NC];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -999,26 +1038,21 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
 #pragma unroll
         for (int dir = 0; dir < 8; ++dir) {
 #pragma unroll
-            for (int a = 0; a < NC; ++a) {
+            for (int b = 0; b < NC; ++b) {
+                if (!LINKS) {
+                    hr[b] += __uint_as_float(v[dir + 1][b] << 16);
+                    hi[b] += __uint_as_float(v[dir + 1][b] & 0xffff0000u);
+                    continue;
+                }
+                uint32_t c1, c2;
+                hop_vec_words(v[dir + 1][b], dir >= 4, c1, c2);
 #pragma unroll
-                for (int b = 0; b < NC; ++b) {
-                    if (!LINKS) {
-                        if (a == b) {
-                            hr[a] += __uint_as_float(v[dir + 1][b] << 16);
-                            hi[a] += __uint_as_float(v[dir + 1][b] & 0xffff0000u);
-                        }
-                        continue;
-                    }
-                    uint32_t A, B;
-                    if (STAGE) {
-                        A = su[((sl * 8 + dir) * NC * NC + a * NC + b) * 2];
-                        B = su[((sl * 8 + dir) * NC * NC + a * NC + b) * 2 + 1];
-                    } else {
-                        const int el = dir < 4 ? a * NC + b : b * NC + a;
-                        hop_words(ldg(U + ((size_t)site * 8 + dir) * NC * NC + el).v, dir >= 4, A, B);
-                    }
-                    hr[a] = dot2_bf16(A, v[dir + 1][b], hr[a]);
-                    hi[a] = dot2_bf16(B, v[dir + 1][b], hi[a]);
+                for (int a = 0; a < NC; ++a) {
+                    const int el = dir < 4 ? a * NC + b : b * NC + a;
+                    const uint32_t w = STAGE ? lw[(sl * 8 + dir) * NC * NC + el]
+                                             : ldg(U + ((size_t)site * 8 + dir) * NC * NC + el).v;
+                    hr[a] = dot2_bf16(w, c1, hr[a]);
+                    hi[a] = dot2_bf16(w, c2, hi[a]);
                 }
             }
         }
@@ -1029,7 +1063,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             const float ar = fmaf(diag, pr, -hr[a]), ai = fmaf(diag, pi, -hi[a]);
             bf16x2 o;
             o.v = pack_bf16(ar, ai);
-            stg(at32(Q.b[a], vidx(site, NC, 0, logW, j)), o);
+            qw[a] = o.v;
             if (cg) {
                 // the real parts of the dot products of the stored words (the
                 // rounded q): one packed dot each, the products exact in FP32
@@ -1039,11 +1073,14 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
                 rps = dot2_bf16(rv[a], v[0][a], rps);
             }
         }
+        qi = vidx(site, NC, 0, logW, j);
+        qpend = true;
         acc[0] += (double)pqs;
         acc[1] += (double)rqs;
         acc[2] += (double)qqs;
         acc[3] += (double)rps;
     }
+    store_q();
     if (!cg) return;
     if (kReuse) __syncthreads();  // every wavefront is done with the link tile
     block_partials<4>(bk, acc, W, logW, rd, sm);
