@@ -85,13 +85,16 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     for (auto &I : in) {
         maxN = std::max(maxN, I.lat.N);
         DP_TRY(mem.alloc(ctx, (void **)&I.nbr, (size_t)I.lat.N * 8 * sizeof(int)));
+        // hop links in the storage precision, and in FP64 for the true
+        // residual (the same array when the storage is FP64)
         if (I.links) {
-            const size_t nl = (size_t)I.lat.N * 4 * nc * nc;
-            DP_TRY(mem.alloc(ctx, &I.U64, nl * 16));
-            DP_TRY(mem.alloc(ctx, &I.U8, 2 * nl * prec_bytes(cfg.inner)));
+            const size_t nh = (size_t)I.lat.N * 8 * nc * nc;
+            DP_TRY(mem.alloc(ctx, &I.U8, nh * prec_bytes(cfg.inner)));
+            if (cfg.inner != kF64) DP_TRY(mem.alloc(ctx, &I.U64, nh * 16));
+            else I.U64 = I.U8;
         }
-        prepare_links(I.lat, nc, I.links ? I.links_abi : nullptr, I.nbr, (double *)I.U64, cfg.inner, I.U8,
-                      nullptr, s);
+        prepare_links(I.lat, nc, I.links ? I.links_abi : nullptr, I.nbr, nullptr, cfg.inner, I.U8,
+                      cfg.inner != kF64 ? (double *)I.U64 : nullptr, s);
     }
     DP_HIP(hipGetLastError());
 

@@ -108,7 +108,7 @@ struct SlotDesc {
     int flags;           // kSlot* phases this slot takes part in
     double diag;         // m2 + 8
     const void *U;       // inner-precision hop links [N][8][nc][nc]
-    const void *U64;     // FP64 links
+    const void *U64;     // FP64 hop links [N][8][nc][nc] (the true residual)
     const int *nbr;
     void *r, *p, *q, *xlo;
     double *x64, *b64;

@@ -788,43 +788,13 @@ __device__ __forceinline__ void mul_sub(const R *u, const R (&vr)[NC], const R (
     }
 }
 
-// link U_mu(src) converted to the compute precision
-template <typename LS, typename R, int NC>
-__device__ __forceinline__ void ld_link(const LS *__restrict__ U, int src, int mu, R *u) {
-    const LS *base = U + ((size_t)src * 4 + mu) * NC * NC;
-#pragma unroll
-    for (int e = 0; e < NC * NC; ++e) {
-        typename St<LS>::R re, im;
-        St<LS>::ld(base, e, re, im);
-        u[2 * e] = (R)re;
-        u[2 * e + 1] = (R)im;
-    }
-}
-
-// Stages the links of the tile's sites (forward U_mu(x), backward
-// U_mu(x - mu)) and their neighbour indices in LDS, converted to the compute
-// precision R.  All threads of the workgroup call it; it ends with a barrier.
-template <typename LS, typename R, int NC, bool LINKS>
-__device__ __forceinline__ void stage_tile(R *su, int *snb, const SiteWalk &wk, int item0, int sites_per_tile,
-                                           const LS *__restrict__ U, const int *__restrict__ nbr) {
+// Stages the neighbour indices of the tile's sites in LDS (the bodies
+// without links).  All threads of the workgroup call it; it ends with a
+// barrier.
+__device__ __forceinline__ void stage_nbr(int *snb, const SiteWalk &wk, int item0, int sites_per_tile,
+                                          const int *__restrict__ nbr) {
     const int tid = threadIdx.x;
     __syncthreads();
-    if (LINKS) {
-        const int ne = sites_per_tile * 8 * NC * NC;
-        for (int e = tid; e < ne; e += kBlock) {
-            const int s_l = e / (8 * NC * NC);
-            const int rem = e - s_l * 8 * NC * NC;
-            const int dir = rem / (NC * NC), ab = rem - dir * NC * NC;
-            typename St<LS>::R re = 0, im = 0;
-            if (item0 + s_l < wk.items) {
-                const int gs = walk_site(wk, item0 + s_l);
-                const int src = dir < 4 ? gs : ldg(nbr + gs * 8 + dir);
-                St<LS>::ld(U, ((size_t)src * 4 + (dir & 3)) * NC * NC + ab, re, im);
-            }
-            su[2 * e] = (R)re;
-            su[2 * e + 1] = (R)im;
-        }
-    }
     for (int e = tid; e < sites_per_tile * 8; e += kBlock)
         snb[e] = item0 + e / 8 < wk.items ? ldg(nbr + walk_site(wk, item0 + e / 8) * 8 + (e & 7)) : 0;
     __syncthreads();
@@ -914,18 +884,19 @@ __device__ __forceinline__ void stage_hops_wave(R *su, int *snb, const SiteWalk 
     wave_fence();
 }
 
-// Starts the copy of one tile's hop links (the stored words, [site][dir][a][b])
-// and neighbour indices into an LDS buffer laid out [site][8 NC^2] words,
-// then [site][8] indices: 16-byte loads that write LDS directly, without
-// registers, issued by every wavefront for its share of the tile.  The copy
-// is complete for this wavefront after its next `s_waitcnt vmcnt(0)`, for
-// the workgroup after the barrier that follows it.  Sites past the walk's
-// end copy site 0 (their values are not used).
-template <int NC>
-__device__ __forceinline__ void dma_tile_bf16(uint32_t *buf, const SiteWalk &wk, int item0, int sites_per_tile,
-                                              const bf16x2 *__restrict__ U, const int *__restrict__ nbr) {
-    constexpr int kLC = 8 * NC * NC / 4;  // 16-byte pieces of a site's links
-    static_assert(8 * NC * NC % 4 == 0, "a site's hop links are whole 16-byte pieces");
+// Starts the copy of one tile's hop links (as stored, [site][dir][a][b]) and
+// neighbour indices into an LDS buffer laid out the same way: the links of
+// the tile's sites, then their [site][8] indices.  16-byte loads that write
+// LDS directly, without registers, issued by every wavefront for its share
+// of the tile.  The copy is complete for this wavefront after its next
+// `s_waitcnt vmcnt(0)`, for the workgroup after the barrier that follows it.
+// Sites past the walk's end copy site 0 (their values are not used).
+template <typename LS, int NC>
+__device__ __forceinline__ void dma_tile(void *buf, const SiteWalk &wk, int item0, int sites_per_tile,
+                                         const LS *__restrict__ U, const int *__restrict__ nbr) {
+    constexpr int kSiteB = 8 * NC * NC * (int)sizeof(LS);  // bytes of a site's hop links
+    static_assert(kSiteB % 16 == 0, "a site's hop links are whole 16-byte pieces");
+    constexpr int kLC = kSiteB / 16;
     const int nlc = sites_per_tile * kLC, nch = nlc + sites_per_tile * 2;
     const int lane = threadIdx.x & 63;
     for (int c0 = (threadIdx.x >> 6) * 64; c0 < nch; c0 += kBlock) {
@@ -935,10 +906,10 @@ __device__ __forceinline__ void dma_tile_bf16(uint32_t *buf, const SiteWalk &wk,
         const int s_l = link ? c / kLC : (c - nlc) >> 1;
         const int k = link ? c - s_l * kLC : (c - nlc) & 1;
         const int site = item0 + s_l < wk.items ? walk_site(wk, item0 + s_l) : 0;
-        const uint32_t *src = link ? (const uint32_t *)U + (size_t)site * 8 * NC * NC + 4 * k
-                                   : (const uint32_t *)nbr + (size_t)site * 8 + 4 * k;
+        const char *src = link ? (const char *)U + (size_t)site * kSiteB + 16 * k
+                               : (const char *)(nbr + (size_t)site * 8) + 16 * k;
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
-                                         (__attribute__((address_space(3))) void *)(buf + 4 * c0), 16, 0, 0);
+                                         (__attribute__((address_space(3))) void *)((char *)buf + 16 * c0), 16, 0, 0);
     }
 }
 
@@ -980,7 +951,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
     // STAGE: the copy of the next tile is in flight while this tile is worked
     // on, so that a tile waits for one round trip to memory rather than two
     if (STAGE && wk.first * sites_per_tile < wk.items)
-        dma_tile_bf16<NC>(su, wk, wk.first * sites_per_tile, sites_per_tile, U, nbr);
+        dma_tile<bf16x2, NC>(su, wk, wk.first * sites_per_tile, sites_per_tile, U, nbr);
     // q of a tile is stored at the start of the next one, after the wait for
     // that tile's copy: the wait (for every outstanding vector memory
     // operation) then does not wait for the stores too
@@ -1007,10 +978,10 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             dma_wait_barrier();
             store_q();
             const int next0 = (t + wk.stride) * sites_per_tile;
-            if (next0 < wk.items) dma_tile_bf16<NC>(su + (cur ^ 1) * kBuf, wk, next0, sites_per_tile, U, nbr);
+            if (next0 < wk.items) dma_tile<bf16x2, NC>(su + (cur ^ 1) * kBuf, wk, next0, sites_per_tile, U, nbr);
         } else {
             store_q();
-            if (MODE == 1) stage_tile<bf16x2, float, NC, false>(nullptr, snb, wk, item0, sites_per_tile, U, nbr);
+            if (MODE == 1) stage_nbr(snb, wk, item0, sites_per_tile, nbr);
         }
         if (item0 + sl >= wk.items) continue;
         const int site = walk_site(wk, item0 + sl);
@@ -1539,8 +1510,8 @@ __global__ __launch_bounds__(kBlock) void k_fold(Launch L, double2 *__restrict__
     k_fold_body<S>(own_blk(), L, x64, xlo);
 }
 
-// FP64 true residual r_new = b - A x64 with FP64 links, |r_new|^2 per lane
-// into rd.part2.  ru (a reliable update): r_new replaces the residual in the
+// FP64 true residual r_new = b - A x64 with the FP64 hop links, |r_new|^2 per
+// lane into rd.part2.  ru (a reliable update): r_new replaces the residual in the
 // storage precision; a lane flagged to restart takes r_new as its direction.
 // The other directions: FP32 storage continues them as p + (r_new - r_old),
 // the direction the last update would have formed from r_new (so that
@@ -1556,9 +1527,15 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
                                                   S *__restrict__ pio, const S *__restrict__ qin, int ru, Red rd,
                                                   CgState cs, ProbeGen g, int gen) {
     constexpr int kMaxSites = kBlock / 16;
-    __shared__ double su[MODE == 1 && LINKS ? kMaxSites * 8 * NC * NC * 2 : 1];
-    __shared__ int snb[MODE == 1 ? kMaxSites * 8 : 1];
-    __shared__ double sm[2 * kBlock];
+    // STAGE: two tile buffers, each the tile's hop links then its neighbour
+    // indices; the next tile is copied into one while the other is read
+    constexpr bool STAGE = MODE == 1 && LINKS;
+    constexpr int kBufB = kMaxSites * 8 * NC * NC * 16 + kMaxSites * 8 * 4;
+    __shared__ __align__(16) char sbuf[STAGE ? 2 * kBufB : 16];
+    __shared__ int snb[MODE == 1 && !STAGE ? kMaxSites * 8 : 1];
+    // the reduction at the end reuses the tile buffers when there are any
+    __shared__ double sm_own[STAGE ? 1 : 2 * kBlock];
+    double *sm = STAGE ? (double *)sbuf : sm_own;
     const int tid = threadIdx.x, logW = L.logW, W = L.W;
     const int j = tid & (W - 1);
     const int sl = MODE == 2 ? __builtin_amdgcn_readfirstlane(tid >> logW) : tid >> logW;
@@ -1568,14 +1545,27 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
     const unsigned long long seedmix = gen ? mix64(g.seed) : 0ull;
     const ProbeLane pl = gen ? probe_lane(g, NC, g.rhs0 + j) : ProbeLane{};
     const bool restart = ru && (cs.flags[j] & kFlagRestart);
-    for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride) {
-        if (MODE == 1) stage_tile<double2, double, NC, LINKS>(su, snb, wk, t * sites_per_tile, sites_per_tile, U, nbr);
+    if (STAGE && wk.first * sites_per_tile < wk.items)
+        dma_tile<double2, NC>(sbuf, wk, wk.first * sites_per_tile, sites_per_tile, U, nbr);
+    int cur = 0;
+    for (int t = wk.first; t * sites_per_tile < wk.items; t += wk.stride, cur ^= 1) {
+        const double *tsu = (const double *)(sbuf + cur * kBufB);  // this tile's hop links
+        const int *tnb = (const int *)(sbuf + cur * kBufB + sites_per_tile * 8 * NC * NC * 16);
+        if (STAGE) {
+            // this tile's copy is complete, and every wavefront is done with the other buffer
+            dma_wait_barrier();
+            const int next0 = (t + wk.stride) * sites_per_tile;
+            if (next0 < wk.items) dma_tile<double2, NC>(sbuf + (cur ^ 1) * kBufB, wk, next0, sites_per_tile, U, nbr);
+        } else if (MODE == 1) {
+            stage_nbr(snb, wk, t * sites_per_tile, sites_per_tile, nbr);
+        }
         if (t * sites_per_tile + sl >= wk.items) continue;
         const int site = walk_site(wk, t * sites_per_tile + sl);
         int y[9];
         y[0] = site;
 #pragma unroll
-        for (int dir = 0; dir < 8; ++dir) y[dir + 1] = MODE == 1 ? snb[sl * 8 + dir] : ldg(nbr + site * 8 + dir);
+        for (int dir = 0; dir < 8; ++dir)
+            y[dir + 1] = STAGE ? tnb[sl * 8 + dir] : (MODE == 1 ? snb[sl * 8 + dir] : ldg(nbr + site * 8 + dir));
         // Two halves: the site and its forward neighbours, then the backward
         // ones, each half's loads in flight together before its arithmetic
         // (all nine at once hold 108 registers of FP64 values: two waves per
@@ -1618,11 +1608,11 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
                 continue;
             }
             double u[2 * NC * NC];
-            if (MODE == 1) {
+            if (STAGE) {
 #pragma unroll
-                for (int e = 0; e < 2 * NC * NC; ++e) u[e] = su[(sl * 8 + dir) * NC * NC * 2 + e];
+                for (int e = 0; e < 2 * NC * NC; ++e) u[e] = tsu[(sl * 8 + dir) * NC * NC * 2 + e];
             } else {
-                ld_link<double2, double, NC>(U, dir < 4 ? site : y[dir + 1], dir & 3, u);
+                ld_hop<double2, double, NC>(U, site, dir, u);
             }
             if (dir < 4)
                 mul_sub<double, NC, false>(u, vr[k], vi[k], ar, ai);
@@ -1661,6 +1651,7 @@ __device__ __forceinline__ void k_true_resid_body(const Blk &bk, Launch L, doubl
         for (int a = 0; a < NC; ++a) acc[0] += ar[a] * ar[a] + ai[a] * ai[a];
     }
     if (ru && cs.rq_direct) acc[1] = (bk.b == 0 && tid < W) ? cs.qp[j] : 0.0;
+    if (STAGE) __syncthreads();  // every wavefront is done with the tile buffers
     block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
 }
 
