@@ -913,6 +913,48 @@ __device__ __forceinline__ void dma_tile(void *buf, const SiteWalk &wk, int item
     }
 }
 
+// dma_tile with the division of the pieces among the threads taken once:
+// thread (wavefront w, lane) copies pieces 64 (w + 4 i) + lane, i < kN, of
+// every tile, whose place in a site (piece of its links, or of its
+// indices) does not change from tile to tile.
+template <typename LS, int NC, int kN>
+struct DmaPlan {
+    static constexpr int kSiteB = 8 * NC * NC * (int)sizeof(LS);
+    static constexpr int kLC = kSiteB / 16;
+    int nch;          // pieces of a tile
+    int s_l[kN];      // the piece's site in the tile
+    int boff[kN];     // its byte offset in the site's links, or -1 - offset in its indices
+    __device__ __forceinline__ DmaPlan(int sites_per_tile) {
+        static_assert(kSiteB % 16 == 0, "a site's hop links are whole 16-byte pieces");
+        const int nlc = sites_per_tile * kLC;
+        nch = nlc + sites_per_tile * 2;
+        const int c1 = (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
+#pragma unroll
+        for (int i = 0; i < kN; ++i) {
+            const int c = c1 + i * kBlock;
+            const bool link = c < nlc;
+            s_l[i] = link ? c / kLC : (c - nlc) >> 1;
+            boff[i] = link ? 16 * (c - (c / kLC) * kLC) : -1 - 16 * ((c - nlc) & 1);
+        }
+    }
+    __device__ __forceinline__ void copy(void *buf, const SiteWalk &wk, int item0, const LS *__restrict__ U,
+                                         const int *__restrict__ nbr) const {
+        const int c1 = (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
+#pragma unroll
+        for (int i = 0; i < kN; ++i) {
+            const int c0 = (threadIdx.x >> 6) * 64 + i * kBlock;  // uniform in the wavefront
+            if (c0 >= nch) break;
+            if (c1 + i * kBlock >= nch) continue;
+            const int site = item0 + s_l[i] < wk.items ? walk_site(wk, item0 + s_l[i]) : 0;
+            const char *src = boff[i] >= 0 ? (const char *)U + (size_t)site * kSiteB + boff[i]
+                                           : (const char *)(nbr + (size_t)site * 8) + (-1 - boff[i]);
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                             (__attribute__((address_space(3))) void *)((char *)buf + 16 * c0), 16, 0,
+                                             0);
+        }
+    }
+};
+
 // Waits for this wavefront's outstanding vector memory operations (the LDS
 // copies above among them), then for the workgroup.
 __device__ __forceinline__ void dma_wait_barrier() {
@@ -950,8 +992,9 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
     const SiteWalk wk = site_walk(L, bk);
     // STAGE: the copy of the next tile is in flight while this tile is worked
     // on, so that a tile waits for one round trip to memory rather than two
-    if (STAGE && wk.first * sites_per_tile < wk.items)
-        dma_tile<bf16x2, NC>(su, wk, wk.first * sites_per_tile, sites_per_tile, U, nbr);
+    // (at most 16 sites of 8 NC^2 + 8 words: two pieces per thread)
+    const DmaPlan<bf16x2, NC, 2> plan(sites_per_tile);
+    if (STAGE && wk.first * sites_per_tile < wk.items) plan.copy(su, wk, wk.first * sites_per_tile, U, nbr);
     // q of a tile is stored at the start of the next one, after the wait for
     // that tile's copy: the wait (for every outstanding vector memory
     // operation) then does not wait for the stores too
@@ -978,7 +1021,7 @@ __device__ __forceinline__ void k_stencil_bf16_body(const Blk &bk, Launch L, flo
             dma_wait_barrier();
             store_q();
             const int next0 = (t + wk.stride) * sites_per_tile;
-            if (next0 < wk.items) dma_tile<bf16x2, NC>(su + (cur ^ 1) * kBuf, wk, next0, sites_per_tile, U, nbr);
+            if (next0 < wk.items) plan.copy(su + (cur ^ 1) * kBuf, wk, next0, U, nbr);
         } else {
             store_q();
             if (MODE == 1) stage_nbr(snb, wk, item0, sites_per_tile, nbr);
