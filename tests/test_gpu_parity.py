@@ -504,7 +504,10 @@ def _forced_context(monkeypatch, cfg):
 @pytest.mark.parametrize("dims,nc,links,nrhs,modes", [
     # two-slice slabs (D0 = 16): pairs, quads; four-slice slabs (D0 = 32): lines
     ((16, 4, 4, 4), 3, True, 32, (0, 1, 3, 4)), ((32, 4, 4, 2), 3, True, 32, (0, 1, 3, 6)),
-    ((16, 2, 4, 4), 1, False, 64, (0, 1, 2, 3, 4)), ((32, 2, 4, 2), 3, True, 16, (0, 1, 3))])
+    ((16, 2, 4, 4), 1, False, 64, (0, 1, 2, 3, 4)), ((32, 2, 4, 2), 3, True, 16, (0, 1, 3)),
+    # 360 sites: each XCD's 45 end in a part tile (the LDS copies of the
+    # tiles ahead take site 0 for the missing ones)
+    ((6, 4, 5, 3), 3, True, 32, (0, 1)), ((6, 4, 5, 3), 3, True, 16, (1,))])
 def test_apply_every_stencil_mode(monkeypatch, prec, rtol, dims, nc, links, nrhs, modes):
     """Every stencil launch the tuner may pick gives the operator: each
     admissible mode (the BF16 grouped ones included), on a grid of 8 and of
