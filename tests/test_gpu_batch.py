@@ -48,7 +48,9 @@ def _instances(ctx, inst, nsamples=1, noise="z2_complex"):
 
 
 @pytest.mark.parametrize("inner,block,tol,rtol", [("f64", 16, 1e-12, 1e-10), ("f32", 32, 1e-10, 1e-6),
-                                                  ("bf16", 32, 1e-10, 1e-6), ("f64", 8, 1e-12, 1e-10)])
+                                                  ("bf16", 32, 1e-10, 1e-6), ("f64", 8, 1e-12, 1e-10),
+                                                  # 16 sites per tile in the LDS-staged kernels
+                                                  ("f32", 16, 1e-10, 1e-6), ("bf16", 16, 1e-10, 1e-6)])
 def test_batched_trace_matches_oracle(ctx, inner, block, tol, rtol):
     _say("batched trace", inner, block)
     ops, pss, ps_, Us, cols = _instances(ctx, SMALL)
