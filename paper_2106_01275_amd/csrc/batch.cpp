@@ -231,9 +231,10 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         SlotDesc &d = hsd[k];
         d.L.lat = I.lat;
         d.L.nc = nc;
-        d.L.W = W;
-        d.L.logW = logW;
-        d.L.ntiles = (I.lat.N + spt - 1) / spt;
+        const bool half = batch_narrow_last(W, jb.nv);
+        d.L.W = half ? W / 2 : W;
+        d.L.logW = half ? logW - 1 : logW;
+        d.L.ntiles = (I.lat.N + (kBlock >> d.L.logW) - 1) / (kBlock >> d.L.logW);
         d.L.stream = s;
         d.diag = I.m2 + 8.0;
         d.U = I.U8;
@@ -429,7 +430,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         } else {
             double bytes = 0;
             for (int k = 0; k < nslots; ++k)
-                if (hsd[k].flags & kSlotIter) bytes += stencil_alg_bytes(hsd[k].L.lat, nc, W, cfg.inner, B.links);
+                if (hsd[k].flags & kSlotIter) bytes += stencil_alg_bytes(hsd[k].L.lat, nc, hsd[k].L.W, cfg.inner, B.links);
             for (int c = 0; c < steps; ++c) {
                 DP_TRY(timed_launch(ctx, cfg.profile != 0, bytes,
                                     [&](hipEvent_t e0, hipEvent_t e1) { launch_b_stencil(B, e0, e1); }));

@@ -120,6 +120,12 @@ struct SlotDesc {
 };
 enum { kSlotIter = 1, kSlotInit = 2, kSlotRU = 4, kSlotFinal = 8 };
 
+// A multi-instance block of nv right-hand sides at width W runs at W / 2
+// when it fills at most half of W and the launch's stencil mode takes both
+// widths (the LDS-tile mode: 32 and 16 lanes; the wavefront-per-site mode:
+// 128 and more): an instance's last block then pays for less padding.
+inline bool batch_narrow_last(int W, long long nv) { return (W == 32 || W >= 128) && 2 * nv <= W; }
+
 // Multi-instance launches: slot_of[workgroup] = slot; W lanes per slot.
 struct BatchLaunch {
     const SlotDesc *sd;  // device array [nslots]

@@ -2038,7 +2038,7 @@ template <int NV, int EPI>
 __global__ __launch_bounds__(kBlock) void k_b_finish(BatchLaunch B, int phase) {
     const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
     const SlotDesc *d = B.sd + s;
-    if (!(d->flags & phase)) return;
+    if (!(d->flags & phase) || lane >= d->L.W) return;
     k_finish_body<NV, EPI>(lane, d->rd, d->cs);
 }
 
@@ -2050,7 +2050,7 @@ __global__ __launch_bounds__(kBlock) void k_b_finish(BatchLaunch B, int phase) {
 __global__ __launch_bounds__(kBlock) void k_b_reseed(BatchLaunch B) {
     const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
     const SlotDesc *d = B.sd + s;
-    if (!(d->flags & kSlotIter)) return;
+    if (!(d->flags & kSlotIter) || lane >= d->L.W) return;
     const double rr = d->cs.rr[lane], qp = d->cs.qp[lane];
     double *dst = d->rd.part2 + (size_t)lane * d->rd.nblk * 2;
     for (int b = threadIdx.x; b < d->rd.nblk; b += kBlock) {
@@ -2062,13 +2062,13 @@ __global__ __launch_bounds__(kBlock) void k_b_reseed(BatchLaunch B) {
 __global__ __launch_bounds__(kBlock) void k_b_finish_cg(BatchLaunch B) {
     const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
     const SlotDesc *d = B.sd + s;
-    if (!(d->flags & kSlotIter) || (d->cs.live && ldg(d->cs.live) == 0)) return;
+    if (!(d->flags & kSlotIter) || lane >= d->L.W || (d->cs.live && ldg(d->cs.live) == 0)) return;
     k_finish_cg_body(lane, d->rd, d->cs);
 }
 
 __global__ void k_b_ctrl(BatchLaunch B) {
     const SlotDesc *d = B.sd + blockIdx.x;
-    k_ctrl_body(d->cs, B.W);
+    k_ctrl_body(d->cs, d->L.W);
 }
 
 // ============================================================ deflation

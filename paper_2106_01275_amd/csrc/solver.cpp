@@ -834,7 +834,7 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
         // per lane-site, 10 vector passes plus the eight hop links of a site
         // shared by the W lanes (stencil: p, r read, q written; update: x, r,
         // p, q read, x, r, p written), times the padding of every instance's last
-        // block (sum ceil(n_i/W) W N_i / sum n_i N_i).  Timing one instance
+        // block (its lanes and blocks over the useful lane-sites sum n_i N_i).  Timing one instance
         // alone instead rewards wide blocks that fill the GPU by themselves
         // (64 uneven lattices: this ranks W = 16/32/64/128 as the measured
         // 133/123/141/159 ms per step; the timed single instance picked 128).
@@ -852,10 +852,18 @@ dp_status choose_width(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, long 
         double best = 1e300;
         int best_w = wmax;
         for (int w = std::min(16, wmax); w <= wmax; w *= 2) {
-            double padded = 0;
-            for (auto &nw : *work) padded += (double)((nw.first + w - 1) / w) * w * nw.second;
-            const double per_site = 10.0 * op.nc * c + (op.links ? 8.0 * op.nc * op.nc * c / w : 0.0);
-            const double cost = (useful > 0 ? padded / useful : 1.0) * per_site;
+            // lane-sites and block-sites of the instances' blocks (a last
+            // block at most half full runs half as wide where the engine
+            // allows it: batch_narrow_last)
+            double lanes = 0, blocks = 0;
+            for (auto &nw : *work) {
+                const long long full = nw.first / w, rem = nw.first % w;
+                const int last = rem == 0 ? 0 : (batch_narrow_last(w, rem) ? w / 2 : w);
+                lanes += (double)(full * w + last) * nw.second;
+                blocks += (double)(full + (rem ? 1 : 0)) * nw.second;
+            }
+            const double bytes = lanes * 10.0 * op.nc * c + (op.links ? blocks * 8.0 * op.nc * op.nc * c : 0.0);
+            const double cost = useful > 0 ? bytes / useful : bytes;
             if (cost < best * (1 - 1e-9)) {
                 best = cost;
                 best_w = w;

@@ -50,7 +50,10 @@ def _instances(ctx, inst, nsamples=1, noise="z2_complex"):
 @pytest.mark.parametrize("inner,block,tol,rtol", [("f64", 16, 1e-12, 1e-10), ("f32", 32, 1e-10, 1e-6),
                                                   ("bf16", 32, 1e-10, 1e-6), ("f64", 8, 1e-12, 1e-10),
                                                   # 16 sites per tile in the LDS-staged kernels
-                                                  ("f32", 16, 1e-10, 1e-6), ("bf16", 16, 1e-10, 1e-6)])
+                                                  ("f32", 16, 1e-10, 1e-6), ("bf16", 16, 1e-10, 1e-6),
+                                                  # last blocks at half width beside full ones
+                                                  # (64 and 128 lanes, a wavefront per site)
+                                                  ("f32", 128, 1e-10, 1e-6)])
 def test_batched_trace_matches_oracle(ctx, inner, block, tol, rtol):
     _say("batched trace", inner, block)
     ops, pss, ps_, Us, cols = _instances(ctx, SMALL)
@@ -139,8 +142,9 @@ def test_uneven_batch_workload_64(ctx):
 def test_autotuned_batch_width(ctx):
     """rhs_block = 0 on a batch: the width minimises the traffic of a CG
     iteration per useful lane-site, 10 vector passes plus the eight hop links
-    of a site shared by the W lanes, times the padding of every instance's
-    last block, over W = 16..128 (not above the next power of two of the
+    of a site shared by a block's lanes, with the padding of every instance's
+    last block (which runs half as wide when it fills at most half of W = 32
+    or W >= 128), over W = 16..128 (not above the next power of two of the
     largest right-hand-side count).  The estimates equal those at that width
     given explicitly."""
     _say("batch autotuned width")
@@ -156,8 +160,13 @@ def test_autotuned_batch_width(ctx):
     costs = {}
     w = min(16, wmax)
     while w <= wmax:
-        padded = sum(-(-r // w) * w * s for r, s in work)
-        costs[w] = padded / useful * (10 * 3 * 4 + 8 * 9 * 4 / w)
+        lanes = blocks = 0
+        for r, s in work:
+            full, rem = divmod(r, w)
+            last = 0 if rem == 0 else (w // 2 if (w == 32 or w >= 128) and 2 * rem <= w else w)
+            lanes += (full * w + last) * s
+            blocks += (full + (1 if rem else 0)) * s
+        costs[w] = (lanes * 10 * 3 * 4 + blocks * 8 * 9 * 4) / useful
         w *= 2
     assert W == min(costs, key=lambda k: (costs[k], k)), (W, costs)
     assert all(r["solve"]["rhs_block"] == W for r in res)
