@@ -344,7 +344,7 @@ dp_status dp_trace_grad(dp_ctx *ctx, const dp_operator *op, int32_t p, const dp_
  * lattice at that width exceeds the array.  The workspace is, per site,
  * 32 (neighbours) + [links] 8 nc^2 s (+ 8 nc^2 16 mixed) + W nc (32 + 3 s
  * (+ 16 + s mixed)) bytes, s = 16 / 8 / 4 for F64 / F32 / BF16, plus 48 W
- * per workgroup and 22 KB of per-lane state: e.g. an 8^4 x 3 lattice with
+ * per workgroup and 23 KB of per-lane state: e.g. an 8^4 x 3 lattice with
  * links at F32, W = 32 takes about 40 MB.  Every call on one GPU uses that GPU's single
  * array (each call writes every part of it it reads, so no earlier contents
  * matter): calls that overlap on one GPU, from two host threads or two

@@ -28,6 +28,9 @@ dp_status clearance(const int32_t dims[4], const int32_t *colors, int32_t p, int
 // ---------------------------------------------------------------- device side
 constexpr int kBlock = 256;      // threads per workgroup of every lattice kernel
 constexpr int kMaxW = 256;       // largest right-hand-side block width
+// doubles of one block's per-lane state: rr, qp, rr_ref, bb, alpha, beta,
+// true_rr, tj (two per lane), xdef, and 8 more; its ints follow
+constexpr size_t kStateDoubles = 10 * kMaxW + 8;
 
 // Per-workgroup partial sums of the reductions.  part1 [W][nblk][NV] (NV <=
 // 4): the stencil's p^H q, r^H q, |q|^2, r^H p of a CG iteration (r^H q and
@@ -44,6 +47,7 @@ struct Red {
 // Per-right-hand-side CG state of one block of W right-hand sides (device).
 struct CgState {
     double *rr, *qp, *rr_ref, *bb, *alpha, *beta, *true_rr;  // qp: Re q^H p total of part2
+    double *xdef;        // alpha / beta of an x update deferred by one iteration (null: none)
     double *tj;          // [W][2] contraction results / dot products
     int *active, *iters, *flags;
     int *ctrl;           // [0] active, [1] candidates, [2] need reliable update, [3] breakdowns
@@ -188,9 +192,11 @@ void launch_stencil(const Launch &L, int prec, const StencilArgs &a);
 bool stencil_mode_valid(const Launch &L, int prec, int mode);
 int stencil_mode_rule(const Launch &L, int prec);
 // The vector update of a CG iteration: x += alpha p, r -= alpha q,
-// p = r + beta p, and |r|^2 per lane into rd.part2
+// p = r + beta p, and |r|^2 per lane into rd.part2.  xmode (FP32 storage
+// with cs.xdef set, else taken as 0): 1 defers this iteration's x update to
+// the next update, which must be launched with xmode 2; 0 the plain update.
 void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const void *q, const Red &rd,
-                   const CgState &cs);
+                   const CgState &cs, int xmode = 0);
 // x64 += xlo, xlo = 0 (mixed precision)
 void launch_fold(const Launch &L, int prec, double *x64, void *xlo);
 // The FP64 true residual r = b - q64, with q64 = A x64 computed by the FP64

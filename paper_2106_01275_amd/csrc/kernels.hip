@@ -1433,7 +1433,21 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
 // |r|^2 and Re q^H p of the new residual and direction as stored (the next
 // finishing kernel adds the partials up).  A held or stopped lane keeps its
 // direction (alpha = 0: x and r are unchanged too).
-template <typename S>
+// The solution's update x += alpha p can be taken two iterations at a time
+// (XM, FP32 storage): an update with XM = 1 leaves x as it is and records
+// c = alpha_k / beta_k per lane; the next one (XM = 2) recovers the direction
+// p_k it skipped from the two vectors it reads anyway, p_k = (p_{k+1} -
+// r_{k+1}) / beta_k (the relation by which the skipped update formed p_{k+1}),
+// and adds alpha_k p_k + alpha_{k+1} p_{k+1} in one read and write of x: six
+// vector passes per iteration on average instead of seven.  The recovery
+// divides by beta_k; its rounding error relative to alpha_k p_k is about
+// eps / sqrt(beta_k) (|r_{k+1}| = sqrt(beta_k) |r_k| <= sqrt(beta_k) |p_k|),
+// so a lane whose beta_k is below kDeferBetaMin (a restart has beta = 0)
+// updates its x at once instead.  XM = 0 is the plain update.  An XM = 1
+// update is always followed by an XM = 2 one before anything reads x.
+constexpr double kDeferBetaMin = 1.0 / 64;
+
+template <typename S, int XM>
 __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__restrict__ x, S *__restrict__ r,
                                               S *__restrict__ p, const S *__restrict__ q, Red rd, CgState cs) {
     using R = typename St<S>::R;
@@ -1442,8 +1456,15 @@ __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__rest
     const int j = tid & (W - 1);
     const int sites_per_tile = kBlock >> logW;
     const R alpha = (R)ldg(cs.alpha + j);
-    const R beta = (R)ldg(cs.beta + j);
+    const double beta64 = ldg(cs.beta + j);
+    const R beta = (R)beta64;
     const bool keep = (ldg(cs.flags + j) & kFlagHold) || !ldg(cs.active + j);
+    // XM = 1: does this lane defer its x update (else it updates x now)?
+    // XM = 2: the deferred coefficient alpha_k / beta_k (0: nothing deferred)
+    const bool dfr = XM == 1 && !keep && beta64 >= kDeferBetaMin;
+    const bool xio = XM != 1 || (!keep && !dfr);
+    const R cdef = XM == 2 ? (R)ldg(cs.xdef + j) : (R)0;
+    if (XM == 1 && bk.b == 0 && tid < W) cs.xdef[j] = dfr ? ldg(cs.alpha + j) / beta64 : 0.0;
     double acc[2] = {0.0, 0.0};
     int t0, t1;
     tile_range(bk, L.ntiles, t0, t1);
@@ -1465,11 +1486,15 @@ __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__rest
             St<S>::ld(p, e + u * kBlock, pr[u], pi[u]);
             St<S>::ld(q, e + u * kBlock, qr[u], qi[u]);
             St<S>::ld(r, e + u * kBlock, rr_[u], ri[u]);
-            St<S>::ld(x, e + u * kBlock, xr[u], xi[u]);
+            if (xio) St<S>::ld(x, e + u * kBlock, xr[u], xi[u]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            St<S>::st(x, e + u * kBlock, fmaR(alpha, pr[u], xr[u]), fmaR(alpha, pi[u], xi[u]));
+            if (XM == 2) {
+                xr[u] = fmaR(cdef, pr[u] - rr_[u], xr[u]);
+                xi[u] = fmaR(cdef, pi[u] - ri[u], xi[u]);
+            }
+            if (xio) St<S>::st(x, e + u * kBlock, fmaR(alpha, pr[u], xr[u]), fmaR(alpha, pi[u], xi[u]));
             rr_[u] = fmaR(-alpha, qr[u], rr_[u]);
             ri[u] = fmaR(-alpha, qi[u], ri[u]);
             St<S>::st(r, e + u * kBlock, rr_[u], ri[u]);
@@ -1493,8 +1518,12 @@ __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__rest
         St<S>::ld(p, e, pr, pi);
         St<S>::ld(q, e, qr, qi);
         St<S>::ld(r, e, rr_, ri);
-        St<S>::ld(x, e, xr, xi);
-        St<S>::st(x, e, fmaR(alpha, pr, xr), fmaR(alpha, pi, xi));
+        if (xio) St<S>::ld(x, e, xr, xi);
+        if (XM == 2) {
+            xr = fmaR(cdef, pr - rr_, xr);
+            xi = fmaR(cdef, pi - ri, xi);
+        }
+        if (xio) St<S>::st(x, e, fmaR(alpha, pr, xr), fmaR(alpha, pi, xi));
         rr_ = fmaR(-alpha, qr, rr_);
         ri = fmaR(-alpha, qi, ri);
         St<S>::st(r, e, rr_, ri);
@@ -1520,10 +1549,10 @@ __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__rest
     block_partials_to<2>(bk, acc, W, logW, rd.part2, rd.nblk, sm);
 }
 
-template <typename S>
+template <typename S, int XM>
 __global__ __launch_bounds__(kBlock) void k_update(Launch L, S *__restrict__ x, S *__restrict__ r,
                                                    S *__restrict__ p, const S *__restrict__ q, Red rd, CgState cs) {
-    k_update_body<S>(own_blk(), L, x, r, p, q, rd, cs);
+    k_update_body<S, XM>(own_blk(), L, x, r, p, q, rd, cs);
 }
 
 // Mixed precision: x64 += xlo, xlo = 0 (the low-precision iterate folded
@@ -2003,7 +2032,7 @@ __global__ __launch_bounds__(kBlock) void k_b_update(BatchLaunch B) {
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
     // FP64: the iterate is x64 itself (xlo aliases it)
-    k_update_body<S>(bk, d->L, (S *)d->xlo, (S *)d->r, (S *)d->p, (const S *)d->q,
+    k_update_body<S, 0>(bk, d->L, (S *)d->xlo, (S *)d->r, (S *)d->p, (const S *)d->q,
                      d->rd, d->cs);
 }
 
@@ -2402,9 +2431,18 @@ void launch_stencil(const Launch &L, int prec, const StencilArgs &a) {
 }
 
 void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const void *q, const Red &rd,
-                   const CgState &cs) {
-    DP_DISPATCH_PREC(prec, S,
-                     k_update<S><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)x, (S *)r, (S *)p, (const S *)q, rd, cs));
+                   const CgState &cs, int xmode) {
+    if (xmode != 0 && (prec != kF32 || !cs.xdef)) xmode = 0;  // deferral: FP32 storage only
+    if (xmode == 1)
+        k_update<float2, 1><<<L.nblk, kBlock, 0, L.stream>>>(L, (float2 *)x, (float2 *)r, (float2 *)p,
+                                                              (const float2 *)q, rd, cs);
+    else if (xmode == 2)
+        k_update<float2, 2><<<L.nblk, kBlock, 0, L.stream>>>(L, (float2 *)x, (float2 *)r, (float2 *)p,
+                                                              (const float2 *)q, rd, cs);
+    else
+        DP_DISPATCH_PREC(prec, S,
+                         k_update<S, 0><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)x, (S *)r, (S *)p, (const S *)q, rd,
+                                                                         cs));
 }
 
 void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {

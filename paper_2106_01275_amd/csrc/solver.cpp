@@ -412,7 +412,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
         const size_t b = slot_size(slot, op.lat, op.nc, op.links, cfg.inner, W);
         if (b) DP_TRY(ctx->ensure(slot, b));
     }
-    const size_t nd = 9 * kMaxW + 8;
+    const size_t nd = kStateDoubles;
     double *d = (double *)ctx->at(kSlotState);
     cs.rr = d;
     cs.qp = d + kMaxW;
@@ -422,6 +422,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     cs.beta = d + 5 * kMaxW;
     cs.true_rr = d + 6 * kMaxW;
     cs.tj = d + 7 * kMaxW;
+    cs.xdef = cfg.inner == kF32 ? d + 9 * kMaxW : nullptr;
     // the control word lives in pinned host memory: k_ctrl writes it there
     // and the host reads it after the synchronisation, no copy
     cs.ctrld = (double *)(ctx->ctrl_dev + 4);
@@ -458,6 +459,16 @@ int next_check(int dflt, double ratio, double ratio_prev, int dit, double ru_rat
     return std::min(16, std::max(2, next));
 }
 
+// Update mode of iteration c of a group of n: pairs (1, 2) of a deferred
+// and a completing x update, and a plain last one when n is odd, so that x
+// is whole at the end of every group (where a reliable update or the caller
+// may read it).
+static int xmode_of(int c, int n, bool defer) {
+    if (!defer) return 0;
+    if (c & 1) return 2;
+    return c + 1 < n ? 1 : 0;
+}
+
 double stencil_alg_bytes(const Lat &lat, int nc, int W, int prec, bool links) {
     const double c = (double)prec_bytes(prec);  // one complex number
     return (double)lat.N * (2.0 * W * nc * c + (links ? 4.0 * nc * nc * c : 0.0));
@@ -491,13 +502,13 @@ dp_status finish_profile(dp_ctx *ctx, dp_solve_stats *st) {
     return DP_OK;
 }
 
-size_t state_bytes() { return (9 * kMaxW + 8) * sizeof(double) + (3 * kMaxW + 8) * sizeof(int); }
+size_t state_bytes() { return kStateDoubles * sizeof(double) + (3 * kMaxW + 8) * sizeof(int); }
 
 void block_stats(const void *state, BlockStats &bs, dp_solve_stats *acc) {
     // the layout of make_launch: doubles rr .. tj, then the ints active, iters, flags
     const double *d = (const double *)state;
     const double *true_rr = d + 6 * kMaxW, *bbv = d + 3 * kMaxW;
-    const int *iv = (const int *)(d + 9 * kMaxW + 8);
+    const int *iv = (const int *)(d + kStateDoubles);
     const int *iters = iv + kMaxW, *flags = iv + 2 * kMaxW;
     for (int j = 0; j < bs.nvalid; ++j) {
         const double bb = bbv[j];
@@ -618,6 +629,10 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     // Iterations between host checks: start with check_every, then predict
     // from the decay of the slowest lane's residual since the last check.
     int steps_next = std::max(1, ctx->check_every);
+    // FP32 storage takes the x updates of an iteration group in pairs (the
+    // update kernel's deferred mode); DP_XDEFER=0 takes every one at once
+    const char *xd_env = std::getenv("DP_XDEFER");
+    const bool xdefer = cs.xdef != nullptr && !(xd_env && std::strcmp(xd_env, "0") == 0);
     double ratio_prev = -1.0;
     int it_prev = 0, it_ru = 0;
     while (nactive > 0 && it < cfg.max_iter) {
@@ -628,7 +643,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
             // so it is looked up by all of them (two solves of one call, say
             // the forward and adjoint solves of a gradient, or instances of
             // different shapes, never share a graph)
-            const std::string key = graph_key(steps, cfg.inner, L, a, xlo);
+            const std::string key = graph_key(2 * steps + (xdefer ? 1 : 0), cfg.inner, L, a, xlo);
             auto g = ctx->graphs.find(key);
             if (g == ctx->graphs.end()) {
                 if (ctx->graphs.size() >= 64) ctx->drop_graphs();
@@ -637,7 +652,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
                 DP_HIP(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal));
                 for (int c = 0; c < steps; ++c) {
                     launch_stencil(L, cfg.inner, a);
-                    launch_update(L, cfg.inner, xlo, r, p, q, rd, cs);
+                    launch_update(L, cfg.inner, xlo, r, p, q, rd, cs, xmode_of(c, steps, xdefer));
                 }
                 DP_HIP(hipStreamEndCapture(L.stream, &graph));
                 const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -649,7 +664,7 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
         } else {
             for (int c = 0; c < steps; ++c) {
                 DP_TRY(timed_stencil(ctx, cfg, L, a));
-                launch_update(L, cfg.inner, xlo, r, p, q, rd, cs);
+                launch_update(L, cfg.inner, xlo, r, p, q, rd, cs, xmode_of(c, steps, xdefer));
             }
         }
         DP_HIP(hipGetLastError());
