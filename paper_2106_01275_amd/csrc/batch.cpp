@@ -130,7 +130,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
 
     // CG state of all slots in one block (one stride per slot), mirrored in
     // pinned host memory for the read-back of finished slots
-    const size_t st_doubles = 9 * kMaxW + 8, st_ints = 3 * kMaxW + 8;
+    const size_t st_doubles = kStateDoubles, st_ints = 3 * kMaxW + 8;
     const size_t st_stride = (st_doubles * sizeof(double) + st_ints * sizeof(int) + 255) / 256 * 256;
     char *st_all = nullptr;
     DP_TRY(mem.alloc(ctx, (void **)&st_all, st_stride * nslots));
@@ -192,7 +192,8 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
         cs.beta = st + 5 * kMaxW;
         cs.true_rr = st + 6 * kMaxW;
         cs.tj = st + 7 * kMaxW;
-        int *iv = (int *)(st + 9 * kMaxW + 8);
+        cs.xdef = mixed ? st + 9 * kMaxW : nullptr;
+        int *iv = (int *)(st + st_doubles);
         cs.active = iv;
         cs.iters = iv + kMaxW;
         cs.flags = iv + 2 * kMaxW;
@@ -401,6 +402,9 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
     DP_TRY(init_slots());
 
     int steps_next = std::max(1, ctx->check_every);
+    // mixed precision: the x updates of an iteration group in pairs (as in
+    // the single-instance solve)
+    const bool xdefer = mixed && xdefer_enabled();
     std::vector<double> ratio_prev(nslots, -1.0);
     std::vector<int> it_prev(nslots, 0);
     ctx->drop_graphs();
@@ -413,13 +417,13 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             if (hsd[k].flags & kSlotIter) steps = std::min(steps, std::max(1, cfg.max_iter - slot_it[k]));
         if (cfg.use_graph && !cfg.profile) {
             // B is fixed for the call, and the graphs are dropped before and after it
-            const std::string key = "batch " + std::to_string(steps);
+            const std::string key = "batch " + std::to_string(steps) + (xdefer ? " xdefer" : "");
             auto g = ctx->graphs.find(key);
             if (g == ctx->graphs.end()) {
                 hipGraph_t graph = nullptr;
                 hipGraphExec_t exec = nullptr;
                 DP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                for (int c = 0; c < steps; ++c) launch_b_iteration(B);
+                for (int c = 0; c < steps; ++c) launch_b_iteration(B, xmode_of(c, steps, xdefer));
                 DP_HIP(hipStreamEndCapture(s, &graph));
                 const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
@@ -434,7 +438,7 @@ dp_status run_batch(dp_ctx *ctx, std::vector<BatchInst> &in, const SolveCfg &cfg
             for (int c = 0; c < steps; ++c) {
                 DP_TRY(timed_launch(ctx, cfg.profile != 0, bytes,
                                     [&](hipEvent_t e0, hipEvent_t e1) { launch_b_stencil(B, e0, e1); }));
-                launch_b_update(B);
+                launch_b_update(B, xmode_of(c, steps, xdefer));
             }
         }
         DP_HIP(hipGetLastError());

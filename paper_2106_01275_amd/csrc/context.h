@@ -122,6 +122,9 @@ dp_status noalloc_attach(int device, std::string &err);
 // largest number the stencil tuner may pick (partial-sum buffers are sized
 // for it)
 int launch_blocks(const Lat &lat, int W);
+// update mode (launch_update's xmode) of iteration c of a group of n
+int xmode_of(int c, int n, bool defer);
+bool xdefer_enabled();
 int max_launch_blocks(const Lat &lat, int W);
 // bytes of workspace slot `slot` that prepare_operator and make_launch need
 // for this operator, inner precision and width (0: the slot is not used)

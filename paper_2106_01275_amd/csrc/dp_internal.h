@@ -138,10 +138,11 @@ struct BatchLaunch {
     hipStream_t stream;
 };
 void launch_b_init(const BatchLaunch &B, int mixed);
-void launch_b_iteration(const BatchLaunch &B);
+// xmode: as launch_update's (the slots of mixed precision have cs.xdef)
+void launch_b_iteration(const BatchLaunch &B, int xmode = 0);
 // the stencil with its three dot products (ev0/ev1: its own start and stop)
 void launch_b_stencil(const BatchLaunch &B, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_b_update(const BatchLaunch &B);  // the finishing kernel, then the vector update
+void launch_b_update(const BatchLaunch &B, int xmode = 0);  // the finishing kernel, then the vector update
 // iterating slots: |r|^2 partials rebuilt from cs.rr (after a new sharing of the workgroups)
 void launch_b_reseed(const BatchLaunch &B);
 void launch_b_ru(const BatchLaunch &B, int final_stats);
@@ -192,9 +193,10 @@ void launch_stencil(const Launch &L, int prec, const StencilArgs &a);
 bool stencil_mode_valid(const Launch &L, int prec, int mode);
 int stencil_mode_rule(const Launch &L, int prec);
 // The vector update of a CG iteration: x += alpha p, r -= alpha q,
-// p = r + beta p, and |r|^2 per lane into rd.part2.  xmode (FP32 storage
-// with cs.xdef set, else taken as 0): 1 defers this iteration's x update to
-// the next update, which must be launched with xmode 2; 0 the plain update.
+// p = r + beta p, and |r|^2 per lane into rd.part2.  xmode (FP32 or BF16
+// storage with cs.xdef set, else taken as 0): 1 defers this iteration's x
+// update to the next update, which must be launched with xmode 2; 0 the
+// plain update.
 void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const void *q, const Red &rd,
                    const CgState &cs, int xmode = 0);
 // x64 += xlo, xlo = 0 (mixed precision)

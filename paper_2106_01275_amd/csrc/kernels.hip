@@ -1443,9 +1443,15 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
 // divides by beta_k; its rounding error relative to alpha_k p_k is about
 // eps / sqrt(beta_k) (|r_{k+1}| = sqrt(beta_k) |r_k| <= sqrt(beta_k) |p_k|),
 // so a lane whose beta_k is below kDeferBetaMin (a restart has beta = 0)
-// updates its x at once instead.  XM = 0 is the plain update.  An XM = 1
-// update is always followed by an XM = 2 one before anything reads x.
-constexpr double kDeferBetaMin = 1.0 / 64;
+// updates its x at once instead.  With BF16 storage the rounding of the
+// stored p_{k+1} (2^-9 of it) enters the same way, about 2^-9 (1 + 1 /
+// sqrt(beta_k)) of the step, against 2^-9 of the whole accumulated x that
+// every BF16 write of x costs (and the pairs halve those writes); there the
+// floor is 1/16 (at most 5 x 2^-9 of a step).  XM = 0 is the plain update.
+// An XM = 1 update is always followed by an XM = 2 one before anything
+// reads x.
+template <typename S>
+constexpr double kDeferBetaMin = std::is_same<S, bf16x2>::value ? 1.0 / 16 : 1.0 / 64;
 
 template <typename S, int XM>
 __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__restrict__ x, S *__restrict__ r,
@@ -1461,7 +1467,7 @@ __device__ __forceinline__ void k_update_body(const Blk &bk, Launch L, S *__rest
     const bool keep = (ldg(cs.flags + j) & kFlagHold) || !ldg(cs.active + j);
     // XM = 1: does this lane defer its x update (else it updates x now)?
     // XM = 2: the deferred coefficient alpha_k / beta_k (0: nothing deferred)
-    const bool dfr = XM == 1 && !keep && beta64 >= kDeferBetaMin;
+    const bool dfr = XM == 1 && !keep && beta64 >= kDeferBetaMin<S>;
     const bool xio = XM != 1 || (!keep && !dfr);
     const R cdef = XM == 2 ? (R)ldg(cs.xdef + j) : (R)0;
     if (XM == 1 && bk.b == 0 && tid < W) cs.xdef[j] = dfr ? ldg(cs.alpha + j) / beta64 : 0.0;
@@ -2026,14 +2032,14 @@ __global__ __launch_bounds__(kBlock) void k_b_stencil(BatchLaunch B) {
                                            d->nbr, 1, d->rd);
 }
 
-template <typename S>
+template <typename S, int XM>
 __global__ __launch_bounds__(kBlock) void k_b_update(BatchLaunch B) {
     Blk bk;
     const SlotDesc *d = slot_of_block(B, bk, kSlotIter);
     if (!d) return;
     // FP64: the iterate is x64 itself (xlo aliases it)
-    k_update_body<S, 0>(bk, d->L, (S *)d->xlo, (S *)d->r, (S *)d->p, (const S *)d->q,
-                     d->rd, d->cs);
+    k_update_body<S, XM>(bk, d->L, (S *)d->xlo, (S *)d->r, (S *)d->p, (const S *)d->q,
+                         d->rd, d->cs);
 }
 
 template <typename S>
@@ -2432,17 +2438,15 @@ void launch_stencil(const Launch &L, int prec, const StencilArgs &a) {
 
 void launch_update(const Launch &L, int prec, void *x, void *r, void *p, const void *q, const Red &rd,
                    const CgState &cs, int xmode) {
-    if (xmode != 0 && (prec != kF32 || !cs.xdef)) xmode = 0;  // deferral: FP32 storage only
-    if (xmode == 1)
-        k_update<float2, 1><<<L.nblk, kBlock, 0, L.stream>>>(L, (float2 *)x, (float2 *)r, (float2 *)p,
-                                                              (const float2 *)q, rd, cs);
-    else if (xmode == 2)
-        k_update<float2, 2><<<L.nblk, kBlock, 0, L.stream>>>(L, (float2 *)x, (float2 *)r, (float2 *)p,
-                                                              (const float2 *)q, rd, cs);
-    else
-        DP_DISPATCH_PREC(prec, S,
-                         k_update<S, 0><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)x, (S *)r, (S *)p, (const S *)q, rd,
-                                                                         cs));
+    if (prec == kF64 || !cs.xdef) xmode = 0;  // deferral: FP32 and BF16 storage
+    DP_DISPATCH_PREC(prec, S, {
+        if (xmode == 1)
+            k_update<S, 1><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)x, (S *)r, (S *)p, (const S *)q, rd, cs);
+        else if (xmode == 2)
+            k_update<S, 2><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)x, (S *)r, (S *)p, (const S *)q, rd, cs);
+        else
+            k_update<S, 0><<<L.nblk, kBlock, 0, L.stream>>>(L, (S *)x, (S *)r, (S *)p, (const S *)q, rd, cs);
+    });
 }
 
 void launch_fold(const Launch &L, int prec, double *x64, void *xlo) {
@@ -2662,16 +2666,24 @@ void launch_b_stencil(const BatchLaunch &B, hipEvent_t ev0, hipEvent_t ev1) {
     DP_DISPATCH_PREC(B.prec, S, b_stencil<S>(B, ev0, ev1));
 }
 
-void launch_b_update(const BatchLaunch &B) {
+void launch_b_update(const BatchLaunch &B, int xmode) {
     k_b_finish_cg<<<B.nslots * B.W, kBlock, 0, B.stream>>>(B);
-    DP_DISPATCH_PREC(B.prec, S, k_b_update<S><<<B.nblocks, kBlock, 0, B.stream>>>(B));
+    if (B.prec == kF64) xmode = 0;  // the slots' state of mixed precision has xdef
+    DP_DISPATCH_PREC(B.prec, S, {
+        if (xmode == 1)
+            k_b_update<S, 1><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+        else if (xmode == 2)
+            k_b_update<S, 2><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+        else
+            k_b_update<S, 0><<<B.nblocks, kBlock, 0, B.stream>>>(B);
+    });
 }
 
 void launch_b_reseed(const BatchLaunch &B) { k_b_reseed<<<B.nslots * B.W, kBlock, 0, B.stream>>>(B); }
 
-void launch_b_iteration(const BatchLaunch &B) {
+void launch_b_iteration(const BatchLaunch &B, int xmode) {
     launch_b_stencil(B);
-    launch_b_update(B);
+    launch_b_update(B, xmode);
 }
 
 template <typename S, int NC, bool LINKS>

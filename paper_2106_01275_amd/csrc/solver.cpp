@@ -422,7 +422,7 @@ dp_status make_launch(dp_ctx *ctx, const OpPrep &op, int W, hipStream_t s, Launc
     cs.beta = d + 5 * kMaxW;
     cs.true_rr = d + 6 * kMaxW;
     cs.tj = d + 7 * kMaxW;
-    cs.xdef = cfg.inner == kF32 ? d + 9 * kMaxW : nullptr;
+    cs.xdef = cfg.inner != kF64 ? d + 9 * kMaxW : nullptr;
     // the control word lives in pinned host memory: k_ctrl writes it there
     // and the host reads it after the synchronisation, no copy
     cs.ctrld = (double *)(ctx->ctrl_dev + 4);
@@ -463,10 +463,16 @@ int next_check(int dflt, double ratio, double ratio_prev, int dit, double ru_rat
 // and a completing x update, and a plain last one when n is odd, so that x
 // is whole at the end of every group (where a reliable update or the caller
 // may read it).
-static int xmode_of(int c, int n, bool defer) {
+int xmode_of(int c, int n, bool defer) {
     if (!defer) return 0;
     if (c & 1) return 2;
     return c + 1 < n ? 1 : 0;
+}
+
+// DP_XDEFER=0 takes every x update at once (for comparison)
+bool xdefer_enabled() {
+    const char *e = std::getenv("DP_XDEFER");
+    return !(e && std::strcmp(e, "0") == 0);
 }
 
 double stencil_alg_bytes(const Lat &lat, int nc, int W, int prec, bool links) {
@@ -629,10 +635,9 @@ dp_status solve_block(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, const 
     // Iterations between host checks: start with check_every, then predict
     // from the decay of the slowest lane's residual since the last check.
     int steps_next = std::max(1, ctx->check_every);
-    // FP32 storage takes the x updates of an iteration group in pairs (the
-    // update kernel's deferred mode); DP_XDEFER=0 takes every one at once
-    const char *xd_env = std::getenv("DP_XDEFER");
-    const bool xdefer = cs.xdef != nullptr && !(xd_env && std::strcmp(xd_env, "0") == 0);
+    // mixed precision takes the x updates of an iteration group in pairs
+    // (the update kernel's deferred mode)
+    const bool xdefer = cs.xdef != nullptr && xdefer_enabled();
     double ratio_prev = -1.0;
     int it_prev = 0, it_ru = 0;
     while (nactive > 0 && it < cfg.max_iter) {

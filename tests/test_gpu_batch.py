@@ -68,6 +68,27 @@ def test_batched_trace_matches_oracle(ctx, inner, block, tol, rtol):
         assert res[i]["solve"]["max_true_resid"] <= tol * (1 if inner != "f64" else 10)
 
 
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_batched_deferred_x_update(ctx, monkeypatch, inner):
+    """The multi-instance engine takes the x updates of an iteration group in
+    pairs as the single solve does; with DP_XDEFER=0 it writes x at every
+    update.  Both match the oracle, with about as many iterations."""
+    _say("batched deferred x", inner)
+    ops, pss, ps_, Us, cols = _instances(ctx, SMALL)
+    iters = {}
+    for xd in ("1", "0"):
+        monkeypatch.setenv("DP_XDEFER", xd)
+        res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-10, inner=inner, rhs_block=32,
+                                                         reliable_delta=1e-2))
+        for i, (dims, m2, eps, p, k, seed) in enumerate(SMALL):
+            col, n, _ = cols[i]
+            o = oracle.trace(dims, 3, m2, Us[i], p, col, n, i, 0, 1, oracle.Z2_COMPLEX, True, tol=1e-13)
+            assert np.abs(res[i]["tj"] - o["tj"]).max() < 1e-6 * np.abs(o["tj"]).max(), (xd, i)
+            assert res[i]["solve"]["max_true_resid"] <= 1e-10
+        iters[xd] = sum(r["solve"]["rhs_iters"] for r in res)
+    assert abs(iters["1"] - iters["0"]) <= 0.05 * iters["0"] + 4, iters
+
+
 def test_batched_equals_single_instance(ctx):
     """The batch engine and the single-instance path run the same kernels on
     the same data: FP64 contractions agree to rounding."""

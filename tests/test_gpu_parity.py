@@ -135,15 +135,15 @@ def test_solve_batch_mixed_matches_oracle(ctx, inner, block):
     assert err < 1e-8, err
 
 
-@pytest.mark.parametrize("graph", [0, 1])
-def test_deferred_x_update_matches_oracle(ctx, monkeypatch, graph):
-    """FP32 storage takes the x updates of an iteration group in pairs (the
+@pytest.mark.parametrize("inner,graph", [("f32", 0), ("f32", 1), ("bf16", 0)])
+def test_deferred_x_update_matches_oracle(ctx, monkeypatch, inner, graph):
+    """Mixed precision takes the x updates of an iteration group in pairs (the
     first of a pair leaves x alone, the second recovers the skipped direction
     from p and r); DP_XDEFER=0 writes x at every update.  Both must reach the
     oracle's solution, take about as many iterations, and a lane whose beta
     is tiny (an eigenvector of the free field converges in one step) must
     update its x at once.  Eager launches and graph replay."""
-    _say("deferred x update, graph", graph)
+    _say("deferred x update", inner, "graph", graph)
     dims, nc, nrhs = (8, 6, 4, 4), 3, 40
     N = int(np.prod(dims))
     rng = np.random.default_rng(31)
@@ -155,7 +155,7 @@ def test_deferred_x_update_matches_oracle(ctx, monkeypatch, graph):
     for xd in ("1", "0"):
         monkeypatch.setenv("DP_XDEFER", xd)
         (X,), (st,) = ctx.solve_batch([op], [cuda(B)],
-                                      ctx.opts(tol=1e-10, inner="f32", rhs_block=32, use_graph=graph))
+                                      ctx.opts(tol=1e-10, inner=inner, rhs_block=32, use_graph=graph))
         X = X.cpu().numpy()
         assert st["nconverged"] == nrhs and st["max_true_resid"] <= 1e-10, (xd, st)
         err = np.abs(X - Xo).max() / np.abs(Xo).max()
