@@ -146,12 +146,14 @@ def cg_bandwidth(site_iters, elapsed, inner, W, nc=3):
     """Whole-CG bandwidth.  site_iters = sum over right-hand sides of CG
     iterations x sites.  Algorithmic bytes per RHS*site*iteration: 6V + 4L/W.
     This schedule: the stencil reads p (and, BF16, r) and writes q; the
-    update reads x, r, p, q and writes x, r, p; the eight hop links of a site
-    are read once per W lanes: 9V (BF16 10V) + 8L/W."""
+    update reads r, p, q and writes r, p, and with FP64 storage reads and
+    writes x too (mixed precision: every other iteration); the eight hop
+    links of a site are read once per W lanes: FP64 9V, FP32 8V, BF16 9V,
+    each + 8L/W."""
     c = CB[inner]
     V, L = nc * c, nc * nc * c
     alg = 6 * V + 4 * L / W
-    sched = (10 if inner == "bf16" else 9) * V + 8 * L / W
+    sched = {"f64": 9, "f32": 8, "bf16": 9}[inner] * V + 8 * L / W
     a = site_iters * alg / elapsed / 1e9
     return {"alg_bytes_per_rhs_site_iter": alg, "alg_bytes": site_iters * alg, "achieved": a, "unit": "GB/s",
             "frac": a / HBM_PEAK_GBS, "schedule_bytes_per_rhs_site_iter": sched,
