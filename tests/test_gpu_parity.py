@@ -165,6 +165,34 @@ def test_deferred_x_update_matches_oracle(ctx, monkeypatch, inner, graph):
     assert abs(iters["1"] - iters["0"]) <= 0.05 * iters["0"] + 2, iters
 
 
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_deferred_x_update_every_stop(ctx, monkeypatch, inner):
+    """Stopped after exactly k iterations (max_iter = k, k = 1..7: groups
+    that end after an odd or an even number of updates), the iterate is the
+    same with the x updates paired as with one x update per iteration, to
+    the storage precision: no deferred step is lost or counted twice at a
+    group's end."""
+    _say("deferred x update at every stop", inner)
+    dims, nc, nrhs = (6, 4, 5, 4), 3, 32
+    N = int(np.prod(dims))
+    rng = np.random.default_rng(41)
+    U = workloads.random_links(dims, 0.4, 6, nc)
+    B = rng.standard_normal((nrhs, N, nc)) + 1j * rng.standard_normal((nrhs, N, nc))
+    op = ctx.operator(dims, nc, 0.1, cuda(U))
+    rtol = 1e-5 if inner == "f32" else 5e-2
+    for k in range(1, 8):
+        xs = {}
+        for xd in ("1", "0"):
+            monkeypatch.setenv("DP_XDEFER", xd)
+            (X,), (st,) = ctx.solve_batch([op], [cuda(B)],
+                                          ctx.opts(tol=1e-14, max_iter=k, inner=inner, rhs_block=32), check=False)
+            # (a BF16 lane that holds for its reliable update counts no iteration)
+            assert st["max_iters"] == k if inner == "f32" else 0 < st["max_iters"] <= k, (k, xd, st)
+            xs[xd] = X.cpu().numpy()
+        err = np.abs(xs["1"] - xs["0"]).max() / np.abs(xs["0"]).max()
+        assert err < rtol, (k, err)
+
+
 def test_solve_empty_and_zero_rhs(ctx):
     dims, nc = (4, 4, 4, 4), 3
     op = ctx.operator(dims, nc, 0.5, None)
