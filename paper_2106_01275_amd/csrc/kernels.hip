@@ -1434,7 +1434,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Launch L, typename St<S>::R 
 // finishing kernel adds the partials up).  A held or stopped lane keeps its
 // direction (alpha = 0: x and r are unchanged too).
 // The solution's update x += alpha p can be taken two iterations at a time
-// (XM, FP32 storage): an update with XM = 1 leaves x as it is and records
+// (XM; FP32 or BF16 storage): an update with XM = 1 leaves x and records
 // c = alpha_k / beta_k per lane; the next one (XM = 2) recovers the direction
 // p_k it skipped from the two vectors it reads anyway, p_k = (p_{k+1} -
 // r_{k+1}) / beta_k (the relation by which the skipped update formed p_{k+1}),
