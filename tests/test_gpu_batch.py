@@ -135,7 +135,10 @@ def test_uneven_batch_workload_64(ctx):
     """The 64-instance uneven batch (extents from {4,6,8,10,12}^4, BF16
     storage, FP64 refinement, distance-4 colourings): every instance
     converges to tol 1e-8 in FP64 true residual; three sampled instances are
-    recomputed by the oracle."""
+    recomputed by the oracle: the three smallest, the median, the largest
+    and three drawn at random (seeded), each instance's T to 1e-5 and its
+    per-probe contractions to 1e-5 of the largest (the measured errors are
+    printed)."""
     _say("uneven batch 64")
     batch = workloads.uneven_batch()
     ops, pss, ps_, Us, cols = [], [], [], [], []
@@ -148,16 +151,23 @@ def test_uneven_batch_workload_64(ctx):
         ps_.append(w.p)
         Us.append(U)
         cols.append((col, n))
-    # the benchmark's configuration: W = 32 (414 jobs over 256 slots), the library's BF16 delta
-    res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-8, inner="bf16", rhs_block=32))
+    # the benchmark's configuration: W = 32, reliable-update drop 0.005
+    res = ctx.trace_estimate(ops, pss, ps_, ctx.opts(tol=1e-8, inner="bf16", rhs_block=32, reliable_delta=0.005))
     for r in res:
         assert r["solve"]["nconverged"] == r["solve"]["nrhs"] and r["solve"]["max_true_resid"] <= 1e-8
-    order = np.argsort([w.volume for w in batch])
-    for i in (order[0], order[len(order) // 2], order[-1]):
+    order = [int(v) for v in np.argsort([w.volume for w in batch])]
+    picks = order[:3] + [order[len(order) // 2], order[-1]]
+    rest = [i for i in range(len(batch)) if i not in picks]
+    picks += [int(v) for v in np.random.default_rng(64).choice(rest, 3, replace=False)]
+    for i in picks:
         w = batch[i]
         col, n = cols[i]
         o = oracle.trace(w.dims, 3, w.m2, Us[i], w.p, col, n, i, 0, 1, oracle.Z2_COMPLEX, True, tol=1e-11)
-        assert abs(res[i]["T"] - o["T"]) < 1e-5 * abs(o["T"]), (i, res[i]["T"], o["T"])
+        eT = abs(res[i]["T"] - o["T"]) / abs(o["T"])
+        etj = np.abs(res[i]["tj"] - o["tj"]).max() / np.abs(o["tj"]).max()
+        _say("instance", i, w.dims, "T rel err", f"{eT:.2e}", "tj err / max|tj|", f"{etj:.2e}")
+        assert eT < 1e-5, (i, res[i]["T"], o["T"])
+        assert etj < 1e-5, (i, etj)
 
 
 def test_autotuned_batch_width(ctx):

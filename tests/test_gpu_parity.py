@@ -135,7 +135,7 @@ def test_solve_batch_mixed_matches_oracle(ctx, inner, block):
     assert err < 1e-8, err
 
 
-@pytest.mark.parametrize("inner,graph", [("f32", 0), ("f32", 1), ("bf16", 0)])
+@pytest.mark.parametrize("inner,graph", [("f32", 0), ("f32", 1), ("bf16", 0), ("bf16", 1)])
 def test_deferred_x_update_matches_oracle(ctx, monkeypatch, inner, graph):
     """Mixed precision takes the x updates of an iteration group in pairs (the
     first of a pair leaves x alone, the second recovers the skipped direction
