@@ -598,8 +598,10 @@ static void true_residual(dp_ctx *ctx, const OpPrep &op, const SolveCfg &cfg, co
     a.U = op.U8x;
     a.nbr = op.nbr;
     a.cg = 0;
-    // the built-in choice (16^4, W = 32: FP64 quads 101 us, the LDS tile
-    // 106 us, although the quads hold 177 registers: two waves per SIMD)
+    // the built-in choice, the fastest measured: 16^4, W = 32: FP64 quads
+    // 100 us (although they hold 177 registers: two waves per SIMD), the LDS
+    // tile 105, x0 pairs 108, per-lane links 157; 32^4: x0 lines 1504 us,
+    // pairs 1672, the LDS tile 1756, per-lane links 2417
     Launch L64 = L;
     L64.smode = -1;
     launch_stencil(L64, kF64, a);
