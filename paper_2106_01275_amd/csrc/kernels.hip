@@ -379,6 +379,25 @@ __device__ __forceinline__ void lane_total(const double *src, int nblk, double (
     }
 }
 
+// The same total by one wavefront alone (any wavefront of the workgroup;
+// no LDS, no barrier): thread t adds partials t, t + 64, ..., then a
+// butterfly; the totals are valid in every thread of the wavefront.  For the
+// slots of the multi-instance engine, whose lanes have a few dozen partials
+// each.
+template <int NV>
+__device__ __forceinline__ void lane_total_wave(const double *src, int nblk, double (&tot)[NV]) {
+    const int t = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) tot[v] = 0.0;
+    for (int b = t; b < nblk; b += 64) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tot[v] += src[(size_t)b * NV + v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int off = 32; off > 0; off >>= 1) tot[v] += __shfl_xor(tot[v], off, 64);
+}
+
 // Epilogues of the finishing kernels.  Those marked (part2, NV = 2) total
 // the |r|^2 and Re q^H p partials of the last vector update, initialisation
 // or reliable update; kEpiTj and kEpiStatsP1 total rd.part1.
@@ -483,23 +502,54 @@ __global__ __launch_bounds__(kBlock) void k_finish(Red rd, CgState cs) {
 // the lane (breakdown); mixed precision flags it to restart its direction
 // at the next reliable update (FP32 takes a steepest-descent step
 // meanwhile, BF16 holds).
+// The lane's state as the finishing kernel reads it (loaded before the
+// partials, so that the two latencies overlap).
+struct LaneState {
+    double ref = 0.0, bb = 0.0, beta = 0.0;
+    int active = 0, flags = 0, iters = 0;
+};
+
+__device__ __forceinline__ LaneState load_lane_state(int j, const CgState &cs) {
+    LaneState st;
+    st.ref = cs.rr_ref[j];
+    st.bb = cs.bb[j];
+    st.beta = cs.beta[j];
+    st.active = cs.active[j];
+    st.flags = cs.flags[j];
+    st.iters = cs.iters[j];
+    return st;
+}
+
+__device__ __forceinline__ void finish_cg_epilogue(int j, const CgState &cs, const LaneState &ls, const double (&d3)[4],
+                                                   const double (&d2)[2]);
+
 __device__ __forceinline__ void k_finish_cg_body(int lane, const Red &rd, const CgState &cs) {
     __shared__ double sm[6 * kBlock / 64];
-    const int tid = threadIdx.x, j = lane;
-    double st_ref = 0.0, st_bb = 0.0, st_beta = 0.0;
-    int st_active = 0, st_flags = 0, st_iters = 0;
-    if (tid == 0) {
-        st_ref = cs.rr_ref[j];
-        st_bb = cs.bb[j];
-        st_beta = cs.beta[j];
-        st_active = cs.active[j];
-        st_flags = cs.flags[j];
-        st_iters = cs.iters[j];
-    }
+    const int tid = threadIdx.x;
+    LaneState ls;
+    if (tid == 0) ls = load_lane_state(lane, cs);
     double d3[4], d2[2];
     lane_total<4>(rd.part1 + (size_t)lane * rd.nblk * 4, rd.nblk, d3, sm);
     lane_total<2>(rd.part2 + (size_t)lane * rd.nblk * 2, rd.nblk, d2, sm + 4 * kBlock / 64);
-    if (tid != 0) return;
+    if (tid == 0) finish_cg_epilogue(lane, cs, ls, d3, d2);
+}
+
+// The same with one wavefront per lane (the multi-instance engine: a few
+// dozen partials per lane).
+__device__ __forceinline__ void k_finish_cg_wave_body(int lane, const Red &rd, const CgState &cs) {
+    LaneState ls;
+    if ((threadIdx.x & 63) == 0) ls = load_lane_state(lane, cs);
+    double d3[4], d2[2];
+    lane_total_wave<4>(rd.part1 + (size_t)lane * rd.nblk * 4, rd.nblk, d3);
+    lane_total_wave<2>(rd.part2 + (size_t)lane * rd.nblk * 2, rd.nblk, d2);
+    if ((threadIdx.x & 63) == 0) finish_cg_epilogue(lane, cs, ls, d3, d2);
+}
+
+// alpha, beta, flags and counts of lane j from its totals (thread-local)
+__device__ __forceinline__ void finish_cg_epilogue(int j, const CgState &cs, const LaneState &ls, const double (&d3)[4],
+                                                   const double (&d2)[2]) {
+    const double st_ref = ls.ref, st_bb = ls.bb, st_beta = ls.beta;
+    const int st_active = ls.active, st_flags = ls.flags, st_iters = ls.iters;
     const double rr = d2[0], pq = d3[0], qq = d3[2];
     // r^H q: since the residual is r = p - beta p_prev (beta the one that
     // formed p), r^H q = p^H q - beta p_prev^H A p, and p_prev^H A p =
@@ -2094,11 +2144,16 @@ __global__ __launch_bounds__(kBlock) void k_b_reseed(BatchLaunch B) {
     }
 }
 
+// One wavefront per (slot, lane): wavefront g = blockIdx.x * 4 + wave takes
+// slot g / W, lane g % W (a slot's few dozen partials per lane need no
+// more; with a workgroup per lane the launch was mostly idle threads).
 __global__ __launch_bounds__(kBlock) void k_b_finish_cg(BatchLaunch B) {
-    const int s = blockIdx.x / B.W, lane = blockIdx.x % B.W;
+    const int g = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int s = g / B.W, lane = g % B.W;
+    if (s >= B.nslots) return;
     const SlotDesc *d = B.sd + s;
     if (!(d->flags & kSlotIter) || lane >= d->L.W || (d->cs.live && ldg(d->cs.live) == 0)) return;
-    k_finish_cg_body(lane, d->rd, d->cs);
+    k_finish_cg_wave_body(lane, d->rd, d->cs);
 }
 
 __global__ void k_b_ctrl(BatchLaunch B) {
@@ -2667,7 +2722,7 @@ void launch_b_stencil(const BatchLaunch &B, hipEvent_t ev0, hipEvent_t ev1) {
 }
 
 void launch_b_update(const BatchLaunch &B, int xmode) {
-    k_b_finish_cg<<<B.nslots * B.W, kBlock, 0, B.stream>>>(B);
+    k_b_finish_cg<<<(B.nslots * B.W + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, B.stream>>>(B);
     if (B.prec == kF64) xmode = 0;  // the slots' state of mixed precision has xdef
     DP_DISPATCH_PREC(B.prec, S, {
         if (xmode == 1)
