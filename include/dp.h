@@ -194,7 +194,7 @@ typedef struct {
     double reliable_delta;  /* mixed precision: replace the residual by the FP64
                                true residual once it dropped by this factor; a lane
                                that reaches it waits for that update before it moves
-                               on (0: 0.05 for BF16, 1e-3 for F32).  BF16 storage
+                               on (0: 0.002 for BF16, 1e-3 for F32).  BF16 storage
                                resolves about 3 digits: smaller values cost extra
                                iterations, larger ones extra FP64 updates */
     int32_t use_graph;      /* 1: replay the iteration loop from a captured hipGraph */

@@ -41,12 +41,10 @@ dp_status solve_cfg(dp_ctx *ctx, const dp_solve_opts *o, SolveCfg &c) {
     c.tol = o->tol;
     c.max_iter = o->max_iter > 0 ? o->max_iter : 100000;
     c.inner = o->inner;
-    // default residual drop between reliable updates: about what the storage
-    // precision resolves (BF16 keeps ~3 digits, FP32 ~7)
-    c.delta = o->reliable_delta > 0 ? o->reliable_delta : (c.inner == kBF16 ? 0.05 : 1e-3);
+    c.delta = o->reliable_delta > 0 ? o->reliable_delta : default_reliable_delta(c.inner);
     c.profile = o->profile;
     c.use_graph = o->use_graph;
-    c.ru_gap = c.inner == kBF16 ? 24 : 100;
+    c.ru_gap = default_ru_gap(c.inner);
     if (!(c.tol > 0) || !(c.delta < 1)) {
         ctx->err = "tol must be > 0 and reliable_delta < 1";
         return DP_EINVAL;

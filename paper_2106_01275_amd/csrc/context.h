@@ -125,6 +125,11 @@ int launch_blocks(const Lat &lat, int W);
 // update mode (launch_update's xmode) of iteration c of a group of n
 int xmode_of(int c, int n, bool defer);
 bool xdefer_enabled();
+// The solve options' defaults shared by every entry point: the residual drop
+// between reliable updates (reliable_delta = 0) and the longest run of
+// iterations without one.
+double default_reliable_delta(int inner);
+int default_ru_gap(int inner);
 int max_launch_blocks(const Lat &lat, int W);
 // bytes of workspace slot `slot` that prepare_operator and make_launch need
 // for this operator, inner precision and width (0: the slot is not used)

@@ -122,8 +122,8 @@ extern "C" dp_status dp_solve_noalloc(dp_ctx *ctx, const dp_operator *op, const 
     cfg.tol = o->tol;
     cfg.max_iter = o->max_iter > 0 ? o->max_iter : 100000;
     cfg.inner = o->inner;
-    cfg.delta = o->reliable_delta > 0 ? o->reliable_delta : (cfg.inner == kBF16 ? 0.05 : 1e-3);
-    cfg.ru_gap = cfg.inner == kBF16 ? 24 : 100;
+    cfg.delta = o->reliable_delta > 0 ? o->reliable_delta : default_reliable_delta(cfg.inner);
+    cfg.ru_gap = default_ru_gap(cfg.inner);
     if (!(cfg.tol > 0) || !(cfg.delta < 1) || (cfg.inner != kF64 && cfg.inner != kF32 && cfg.inner != kBF16)) {
         ctx->err = "solve_noalloc: tol must be > 0, reliable_delta < 1, inner a DP_PREC_* value";
         return DP_EINVAL;

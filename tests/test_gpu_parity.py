@@ -304,7 +304,7 @@ def test_trace_gauge_8(ctx, inner, block):
 
 
 def test_bf16_iterations_near_fp64(ctx):
-    """BF16 storage with the default reliable-update drop (0.05) and held lanes
+    """BF16 storage with the default reliable-update drop (0.002) and held lanes
     converges in about as many iterations as FP64 CG on the same probes (a
     lane never iterates past what BF16 resolves)."""
     _say("bf16 iteration count vs fp64")
